@@ -1,0 +1,184 @@
+/*
+ * rpca.h -- C ABI of an MI355X (gfx950) implementation of the randomized
+ * principal component analysis of Szlam, Kluger and Tygert, "An
+ * implementation of a randomized algorithm for principal component analysis"
+ * (ACM TOMS 2014, arXiv:1412.3510).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix pointers (A, U, V, S, lambda, workspace-free outputs) are
+ *    DEVICE pointers owned by the caller.  The library never frees them.
+ *    Host pointers appear only where a name says so (``*_host``).
+ *  - Dense matrices are row-major with an explicit leading dimension (in
+ *    elements).  A leading dimension that is a multiple of 4 and a 16-byte
+ *    aligned base give the vectorized load path; other layouts are accepted
+ *    and take a scalar path.
+ *  - Every call is ordered on the context's HIP stream and returns before the
+ *    device has finished, unless RPCA_SYNC is passed (or the call returns a
+ *    host value, which implies a synchronization).
+ *  - On error nothing is launched (argument errors) or the outputs are left
+ *    unspecified (device-side failures); the status says which, and
+ *    rpca_last_error() gives a message.
+ *  - l <= 0 means l = k + 2 (the paper's default oversampling, Section 7).
+ *    Supported range: 1 <= k <= l <= min(m, n) and l <= 128.
+ *  - A context is not thread-safe; calls that overlap on one context race.
+ */
+#ifndef RPCA_H
+#define RPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpca_ctx_s* rpca_ctx;
+
+typedef enum {
+  RPCA_OK = 0,
+  RPCA_ERR_INVALID_ARG = 1, /* bad sizes, null pointers, k > l, ...        */
+  RPCA_ERR_UNSUPPORTED = 2, /* a format/dtype/size this build does not do   */
+  RPCA_ERR_NO_MEMORY = 3,   /* workspace allocation failed or over the limit */
+  RPCA_ERR_HIP = 4,         /* a HIP runtime call failed                     */
+  RPCA_ERR_NOT_PSD = 5,     /* Nystrom: shifted B2 never positive definite   */
+  RPCA_ERR_NUMERICAL = 6    /* non-finite values met on the device           */
+} rpca_status;
+
+typedef enum { RPCA_F32 = 0, RPCA_BF16 = 1, RPCA_FP8_E4M3 = 2 } rpca_dtype;
+typedef enum { RPCA_DENSE_ROWMAJOR = 0, RPCA_SPARSE_CSR = 1 } rpca_format;
+
+/* A matrix operand.  For RPCA_DENSE_ROWMAJOR, ``data`` holds m rows of n
+ * elements of ``dtype`` with leading dimension ``ld``.  ``col_scale`` (FP8
+ * only, length n) gives the per-column scale: A = data * diag(col_scale).
+ * ``data_f32``/``ld_f32`` optionally give the float32 matrix used for the
+ * final Rayleigh-Ritz product when ``dtype`` is a reduced precision (the
+ * precision form); NULL means the reduced-precision data is used there too.
+ * The sparse fields are reserved for the CSR format. */
+typedef struct {
+  int32_t format; /* rpca_format */
+  int32_t dtype;  /* rpca_dtype  */
+  int64_t m, n;
+  const void* data;
+  int64_t ld;
+  const float* col_scale;
+  const float* data_f32;
+  int64_t ld_f32;
+  int64_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+  const int32_t* col_ptr;
+  const int32_t* row_idx;
+  const void* val_t;
+} rpca_matrix;
+
+/* flags */
+enum {
+  RPCA_CENTER = 1u, /* PCA of the column-centered matrix (Sections 2 and 5) */
+  RPCA_SYNC = 2u    /* synchronize the stream before returning              */
+};
+
+/* Create a context on the current HIP device, ordered on ``hip_stream``
+ * (a hipStream_t; NULL = the null stream).  Owns its workspace. */
+rpca_status rpca_create(rpca_ctx* out, void* hip_stream);
+rpca_status rpca_destroy(rpca_ctx ctx);
+rpca_status rpca_set_stream(rpca_ctx ctx, void* hip_stream);
+/* Cap on the workspace the context may hold (bytes; 0 = no cap).  A call
+ * that needs more returns RPCA_ERR_NO_MEMORY before launching anything. */
+rpca_status rpca_set_workspace_limit(rpca_ctx ctx, size_t bytes);
+rpca_status rpca_workspace_size(rpca_ctx ctx, const rpca_matrix* A, int k, int l,
+                                size_t* bytes);
+
+/* Randomized SVD / PCA, Section 2 (formulas (i1)-(i4) and (approx)) with the
+ * renormalized power iteration of Sections 2 and 5: Y = A Omega, then ``its``
+ * times Z = A* Q, Y = A Q, renormalizing by pivoted LU after every
+ * application except the last, which is orthonormalized (QR); then
+ * B = Q* A and its SVD.  Omega (n x l, Gaussian) is a pure function of
+ * ``seed``: Philox4x32-10 stream 0.  With RPCA_CENTER the result is the PCA of
+ * A - 1 c (c = column means) without forming it (Section 5).
+ * Outputs: U (m x k, row-major, ldu >= k), S (k doubles, descending),
+ * V (n x k, row-major, ldv >= k); U diag(S) V^T approximates A.  Columns of U
+ * are signed so that the largest-magnitude entry is positive. */
+rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
+                     uint64_t seed, unsigned flags, float* U, int64_t ldu, double* S,
+                     float* V, int64_t ldv);
+
+/* Shift-stabilized Nystrom method for a symmetric positive semidefinite n x n
+ * A (Section 3, formulas (start)-(finish), after the self-adjoint core loop of
+ * Section 5): U (n x k) and lambda (k, descending) with A ~ U diag(lambda) U*.
+ * The shift is nu = sqrt(n) * u * ||A Q||_F (u = unit roundoff of the storage
+ * precision), multiplied by 10 up to 10 times while the Cholesky factor does
+ * not exist; then RPCA_ERR_NOT_PSD. */
+rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
+                         uint64_t seed, unsigned flags, float* U, int64_t ldu,
+                         double* lambda);
+
+/* Randomized power-method estimate of ||A - U diag(S) V^T||_2 (Section 4),
+ * in float64: ``iters`` steps of X <- orth(E^T E X) from a Gaussian n x 4
+ * start block (Philox stream 1), estimate = ||E X||_2 <= ||E||_2.
+ * V == NULL means the symmetric residual A - U diag(S) U^T.  RPCA_CENTER
+ * measures against the column-centered A.  ``err_host`` is a host pointer;
+ * the call synchronizes. */
+rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const float* U,
+                              int64_t ldu, const double* S, const float* V, int64_t ldv,
+                              int iters, uint64_t seed, unsigned flags, double* err_host);
+
+/* The Gaussian test matrix alone: out[i*ldo + j] = z[j*n + i] for i < n,
+ * j < l, where z is Philox4x32-10 stream ``stream`` under key ``seed`` mapped
+ * through the Box-Muller transform (evaluated in float64, rounded to float32).
+ * Exposed so that the generator can be checked against an independent
+ * implementation.  ``words_out`` (may be NULL) receives the raw 32-bit words
+ * of blocks 0 .. ceil(n*l/4)-1, four per block. */
+rpca_status rpca_gaussian(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
+                          float* out, int64_t ldo, uint32_t* words_out);
+
+/* ---- single steps of the method, exposed for testing ------------------- */
+
+/* Y = A X (trans = 0; X is n x l, Y is m x l) or Y = A^T X (trans = 1; X is
+ * m x l, Y is n x l), float32 X/Y row-major, using the same kernels as the
+ * solvers.  With RPCA_CENTER, A is replaced by A - 1 c. */
+rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l,
+                           const float* X, int64_t ldx, float* Y, int64_t ldy,
+                           unsigned flags);
+/* Renormalization of a tall r x l float32 matrix Y, in place.
+ * kind = 0: pivoted LU (Q = P L, tournament pivoting), ``piv`` (may be NULL,
+ *           device int32[l]) receives the pivot rows;
+ * kind = 1: orthonormalization (Cholesky QR with float64 Gram matrices),
+ *           ``R`` (may be NULL, device double[l*l], row-major) receives the
+ *           upper triangular R with Y_in = Q R. */
+rpca_status rpca_op_renorm(rpca_ctx ctx, int kind, int64_t rows, int l, float* Y, int64_t ldy,
+                           int32_t* piv, double* R);
+/* SVD of an l x l float64 matrix M (row-major, device): M = W diag(s) X^T
+ * with s descending; W, X are l x l row-major (device). */
+rpca_status rpca_op_small_svd(rpca_ctx ctx, int l, const double* M, double* s, double* W,
+                              double* X);
+
+/* ---- diagnostics -------------------------------------------------------- */
+
+typedef struct {
+  int64_t calls;          /* solver calls since the last reset               */
+  int64_t a_passes;       /* passes over A launched                          */
+  int64_t timed_launches; /* launches of the A-pass kernels that were timed  */
+  double ms_ax;           /* total device time of Y = A X kernels (ms)        */
+  double ms_atx;          /* total device time of A^T X kernels (ms)          */
+  int64_t n_ax, n_atx;    /* number of timed launches of each                */
+  double bytes_ax;        /* algorithmic bytes of the timed A X launches      */
+  double bytes_atx;       /* algorithmic bytes of the timed A^T X launches    */
+  int64_t shift_retries;  /* Nystrom shift retries (last call)               */
+} rpca_stats;
+
+/* Record HIP events around every A-pass kernel launch (on the context
+ * stream) when ``enable`` is nonzero. */
+rpca_status rpca_set_timing(rpca_ctx ctx, int enable);
+/* Synchronizes the stream, folds the recorded events into the totals. */
+rpca_status rpca_get_stats(rpca_ctx ctx, rpca_stats* out);
+rpca_status rpca_reset_stats(rpca_ctx ctx);
+
+const char* rpca_status_str(rpca_status s);
+const char* rpca_last_error(rpca_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPCA_H */

@@ -1,0 +1,289 @@
+"""Python binding of librpca, an MI355X (gfx950) implementation of the
+randomized PCA of Szlam, Kluger and Tygert (ACM TOMS 2014, arXiv:1412.3510).
+
+The binding only marshals arguments: every step runs in the HIP kernels of
+``librpca.so`` (built by ``paper_1412_3510_amd.build``).  PyTorch provides the
+device memory and the stream.  There is no fallback: if the library is
+missing, ``load()`` raises.
+
+    import torch, paper_1412_3510_amd as rp
+    ctx = rp.Context()
+    U, S, V = ctx.svd(A, k=50, l=60, its=2, seed=1, center=True)
+"""
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpca.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rpca.h")
+
+F32, BF16, FP8_E4M3 = 0, 1, 2
+DENSE_ROWMAJOR, SPARSE_CSR = 0, 1
+CENTER, SYNC = 1, 2
+
+STATUS = {
+    0: "RPCA_OK",
+    1: "RPCA_ERR_INVALID_ARG",
+    2: "RPCA_ERR_UNSUPPORTED",
+    3: "RPCA_ERR_NO_MEMORY",
+    4: "RPCA_ERR_HIP",
+    5: "RPCA_ERR_NOT_PSD",
+    6: "RPCA_ERR_NUMERICAL",
+}
+
+
+class RpcaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [
+        ("format", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("data", ctypes.c_void_p),
+        ("ld", ctypes.c_int64),
+        ("col_scale", ctypes.c_void_p),
+        ("data_f32", ctypes.c_void_p),
+        ("ld_f32", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+        ("col_ptr", ctypes.c_void_p),
+        ("row_idx", ctypes.c_void_p),
+        ("val_t", ctypes.c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("calls", ctypes.c_int64),
+        ("a_passes", ctypes.c_int64),
+        ("timed_launches", ctypes.c_int64),
+        ("ms_ax", ctypes.c_double),
+        ("ms_atx", ctypes.c_double),
+        ("n_ax", ctypes.c_int64),
+        ("n_atx", ctypes.c_int64),
+        ("bytes_ax", ctypes.c_double),
+        ("bytes_atx", ctypes.c_double),
+        ("shift_retries", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+P, I32, I64, U32, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                            ctypes.c_uint64, ctypes.c_double)
+
+_SIGS = {
+    "rpca_create": [ctypes.POINTER(P), P],
+    "rpca_destroy": [P],
+    "rpca_set_stream": [P, P],
+    "rpca_set_workspace_limit": [P, ctypes.c_size_t],
+    "rpca_workspace_size": [P, ctypes.POINTER(Matrix), I32, I32, ctypes.POINTER(ctypes.c_size_t)],
+    "rpca_svd": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P, P, I64],
+    "rpca_eig_psd": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P],
+    "rpca_spectral_err": [P, ctypes.POINTER(Matrix), I32, P, I64, P, P, I64, I32, U64,
+                          ctypes.c_uint, ctypes.POINTER(D)],
+    "rpca_gaussian": [P, U64, U32, I64, I64, P, I64, P],
+    "rpca_op_matmul": [P, ctypes.POINTER(Matrix), I32, I32, P, I64, P, I64, ctypes.c_uint],
+    "rpca_op_renorm": [P, I32, I64, I32, P, I64, P, P],
+    "rpca_op_small_svd": [P, I32, P, P, P, P],
+    "rpca_set_timing": [P, I32],
+    "rpca_get_stats": [P, ctypes.POINTER(Stats)],
+    "rpca_reset_stats": [P],
+}
+
+
+def header_symbols():
+    """Names of the functions declared in include/rpca.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rpca_\w+)\s*\(", text, re.M)))
+
+
+def load():
+    """Load librpca.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("librpca.so is not built: run `python -m paper_1412_3510_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rpca_status_str.argtypes = [ctypes.c_int]
+    lib.rpca_status_str.restype = ctypes.c_char_p
+    lib.rpca_last_error.argtypes = [P]
+    lib.rpca_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def dense(A, dtype=None, col_scale=None, A_f32=None):
+    """rpca_matrix for a row-major 2-D CUDA tensor (float32, bfloat16 or float8_e4m3fn)."""
+    import torch
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor")
+    if not A.is_cuda:
+        raise ValueError("A must live on the GPU")
+    code = {torch.float32: F32, torch.bfloat16: BF16}.get(A.dtype)
+    if code is None and hasattr(torch, "float8_e4m3fn") and A.dtype == torch.float8_e4m3fn:
+        code = FP8_E4M3
+    if code is None:
+        raise ValueError("unsupported dtype %s" % A.dtype)
+    mat = Matrix()
+    mat.format = DENSE_ROWMAJOR
+    mat.dtype = code if dtype is None else dtype
+    mat.m, mat.n = A.shape
+    mat.data = A.data_ptr()
+    mat.ld = A.stride(0)
+    mat.col_scale = col_scale.data_ptr() if col_scale is not None else None
+    if A_f32 is not None:
+        mat.data_f32 = A_f32.data_ptr()
+        mat.ld_f32 = A_f32.stride(0)
+    return mat
+
+
+class Context:
+    """A library context bound to a torch CUDA stream (the current one by default)."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.lib = load()
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.rpca_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream)))
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rpca_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.rpca_last_error(self.h).decode() if getattr(self, "h", None) else ""
+            raise RpcaError(st, msg)
+
+    # ---- solvers -------------------------------------------------------
+    def svd(self, A, k, l=None, its=2, seed=0, center=False, sync=False, out=None, mat=None):
+        """U (m x k), S (k, float64), V (n x k) with U diag(S) V^T ~ A (or A - 1 c)."""
+        torch = self._torch
+        m, n = A.shape
+        l = k + 2 if l is None else l
+        if out is None:
+            U = torch.empty(m, k, device=A.device, dtype=torch.float32)
+            S = torch.empty(k, device=A.device, dtype=torch.float64)
+            V = torch.empty(n, k, device=A.device, dtype=torch.float32)
+        else:
+            U, S, V = out
+        mat = dense(A) if mat is None else mat
+        flags = (CENTER if center else 0) | (SYNC if sync else 0)
+        self._check(self.lib.rpca_svd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
+                                      _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0)))
+        return U, S, V
+
+    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False):
+        torch = self._torch
+        n = A.shape[0]
+        l = k + 2 if l is None else l
+        U = torch.empty(n, k, device=A.device, dtype=torch.float32)
+        lam = torch.empty(k, device=A.device, dtype=torch.float64)
+        mat = dense(A)
+        self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed,
+                                          SYNC if sync else 0, _ptr(U), U.stride(0), _ptr(lam)))
+        return U, lam
+
+    def spectral_err(self, A, U, S, V=None, iters=20, seed=0, center=False):
+        mat = dense(A)
+        out = ctypes.c_double()
+        k = U.shape[1]
+        self._check(self.lib.rpca_spectral_err(
+            self.h, ctypes.byref(mat), k, _ptr(U), U.stride(0), _ptr(S), _ptr(V),
+            V.stride(0) if V is not None else 0, iters, seed, CENTER if center else 0,
+            ctypes.byref(out)))
+        return out.value
+
+    # ---- single steps --------------------------------------------------
+    def gaussian(self, seed, n, l, stream=0, words=False):
+        torch = self._torch
+        out = torch.zeros(n, l, device="cuda", dtype=torch.float32)
+        w = None
+        if words:
+            w = torch.zeros(((n * l + 3) // 4) * 4, device="cuda", dtype=torch.int32)
+        self._check(self.lib.rpca_gaussian(self.h, seed, stream, n, l, _ptr(out), out.stride(0),
+                                           _ptr(w)))
+        return (out, w) if words else out
+
+    def matmul(self, A, X, trans=False, center=False):
+        torch = self._torch
+        m, n = A.shape
+        l = X.shape[1]
+        Y = torch.empty(n if trans else m, l, device=A.device, dtype=torch.float32)
+        mat = dense(A)
+        self._check(self.lib.rpca_op_matmul(self.h, ctypes.byref(mat), 1 if trans else 0, l,
+                                            _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+                                            CENTER if center else 0))
+        return Y
+
+    def renorm(self, Y, kind="lu"):
+        torch = self._torch
+        Y = Y.clone()
+        rows, l = Y.shape
+        piv = torch.empty(l, device=Y.device, dtype=torch.int32)
+        R = torch.empty(l, l, device=Y.device, dtype=torch.float64)
+        k = 0 if kind == "lu" else 1
+        self._check(self.lib.rpca_op_renorm(self.h, k, rows, l, _ptr(Y), Y.stride(0),
+                                            _ptr(piv) if k == 0 else None,
+                                            _ptr(R) if k == 1 else None))
+        return (Y, piv) if k == 0 else (Y, R)
+
+    def small_svd(self, M):
+        torch = self._torch
+        l = M.shape[0]
+        M = M.to(torch.float64).contiguous()
+        s = torch.empty(l, device=M.device, dtype=torch.float64)
+        W = torch.empty(l, l, device=M.device, dtype=torch.float64)
+        X = torch.empty(l, l, device=M.device, dtype=torch.float64)
+        self._check(self.lib.rpca_op_small_svd(self.h, l, _ptr(M), _ptr(s), _ptr(W), _ptr(X)))
+        return W, s, X
+
+    # ---- diagnostics ---------------------------------------------------
+    def set_timing(self, on=True):
+        self._check(self.lib.rpca_set_timing(self.h, 1 if on else 0))
+
+    def stats(self):
+        st = Stats()
+        self._check(self.lib.rpca_get_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        self._check(self.lib.rpca_reset_stats(self.h))
+
+    def set_workspace_limit(self, nbytes):
+        self._check(self.lib.rpca_set_workspace_limit(self.h, nbytes))

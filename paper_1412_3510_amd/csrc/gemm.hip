@@ -1,0 +1,360 @@
+// Passes over A: Y = A X and Z = A^T X with X tall and skinny (l <= 128).
+//
+// These are the products the paper identifies as the cost of the method
+// (Section 2: A has far more entries than any other matrix; Section 5: A* is
+// applied as (Q* A)* so that A is streamed in its own storage order).  Each
+// pass streams A once from HBM in coalesced 128/512-byte row segments and
+// feeds MFMA tiles through LDS.
+//
+// Arithmetic: float32 A and X are split into bfloat16 pairs (hi, lo) and
+// multiplied as hi*hi' + hi*lo' + lo*hi' with float32 accumulation on
+// v_mfma_f32_32x32x16_bf16; the dropped lo*lo' term and the split residuals
+// are below 2^-16 relative per product.  The split keeps the pass bound by
+// HBM bandwidth: three bf16 MFMAs cost less than one float32 FMA stream at
+// the arithmetic intensity of l = 60..120 columns.
+//
+// Fragment order (the layout of LDS tiles and of packed X): for a K16 step s
+// (16 consecutive K indices) and a 32-wide column block cb, a fragment is 64
+// lanes x 8 bf16 = 1 KB in which lane L = c + 32 g holds the K indices
+// 16 s + 8 g + j (j = 0..7) of column c.  This is the operand layout of
+// v_mfma_f32_32x32x16_bf16 for both the A and the B operand; the
+// accumulator of lane L, register r, is (row (r%4) + 4 g + 8 (r/4), col c).
+#include "common.h"
+#include "kernels.h"
+
+namespace rpca {
+
+static constexpr int kFragElems = 512;  // bf16 per 1 KB fragment
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical tile ids so tiles that share operands share an
+// L2.
+__device__ __forceinline__ int xcd_remap(int b, int nwg) {
+  if (nwg % 8 != 0) return b;
+  return (b % 8) * (nwg / 8) + b / 8;
+}
+
+__device__ __forceinline__ f32x16 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                        const bf16x8& bl, f32x16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+  return acc;
+}
+
+// ------------------------------------------------------------------------
+// pack: tall float32 X (rows x cols, ld ldx) -> fragment-ordered bf16 (hi, lo)
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pack_kernel(const float* __restrict__ X, int64_t ldx,
+                                                   int64_t rows, int cols, int nb,
+                                                   const float* __restrict__ mu,
+                                                   const float* __restrict__ rscale,
+                                                   __bf16* __restrict__ out, int64_t nsteps) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = nsteps * nb * RPCA_WAVE;
+  if (t >= total) return;
+  const int L = (int)(t % RPCA_WAVE);
+  const int64_t rest = t / RPCA_WAVE;
+  const int cb = (int)(rest % nb);
+  const int64_t s = rest / nb;
+  const int c = 32 * cb + (L & 31);
+  const int g = L >> 5;
+  bf16x8 hi, lo;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t r = 16 * s + 8 * g + j;
+    float v = 0.f;
+    if (r < rows && c < cols) {
+      v = X[r * ldx + c];
+      if (mu) v -= mu[c];
+      if (rscale) v *= rscale[r];
+    }
+    __bf16 h, lw;
+    split_bf16(v, h, lw);
+    hi[j] = h;
+    lo[j] = lw;
+  }
+  const int64_t base = ((s * nb + cb) * 2) * kFragElems + (int64_t)L * 8;
+  *reinterpret_cast<bf16x8*>(out + base) = hi;
+  *reinterpret_cast<bf16x8*>(out + base + kFragElems) = lo;
+}
+
+size_t packed_bytes(int64_t nsteps, int nb) { return (size_t)nsteps * nb * 2 * 1024; }
+
+void launch_pack(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols, int nb,
+                 const float* mu, const float* rscale, __bf16* out, int64_t nsteps) {
+  const int64_t total = nsteps * nb * RPCA_WAVE;
+  if (total == 0) return;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, X, ldx,
+                     rows, cols, nb, mu, rscale, out, nsteps);
+}
+
+// ------------------------------------------------------------------------
+// float32 row loads with bounds
+// ------------------------------------------------------------------------
+__device__ __forceinline__ float4 load_row4(const float* __restrict__ A, int64_t lda, int64_t r,
+                                            int64_t c, int64_t rmax, int64_t n, bool vec) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (r >= rmax) return v;
+  const float* p = A + r * lda + c;
+  if (vec && c + 4 <= n) return *reinterpret_cast<const float4*>(p);
+  if (c + 0 < n) v.x = p[0];
+  if (c + 1 < n) v.y = p[1];
+  if (c + 2 < n) v.z = p[2];
+  if (c + 3 < n) v.w = p[3];
+  return v;
+}
+
+// ------------------------------------------------------------------------
+// Y = A X.  Workgroup: 4 waves, BM = 32*WR rows x 32*NB columns; each wave a
+// 32-row block and NB/WC column blocks.  K advances 32 columns per stage.
+// ------------------------------------------------------------------------
+template <int NB>
+__global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A, int64_t lda,
+                                                     int64_t m, int64_t n,
+                                                     const __bf16* __restrict__ Xp,
+                                                     float* __restrict__ Y, int64_t ldy,
+                                                     int vec) {
+  constexpr int WR = (NB == 1) ? 4 : 2;
+  constexpr int WC = 4 / WR;
+  constexpr int CBW = NB / WC;
+  constexpr int BM = 32 * WR;
+  constexpr int KC = 32;
+  constexpr int AF4 = BM * KC / 4 / 256;  // float4 per thread per stage
+  constexpr int XU4 = NB;                 // 16-byte words per thread per stage
+  __shared__ __attribute__((aligned(16))) char lds_a[WR * 4 * 1024];
+  __shared__ __attribute__((aligned(16))) char lds_x[NB * 4 * 1024];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rbw = wave % WR, cw = wave / WR;
+  const int64_t row0 = (int64_t)blockIdx.x * BM;
+  const int64_t nstage = ceil_div(n, KC);
+
+  float4 ra[AF4];
+  uint4 rx[XU4];
+  auto load_stage = [&](int64_t stg) {
+#pragma unroll
+    for (int v = 0; v < AF4; ++v) {
+      const int q = tid + 256 * v;
+      ra[v] = load_row4(A, lda, row0 + (q >> 3), stg * KC + 4 * (q & 7), m, n, vec != 0);
+    }
+    const uint4* xs = reinterpret_cast<const uint4*>(Xp + stg * 2 * NB * 2 * kFragElems);
+#pragma unroll
+    for (int v = 0; v < XU4; ++v) rx[v] = xs[tid + 256 * v];
+  };
+
+  f32x16 acc[CBW];
+#pragma unroll
+  for (int i = 0; i < CBW; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+
+  load_stage(0);
+  for (int64_t stg = 0; stg < nstage; ++stg) {
+#pragma unroll
+    for (int v = 0; v < AF4; ++v) {
+      const int q = tid + 256 * v;
+      const int row = q >> 3, c4 = q & 7;
+      const int rb = row >> 5, r = row & 31, s = c4 >> 2, g = (c4 & 3) >> 1, j0 = 4 * (c4 & 1);
+      bf16x4 h, lo;
+      __bf16 th, tl;
+      split_bf16(ra[v].x, th, tl); h[0] = th; lo[0] = tl;
+      split_bf16(ra[v].y, th, tl); h[1] = th; lo[1] = tl;
+      split_bf16(ra[v].z, th, tl); h[2] = th; lo[2] = tl;
+      split_bf16(ra[v].w, th, tl); h[3] = th; lo[3] = tl;
+      const int off = ((rb * 2 + s) * 2) * 1024 + 16 * (r + 32 * g) + 2 * j0;
+      *reinterpret_cast<bf16x4*>(lds_a + off) = h;
+      *reinterpret_cast<bf16x4*>(lds_a + off + 1024) = lo;
+    }
+#pragma unroll
+    for (int v = 0; v < XU4; ++v) reinterpret_cast<uint4*>(lds_x)[tid + 256 * v] = rx[v];
+    __syncthreads();
+    if (stg + 1 < nstage) load_stage(stg + 1);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(lds_a + ((rbw * 2 + s) * 2) * 1024 + 16 * lane);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(lds_a + ((rbw * 2 + s) * 2 + 1) * 1024 + 16 * lane);
+#pragma unroll
+      for (int i = 0; i < CBW; ++i) {
+        const int cb = cw * CBW + i;
+        const bf16x8 xh = *reinterpret_cast<const bf16x8*>(lds_x + ((s * NB + cb) * 2) * 1024 + 16 * lane);
+        const bf16x8 xl = *reinterpret_cast<const bf16x8*>(lds_x + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
+        acc[i] = mfma3(ah, al, xh, xl, acc[i]);
+      }
+    }
+    __syncthreads();
+  }
+  const int g = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < CBW; ++i) {
+    const int col = 32 * (cw * CBW + i) + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = row0 + 32 * rbw + (r & 3) + 4 * g + 8 * (r >> 2);
+      if (row < m) Y[row * ldy + col] = acc[i][r];
+    }
+  }
+}
+
+void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+               const __bf16* Xp, float* Y, int64_t ldy, int nb) {
+  (void)dtype;
+  const float* Af = static_cast<const float*>(A);
+  const int vec = ((lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Af) % 16) == 0) ? 1 : 0;
+  const int bm = (nb == 1) ? 128 : 64;
+  const dim3 grid((unsigned)ceil_div(m, bm));
+  switch (nb) {
+    case 1: hipLaunchKernelGGL(ax_f32_kernel<1>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, Y, ldy, vec); break;
+    case 2: hipLaunchKernelGGL(ax_f32_kernel<2>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, Y, ldy, vec); break;
+    case 4: hipLaunchKernelGGL(ax_f32_kernel<4>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, Y, ldy, vec); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Z = A^T X, split over rows of A.  Workgroup: 4 waves on a 128-column tile
+// of A (one 32-column block per wave) and all 32*NB columns of X.  Each
+// thread loads 4 rows x 4 columns of a 32-row stage (coalesced 512-byte row
+// segments) and scatters them into B-operand fragments.  Partials are
+// written in accumulator order and summed by atx_reduce_kernel.
+// ------------------------------------------------------------------------
+template <int NB>
+__global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ A, int64_t lda,
+                                                      int64_t m, int64_t n,
+                                                      const __bf16* __restrict__ Xp,
+                                                      float* __restrict__ P, int ntiles,
+                                                      int64_t rows_per, int vec) {
+  constexpr int KC = 32;
+  __shared__ __attribute__((aligned(16))) char lds_a[16 * 1024];      // [s 2][jb 4][part 2]
+  __shared__ __attribute__((aligned(16))) char lds_x[NB * 4 * 1024];  // [s 2][cb NB][part 2]
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int split = t / ntiles, tile = t % ntiles;
+  const int64_t col0 = (int64_t)tile * 128;
+  const int64_t rbeg = (int64_t)split * rows_per;
+  const int64_t rend = (rbeg + rows_per < m) ? rbeg + rows_per : m;
+  const int64_t nstage = (rend > rbeg) ? ceil_div(rend - rbeg, KC) : 0;
+
+  const int cg = tid & 31, ro = tid >> 5;
+  float4 ra[4];
+  uint4 rx[NB];
+  auto load_stage = [&](int64_t stg) {
+    const int64_t r0 = rbeg + stg * KC + 4 * ro;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = load_row4(A, lda, r0 + q, col0 + 4 * cg, rend, n, vec != 0);
+    const uint4* xs = reinterpret_cast<const uint4*>(Xp + (rbeg / 16 + 2 * stg) * NB * 2 * kFragElems);
+#pragma unroll
+    for (int v = 0; v < NB; ++v) rx[v] = xs[tid + 256 * v];
+  };
+
+  f32x16 acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+
+  const int s_w = ro >> 2, g_w = (ro & 3) >> 1, jj0 = 4 * (ro & 1);
+  const int jb_w = cg >> 3;
+  if (nstage > 0) load_stage(0);
+  for (int64_t stg = 0; stg < nstage; ++stg) {
+#pragma unroll
+    for (int qc = 0; qc < 4; ++qc) {
+      const int j = (4 * cg + qc) & 31;
+      bf16x4 h, lo;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float x = (qc == 0) ? ra[q].x : (qc == 1) ? ra[q].y : (qc == 2) ? ra[q].z : ra[q].w;
+        __bf16 th, tl;
+        split_bf16(x, th, tl);
+        h[q] = th;
+        lo[q] = tl;
+      }
+      const int off = ((s_w * 4 + jb_w) * 2) * 1024 + 16 * (j + 32 * g_w) + 2 * jj0;
+      *reinterpret_cast<bf16x4*>(lds_a + off) = h;
+      *reinterpret_cast<bf16x4*>(lds_a + off + 1024) = lo;
+    }
+#pragma unroll
+    for (int v = 0; v < NB; ++v) reinterpret_cast<uint4*>(lds_x)[tid + 256 * v] = rx[v];
+    __syncthreads();
+    if (stg + 1 < nstage) load_stage(stg + 1);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(lds_a + ((s * 4 + wave) * 2) * 1024 + 16 * lane);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(lds_a + ((s * 4 + wave) * 2 + 1) * 1024 + 16 * lane);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const bf16x8 xh = *reinterpret_cast<const bf16x8*>(lds_x + ((s * NB + cb) * 2) * 1024 + 16 * lane);
+        const bf16x8 xl = *reinterpret_cast<const bf16x8*>(lds_x + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
+        acc[cb] = mfma3(xh, xl, bh, bl, acc[cb]);
+      }
+    }
+    __syncthreads();
+  }
+  float* out = P + ((int64_t)(split * ntiles + tile) * 4 + wave) * NB * 1024;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[(cb * 16 + r) * 64 + lane] = acc[cb][r];
+}
+
+AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus) {
+  AtxPlan p;
+  p.ntiles = (int)ceil_div(n, 128);
+  const int64_t stages = ceil_div(m, 32);
+  // aim at ~4 workgroups per CU, a multiple of 8 workgroups, >= 8 stages per split
+  int64_t want = (int64_t)4 * num_cus / p.ntiles;
+  if (want < 1) want = 1;
+  int64_t maxs = stages / 8;
+  if (maxs < 1) maxs = 1;
+  if (want > maxs) want = maxs;
+  int64_t per = ceil_div(stages, want);
+  p.nsplit = (int)ceil_div(stages, per);
+  p.rows_per = per * 32;
+  p.partial_bytes = (size_t)p.nsplit * p.ntiles * 4 * nb * 1024 * sizeof(float);
+  return p;
+}
+
+void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+                const __bf16* Xp, float* P, const AtxPlan& plan, int nb) {
+  (void)dtype;
+  const float* Af = static_cast<const float*>(A);
+  const int vec = ((lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Af) % 16) == 0) ? 1 : 0;
+  const dim3 grid((unsigned)(plan.ntiles * plan.nsplit));
+  switch (nb) {
+    case 1: hipLaunchKernelGGL(atx_f32_kernel<1>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per, vec); break;
+    case 2: hipLaunchKernelGGL(atx_f32_kernel<2>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per, vec); break;
+    case 4: hipLaunchKernelGGL(atx_f32_kernel<4>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per, vec); break;
+    default: break;
+  }
+}
+
+// Z[j][c] = sum over splits of the partial at (tile, wave, cb, r, lane).
+__global__ void __launch_bounds__(256) atx_reduce_kernel(const float* __restrict__ P, int nsplit,
+                                                         int ntiles, int nb, int64_t n,
+                                                         const float* __restrict__ cscale,
+                                                         float* __restrict__ Z, int64_t ldz) {
+  const int64_t per_split = (int64_t)ntiles * 4 * nb * 1024;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per_split) return;
+  const int lane = (int)(e & 63);
+  const int r = (int)((e >> 6) & 15);
+  const int cb = (int)((e >> 10) % nb);
+  const int64_t wt = (e >> 10) / nb;  // tile * 4 + wave
+  const int64_t j = (wt >> 2) * 128 + 32 * (wt & 3) + (lane & 31);
+  if (j >= n) return;
+  const int c = 32 * cb + (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2);
+  float s = 0.f;
+  for (int sp = 0; sp < nsplit; ++sp) s += P[sp * per_split + e];
+  if (cscale) s *= cscale[j];
+  Z[j * ldz + c] = s;
+}
+
+void launch_atx_reduce(hipStream_t st, const float* P, const AtxPlan& plan, int nb, int64_t n,
+                       const float* cscale, float* Z, int64_t ldz) {
+  const int64_t per_split = (int64_t)plan.ntiles * 4 * nb * 1024;
+  hipLaunchKernelGGL(atx_reduce_kernel, dim3((unsigned)ceil_div(per_split, 256)), dim3(256), 0, st,
+                     P, plan.nsplit, plan.ntiles, nb, n, cscale, Z, ldz);
+}
+
+}  // namespace rpca

@@ -1,0 +1,116 @@
+// Internal launchers (host side) for the HIP kernels of the randomized PCA.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpca {
+
+// ---- Philox Gaussian (philox.hip) -------------------------------------------
+void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
+                     float* out, int64_t ldo, uint32_t* words);
+
+// ---- dense products (gemm.hip) ----------------------------------------------
+// Fragment-ordered bfloat16 (hi, lo) copy of a tall float32 matrix, used as
+// the small operand of both products.  ``nsteps`` 16-row steps are written
+// (rows past ``rows`` are zero); ``mu`` (nullable, float[cols]) is subtracted
+// from every valid row first; ``rscale`` (nullable, float[rows]) multiplies
+// row r.
+size_t packed_bytes(int64_t nsteps, int nb);
+void launch_pack(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols, int nb,
+                 const float* mu, const float* rscale, __bf16* out, int64_t nsteps);
+
+// Y (m x 32*nb) = A (m x n) X, X packed with >= 2*ceil(n/32) steps.
+void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+               const __bf16* Xp, float* Y, int64_t ldy, int nb);
+
+// Split-K partial products of A^T X (X packed on the m side).
+struct AtxPlan {
+  int ntiles;        // ceil(n / 128)
+  int nsplit;        // number of row splits
+  int64_t rows_per;  // rows per split (multiple of 32)
+  size_t partial_bytes;
+};
+AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus);
+void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+                const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
+// Z (n x 32*nb) = sum of the partials (fixed order); ``cscale`` (nullable,
+// float[n]) multiplies row j of Z.
+void launch_atx_reduce(hipStream_t st, const float* P, const AtxPlan& plan, int nb, int64_t n,
+                       const float* cscale, float* Z, int64_t ldz);
+
+// ---- tall-skinny helpers (tall.hip) -------------------------------------------
+// mu[c] = mean over rows of X[:, c] for c < cols (float64 accumulation).
+void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
+                    double* partial, int nblk_max, float* mu);
+int colmean_blocks(int64_t rows);
+// X[r, c] -= mu[c]
+void launch_sub_rowvec(hipStream_t st, float* X, int64_t ldx, int64_t rows, int cols,
+                       const float* mu);
+// Gram G = X^T X2 (float64; X2 = X when null), in two stages.  ``partial``
+// holds gram_blocks(rows)*lp*lp doubles.  Skipped when *skip_flag == 0.
+int gram_blocks(int64_t rows);
+void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int lp,
+                 const float* X2, int64_t ldx2, double* partial, double* G,
+                 const int* skip_flag);
+// fro2[0] = sum of squares of X (float64); psum/psq hold colmean_blocks(rows)*128 doubles
+void launch_fro2_d(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
+                   double* psum, double* psq, double* fro2);
+// In-place right triangular solve X <- X U^-1 (U upper, float32, lp x lp),
+// with the pivoted-LU convention for zero pivots (see tall.hip).
+void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int lp,
+                 const float* Ut, const int* piv, const int* skip_flag, const float* nu,
+                 const float* addX, int64_t ldadd);
+// Y (rows x k) = X (rows x lp) W (lp x k, float64, row-major ld ldw)
+void launch_small_gemm(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,
+                       const double* W, int ldw, int k, float* Y, int64_t ldy);
+// Sign convention: flip columns of U (and V) so the largest-|.| entry of each
+// U column is positive.  ``work`` holds sign_work_bytes(m) bytes.
+size_t sign_work_bytes(int64_t m);
+void launch_sign_fix(hipStream_t st, float* U, int64_t ldu, int64_t m, int k, float* V,
+                     int64_t ldv, int64_t n, int* work);
+
+// ---- pivoted LU by tournament (lu.hip) ---------------------------------------
+struct LuPlan {
+  int lp;
+  int levels;
+  int nblk[16];        // blocks at each level (level 0 = leaves)
+  int64_t cand_off[16];
+  int64_t cand_total;  // ints
+  int64_t counter_total;
+};
+LuPlan plan_lu(int64_t rows, int lp);
+// Tournament pivoting over rows of X; writes the root's U (lp x lp float32,
+// row-major), the pivot rows piv[l] and zero-pivot markers (U[j][j] == 0).
+void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,
+                    const LuPlan& plan, int* cand, unsigned* counters, float* U, int* piv);
+
+// ---- small dense float64 kernels (small.hip) ---------------------------------
+// One Cholesky-QR step on the Gram G (lp x lp): upper R (float32 copy ``Rf``
+// for the solve), optional accumulation Racc <- R Racc (float64).  Passes 1
+// and 2 always run; passes 3 and 4 only when state[1] is set (a shifted
+// factorization or dependent columns met).  See small.hip for ``state``.
+void launch_chol_qr_step(hipStream_t st, const double* G, int l, int lp, int pass, float* Rf,
+                         double* Racc, int* state);
+// Replace the dependent columns flagged in ``state`` by Gaussian columns.
+void launch_complete(hipStream_t st, float* Q, int64_t ldq, int64_t rows, int l, const int* state,
+                     uint64_t seed);
+// Nystrom: B2 = sym(G) + nu I with nu = n_sqrt_u * sqrt(fro2[0]), Cholesky
+// with nu <- 10 nu retries; writes C (float32 upper), nu (double and float).
+void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const double* fro2,
+                         double n_sqrt_u, float* Rf, double* nu_out, float* nu_f, int* state,
+                         int max_retries);
+// One-sided Jacobi SVD of M (l x l, float64 row-major ld lp) or of M^T:
+// s (descending), Wacc (accumulated rotations, columns sorted), Xn
+// (normalized columns of M Wacc, sorted).  ``work`` holds 2*lp*lp doubles.
+void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
+                       double* Wacc, double* Xn, double* work);
+// out[j] = s[j] (nu null) or max(s[j]^2 - nu, 0), j < k
+void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out);
+
+// ---- spectral-norm estimate (spectral.hip) -------------------------------------
+void launch_spectral(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, bool center,
+                     const float* U, int64_t ldu, const double* S, const float* V, int64_t ldv,
+                     int k, int iters, uint64_t seed, void* work, double* result);
+size_t spectral_work_bytes(int64_t m, int64_t n, int k);
+
+}  // namespace rpca

@@ -1,0 +1,654 @@
+// Host runtime and C ABI: context, workspace, argument checks, and the
+// stream-ordered launch sequences of the randomized SVD (Sections 2 and 5),
+// the Nystrom method (Section 3) and the step-level test entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rpca.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace rpca;
+
+namespace {
+
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int kind;  // 0 = A X, 1 = A^T X
+  double bytes;
+};
+
+}  // namespace
+
+struct rpca_ctx_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cus = 256;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_limit = 0;
+  unsigned* counters = nullptr;  // LU arrival counters; zero between launches
+  size_t counters_n = 0;
+  std::string err;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> event_pool;
+  rpca_stats stats{};
+  int* host_state = nullptr;  // pinned
+};
+
+namespace {
+
+rpca_status fail(rpca_ctx c, rpca_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_OK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, RPCA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int lp_of(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : 128); }
+
+// Bump allocator over the context workspace.  plan() sizes, then carve().
+struct Arena {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    off = round_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+rpca_status ensure_ws(rpca_ctx ctx, size_t bytes) {
+  if (ctx->ws_limit && bytes > ctx->ws_limit)
+    return fail(ctx, RPCA_ERR_NO_MEMORY,
+                "workspace of " + std::to_string(bytes) + " bytes exceeds the limit of " +
+                    std::to_string(ctx->ws_limit));
+  if (bytes <= ctx->ws_bytes) return RPCA_OK;
+  if (ctx->ws) {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    HIP_OK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, RPCA_ERR_NO_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  ctx->ws = static_cast<char*>(p);
+  ctx->ws_bytes = bytes;
+  return RPCA_OK;
+}
+
+rpca_status ensure_counters(rpca_ctx ctx, size_t n) {
+  if (n <= ctx->counters_n) return RPCA_OK;
+  if (ctx->counters) {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    HIP_OK(hipFree(ctx->counters));
+    ctx->counters = nullptr;
+    ctx->counters_n = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, n * sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, RPCA_ERR_NO_MEMORY, "hipMalloc of LU counters failed");
+  }
+  HIP_OK(hipMemset(p, 0, n * sizeof(unsigned)));
+  ctx->counters = static_cast<unsigned*>(p);
+  ctx->counters_n = n;
+  return RPCA_OK;
+}
+
+hipEvent_t take_event(rpca_ctx ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Scratch shared by the steps of one solve.
+struct Work {
+  int l = 0, lp = 0, nb = 0;
+  int64_t rows_max = 0;
+  // tall buffers
+  float* Y = nullptr;     // m x lp
+  float* Z = nullptr;     // n x lp
+  float* Y2 = nullptr;    // m x lp (second tall buffer, Nystrom)
+  __bf16* Xp = nullptr;   // packed operand (max of both sides)
+  float* P = nullptr;     // A^T X partials
+  float* mu = nullptr;    // lp
+  double* colpart = nullptr;
+  double* colpart2 = nullptr;
+  double* gpart = nullptr;
+  double* G = nullptr;
+  float* Rf = nullptr;
+  double* Racc = nullptr;
+  int* cand = nullptr;
+  int* piv = nullptr;
+  float* Ulu = nullptr;
+  int* state = nullptr;
+  double* sv = nullptr;
+  double* Wacc = nullptr;
+  double* Xn = nullptr;
+  double* jwork = nullptr;
+  int* signwork = nullptr;
+  double* scal = nullptr;  // [0] fro2, [1] nu
+  float* nu_f = nullptr;
+  AtxPlan atx{};
+  LuPlan lu_m{}, lu_n{};
+};
+
+void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool need_y2) {
+  w.l = l;
+  w.lp = lp_of(l);
+  w.nb = w.lp / 32;
+  const int lp = w.lp;
+  const int64_t rmax = std::max(m, n);
+  w.rows_max = rmax;
+  w.Y = ar.take<float>((size_t)round_up(m, 32) * lp);
+  w.Z = ar.take<float>((size_t)round_up(n, 32) * lp);
+  if (need_y2) w.Y2 = ar.take<float>((size_t)round_up(m, 32) * lp);
+  const int64_t steps = 2 * ceil_div(rmax, 32);
+  w.Xp = ar.take<__bf16>(packed_bytes(steps, w.nb) / sizeof(__bf16));
+  w.atx = plan_atx(m, n, w.nb, num_cus);
+  w.P = ar.take<float>(w.atx.partial_bytes / sizeof(float));
+  w.mu = ar.take<float>(128);
+  w.colpart = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
+  w.colpart2 = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
+  w.gpart = ar.take<double>((size_t)gram_blocks(rmax) * lp * lp);
+  w.G = ar.take<double>((size_t)lp * lp);
+  w.Rf = ar.take<float>((size_t)lp * lp);
+  w.Racc = ar.take<double>((size_t)lp * lp);
+  w.lu_m = plan_lu(m, lp);
+  w.lu_n = plan_lu(n, lp);
+  w.cand = ar.take<int>((size_t)std::max(w.lu_m.cand_total, w.lu_n.cand_total));
+  w.piv = ar.take<int>(128);
+  w.Ulu = ar.take<float>((size_t)lp * lp);
+  w.state = ar.take<int>(16);
+  w.sv = ar.take<double>(128);
+  w.Wacc = ar.take<double>((size_t)lp * lp);
+  w.Xn = ar.take<double>((size_t)lp * lp);
+  w.jwork = ar.take<double>((size_t)2 * lp * lp);
+  w.signwork = ar.take<int>(sign_work_bytes(rmax) / sizeof(int) + 4);
+  w.scal = ar.take<double>(4);
+  w.nu_f = ar.take<float>(4);
+}
+
+rpca_status prepare(rpca_ctx ctx, Work& w, int64_t m, int64_t n, int l, bool need_y2) {
+  Arena probe;
+  layout(probe, w, m, n, l, ctx->num_cus, need_y2);
+  rpca_status s = ensure_ws(ctx, probe.off + 256);
+  if (s != RPCA_OK) return s;
+  s = ensure_counters(ctx, (size_t)std::max(w.lu_m.counter_total, w.lu_n.counter_total) + 16);
+  if (s != RPCA_OK) return s;
+  Arena real;
+  real.base = ctx->ws;
+  layout(real, w, m, n, l, ctx->num_cus, need_y2);
+  return RPCA_OK;
+}
+
+bool dense_f32(const rpca_matrix* A) {
+  return A->format == RPCA_DENSE_ROWMAJOR && A->dtype == RPCA_F32;
+}
+
+rpca_status check_matrix(rpca_ctx ctx, const rpca_matrix* A) {
+  if (!A) return fail(ctx, RPCA_ERR_INVALID_ARG, "A is null");
+  if (A->m <= 0 || A->n <= 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "A must have m, n >= 1");
+  if (A->format != RPCA_DENSE_ROWMAJOR)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "only dense row-major A is supported in this build");
+  if (A->dtype != RPCA_F32)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "only float32 A is supported in this build");
+  if (!A->data) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->data is null");
+  if (A->ld < A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->ld < n");
+  if (A->m > (int64_t)1 << 30 || A->n > (int64_t)1 << 30)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "dimensions above 2^30");
+  return RPCA_OK;
+}
+
+// ---- timed A-pass launches -------------------------------------------------
+void begin_timed(rpca_ctx ctx, TimedLaunch& t, int kind, double bytes) {
+  t.a = t.b = nullptr;
+  t.kind = kind;
+  t.bytes = bytes;
+  if (!ctx->timing) return;
+  t.a = take_event(ctx);
+  t.b = take_event(ctx);
+  if (t.a) (void)hipEventRecord(t.a, ctx->stream);
+}
+void end_timed(rpca_ctx ctx, TimedLaunch& t) {
+  if (!ctx->timing || !t.a || !t.b) return;
+  (void)hipEventRecord(t.b, ctx->stream);
+  ctx->pending.push_back(t);
+}
+
+void run_ax(rpca_ctx ctx, const rpca_matrix* A, const Work& w, const __bf16* Xp, float* Y) {
+  TimedLaunch t;
+  const double bytes = (double)A->m * A->n * 4.0 + (double)A->n * w.lp * 4.0 +
+                       (double)A->m * w.lp * 4.0;
+  begin_timed(ctx, t, 0, bytes);
+  launch_ax(ctx->stream, A->data, A->dtype, A->ld, A->m, A->n, Xp, Y, w.lp, w.nb);
+  end_timed(ctx, t);
+  ctx->stats.a_passes++;
+}
+
+void run_atx(rpca_ctx ctx, const rpca_matrix* A, const Work& w, const __bf16* Qp) {
+  TimedLaunch t;
+  const double bytes = (double)A->m * A->n * 4.0 + (double)A->m * w.lp * 4.0 +
+                       (double)w.atx.partial_bytes;
+  begin_timed(ctx, t, 1, bytes);
+  launch_atx(ctx->stream, A->data, A->dtype, A->ld, A->m, A->n, Qp, w.P, w.atx, w.nb);
+  end_timed(ctx, t);
+  ctx->stats.a_passes++;
+}
+
+// Y (rows x lp) <- P L with Y = P L U (tournament-pivoted LU), in place.
+void lu_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
+  const LuPlan plan = plan_lu(rows, w.lp);
+  launch_lu_tree(ctx->stream, Y, w.lp, rows, w.l, plan, w.cand, ctx->counters, w.Ulu, w.piv);
+  launch_trsm(ctx->stream, Y, w.lp, rows, w.l, w.lp, w.Ulu, w.piv, nullptr, nullptr, nullptr, 0);
+}
+
+// Y (rows x lp) <- Q with Y = Q R, Q orthonormal (Cholesky QR, float64 Gram,
+// shifted and completed when Y is numerically rank deficient).  With
+// ``Racc`` the product R is accumulated.
+void orth_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows, bool want_r, uint64_t seed) {
+  hipStream_t st = ctx->stream;
+  double* Racc = want_r ? w.Racc : nullptr;
+  for (int pass = 1; pass <= 4; ++pass) {
+    const int* skip = (pass >= 3) ? (w.state + 1) : nullptr;
+    launch_gram(st, Y, w.lp, rows, w.lp, nullptr, 0, w.gpart, w.G, skip);
+    launch_chol_qr_step(st, w.G, w.l, w.lp, pass, w.Rf, Racc, w.state);
+    launch_trsm(st, Y, w.lp, rows, w.l, w.lp, w.Rf, nullptr, skip, nullptr, nullptr, 0);
+    if (pass == 2) launch_complete(st, Y, w.lp, rows, w.l, w.state, seed ^ 0x5bd1e995u);
+  }
+}
+
+void center_rows(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
+  launch_colmean(ctx->stream, Y, w.lp, rows, w.l, w.colpart, 0, w.mu);
+  launch_sub_rowvec(ctx->stream, Y, w.lp, rows, w.l, w.mu);
+}
+
+// Q (m side) -> packed operand for A^T Q; centered when asked (A_c^T Q = A^T (Q - 1 qbar)).
+void pack_m_side(rpca_ctx ctx, Work& w, const float* Q, int64_t m, bool center) {
+  const float* mu = nullptr;
+  if (center) {
+    launch_colmean(ctx->stream, Q, w.lp, m, w.l, w.colpart, 0, w.mu);
+    mu = w.mu;
+  }
+  launch_pack(ctx->stream, Q, w.lp, m, w.l, w.nb, mu, nullptr, w.Xp, 2 * ceil_div(m, 32));
+}
+
+void pack_n_side(rpca_ctx ctx, Work& w, const float* X, int64_t n) {
+  launch_pack(ctx->stream, X, w.lp, n, w.l, w.nb, nullptr, nullptr, w.Xp, 2 * ceil_div(n, 32));
+}
+
+void apply_at(rpca_ctx ctx, const rpca_matrix* A, Work& w, float* Z) {
+  run_atx(ctx, A, w, w.Xp);
+  launch_atx_reduce(ctx->stream, w.P, w.atx, w.nb, A->n, nullptr, Z, w.lp);
+}
+
+rpca_status check_kl(rpca_ctx ctx, int k, int& l, int64_t m, int64_t n) {
+  if (l <= 0) l = k + 2;
+  if (k < 1) return fail(ctx, RPCA_ERR_INVALID_ARG, "k must be >= 1");
+  if (k > l) return fail(ctx, RPCA_ERR_INVALID_ARG, "k must be <= l");
+  if (l > std::min(m, n)) return fail(ctx, RPCA_ERR_INVALID_ARG, "l must be <= min(m, n)");
+  if (l > 128) return fail(ctx, RPCA_ERR_UNSUPPORTED, "l above 128 is not supported");
+  return RPCA_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* rpca_status_str(rpca_status s) {
+  switch (s) {
+    case RPCA_OK: return "ok";
+    case RPCA_ERR_INVALID_ARG: return "invalid argument";
+    case RPCA_ERR_UNSUPPORTED: return "unsupported";
+    case RPCA_ERR_NO_MEMORY: return "out of memory";
+    case RPCA_ERR_HIP: return "HIP error";
+    case RPCA_ERR_NOT_PSD: return "matrix not positive semidefinite";
+    case RPCA_ERR_NUMERICAL: return "non-finite values";
+  }
+  return "unknown status";
+}
+
+const char* rpca_last_error(rpca_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+rpca_status rpca_create(rpca_ctx* out, void* hip_stream) {
+  if (!out) return RPCA_ERR_INVALID_ARG;
+  *out = nullptr;
+  rpca_ctx ctx = new (std::nothrow) rpca_ctx_s();
+  if (!ctx) return RPCA_ERR_NO_MEMORY;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return RPCA_ERR_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->num_cus = prop.multiProcessorCount;
+  void* hs = nullptr;
+  if (hipHostMalloc(&hs, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return RPCA_ERR_HIP;
+  }
+  ctx->host_state = static_cast<int*>(hs);
+  *out = ctx;
+  return RPCA_OK;
+}
+
+rpca_status rpca_destroy(rpca_ctx ctx) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& t : ctx->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->counters) (void)hipFree(ctx->counters);
+  if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+  delete ctx;
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_stream(rpca_ctx ctx, void* hip_stream) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (ctx->stream != static_cast<hipStream_t>(hip_stream)) {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  }
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_workspace_limit(rpca_ctx ctx, size_t bytes) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  ctx->ws_limit = bytes;
+  return RPCA_OK;
+}
+
+rpca_status rpca_workspace_size(rpca_ctx ctx, const rpca_matrix* A, int k, int l, size_t* bytes) {
+  if (!ctx || !bytes) return fail(ctx, RPCA_ERR_INVALID_ARG, "null argument");
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  s = check_kl(ctx, k, l, A->m, A->n);
+  if (s != RPCA_OK) return s;
+  Work w;
+  Arena probe;
+  layout(probe, w, A->m, A->n, l, ctx->num_cus, true);
+  *bytes = probe.off + 256;
+  return RPCA_OK;
+}
+
+rpca_status rpca_gaussian(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
+                          float* out, int64_t ldo, uint32_t* words_out) {
+  if (!ctx || !out || n < 0 || l < 0 || ldo < l) return fail(ctx, RPCA_ERR_INVALID_ARG, "bad arguments");
+  launch_gaussian(ctx->stream, seed, stream, n, l, out, ldo, words_out);
+  HIP_OK(hipGetLastError());
+  return RPCA_OK;
+}
+
+rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
+                     unsigned flags, float* U, int64_t ldu, double* S, float* V, int64_t ldv) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  s = check_kl(ctx, k, l, A->m, A->n);
+  if (s != RPCA_OK) return s;
+  if (its < 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "its must be >= 0");
+  if (!U || !S || !V) return fail(ctx, RPCA_ERR_INVALID_ARG, "null output");
+  if (ldu < k || ldv < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu/ldv must be >= k");
+  const int64_t m = A->m, n = A->n;
+  const bool center = (flags & RPCA_CENTER) != 0;
+  Work w;
+  s = prepare(ctx, w, m, n, l, false);
+  if (s != RPCA_OK) return s;
+  hipStream_t st = ctx->stream;
+  ctx->stats.calls++;
+
+  // Omega (n x l, zero padded to lp) -> packed right operand
+  HIP_OK(hipMemsetAsync(w.Z, 0, (size_t)n * w.lp * sizeof(float), st));
+  launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
+  pack_n_side(ctx, w, w.Z, n);
+  // Y = A Omega
+  run_ax(ctx, A, w, w.Xp, w.Y);
+  if (center) center_rows(ctx, w, w.Y, m);
+  if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
+  else lu_renorm(ctx, w, w.Y, m);
+  for (int it = 1; it <= its; ++it) {
+    // Z = A^T Q, renormalized by LU
+    pack_m_side(ctx, w, w.Y, m, center);
+    apply_at(ctx, A, w, w.Z);
+    lu_renorm(ctx, w, w.Z, n);
+    // Y = A Q; LU except after the last application, which is orthonormalized
+    pack_n_side(ctx, w, w.Z, n);
+    run_ax(ctx, A, w, w.Xp, w.Y);
+    if (center) center_rows(ctx, w, w.Y, m);
+    if (it < its) lu_renorm(ctx, w, w.Y, m);
+    else orth_renorm(ctx, w, w.Y, m, false, seed);
+  }
+  // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
+  pack_m_side(ctx, w, w.Y, m, center);
+  apply_at(ctx, A, w, w.Z);
+  orth_renorm(ctx, w, w.Z, n, true, seed + 1);
+  launch_jacobi_svd(st, w.Racc, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
+  // U = Q W, V = Q2 X, S = top k
+  launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu);
+  launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv);
+  launch_finish_values(st, w.sv, k, nullptr, S);
+  launch_sign_fix(st, U, ldu, m, k, V, ldv, n, w.signwork);
+  HIP_OK(hipGetLastError());
+  if (flags & RPCA_SYNC) HIP_OK(hipStreamSynchronize(st));
+  return RPCA_OK;
+}
+
+rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
+                         unsigned flags, float* U, int64_t ldu, double* lambda) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  if (A->m != A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "eig_psd needs a square matrix");
+  s = check_kl(ctx, k, l, A->m, A->n);
+  if (s != RPCA_OK) return s;
+  if (its < 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "its must be >= 0");
+  if (!U || !lambda) return fail(ctx, RPCA_ERR_INVALID_ARG, "null output");
+  if (ldu < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu must be >= k");
+  if (flags & RPCA_CENTER) return fail(ctx, RPCA_ERR_INVALID_ARG, "centering does not apply to eig_psd");
+  const int64_t n = A->n;
+  Work w;
+  s = prepare(ctx, w, n, n, l, true);
+  if (s != RPCA_OK) return s;
+  hipStream_t st = ctx->stream;
+  ctx->stats.calls++;
+
+  // Q = Omega; its times Q = A Q renormalized (LU, QR after the last).
+  HIP_OK(hipMemsetAsync(w.Y, 0, (size_t)n * w.lp * sizeof(float), st));
+  launch_gaussian(st, seed, 0u, n, l, w.Y, w.lp, nullptr);
+  if (its == 0) orth_renorm(ctx, w, w.Y, n, false, seed);
+  for (int it = 1; it <= its; ++it) {
+    pack_n_side(ctx, w, w.Y, n);
+    run_ax(ctx, A, w, w.Xp, w.Y);
+    if (it < its) lu_renorm(ctx, w, w.Y, n);
+    else orth_renorm(ctx, w, w.Y, n, false, seed);
+  }
+  // B1 = A Q (start); B2 = Q* B1 (second), shifted; C = chol (Cholesky)
+  pack_n_side(ctx, w, w.Y, n);
+  run_ax(ctx, A, w, w.Xp, w.Y2);
+  launch_fro2_d(st, w.Y2, w.lp, n, l, w.colpart, w.colpart2, w.scal);
+  launch_gram(st, w.Y, w.lp, n, w.lp, w.Y2, w.lp, w.gpart, w.G, nullptr);
+  const double u = std::ldexp(1.0, -24);
+  launch_chol_nystrom(st, w.G, l, w.lp, w.scal, std::sqrt((double)n) * u, w.Rf, w.scal + 1,
+                      w.nu_f, w.state, 10);
+  // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
+  launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp);
+  orth_renorm(ctx, w, w.Y2, n, true, seed + 1);
+  launch_jacobi_svd(st, w.Racc, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork);
+  launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu);
+  launch_finish_values(st, w.sv, k, w.scal + 1, lambda);
+  launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
+  HIP_OK(hipGetLastError());
+  // the Cholesky retry outcome decides the status
+  HIP_OK(hipMemcpyAsync(ctx->host_state, w.state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  ctx->stats.shift_retries = ctx->host_state[3];
+  if (ctx->host_state[4])
+    return fail(ctx, RPCA_ERR_NOT_PSD, "shifted B2 = Q*(A + nu I)Q not positive definite after retries");
+  return RPCA_OK;
+}
+
+rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const float* U,
+                              int64_t ldu, const double* S, const float* V, int64_t ldv, int iters,
+                              uint64_t seed, unsigned flags, double* err_host) {
+  (void)A; (void)k; (void)U; (void)ldu; (void)S; (void)V; (void)ldv; (void)iters; (void)seed;
+  (void)flags; (void)err_host;
+  return fail(ctx, RPCA_ERR_UNSUPPORTED, "spectral_err is not built yet");
+}
+
+rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l, const float* X,
+                           int64_t ldx, float* Y, int64_t ldy, unsigned flags) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  if (l < 1 || l > 128) return fail(ctx, RPCA_ERR_INVALID_ARG, "1 <= l <= 128");
+  if (!X || !Y) return fail(ctx, RPCA_ERR_INVALID_ARG, "null operand");
+  const int64_t m = A->m, n = A->n;
+  const int64_t xr = trans ? m : n, yr = trans ? n : m;
+  if (ldx < l || ldy < l) return fail(ctx, RPCA_ERR_INVALID_ARG, "ld < l");
+  const bool center = (flags & RPCA_CENTER) != 0;
+  Work w;
+  s = prepare(ctx, w, m, n, l, false);
+  if (s != RPCA_OK) return s;
+  hipStream_t st = ctx->stream;
+  // copy X into the lp-padded tall buffer
+  float* Xt = trans ? w.Y : w.Z;
+  HIP_OK(hipMemsetAsync(Xt, 0, (size_t)xr * w.lp * sizeof(float), st));
+  HIP_OK(hipMemcpy2DAsync(Xt, w.lp * sizeof(float), X, ldx * sizeof(float), l * sizeof(float), xr,
+                          hipMemcpyDeviceToDevice, st));
+  float* Yt = trans ? w.Z : w.Y;
+  if (trans) {
+    pack_m_side(ctx, w, Xt, m, center);
+    apply_at(ctx, A, w, Yt);
+  } else {
+    pack_n_side(ctx, w, Xt, n);
+    run_ax(ctx, A, w, w.Xp, Yt);
+    if (center) center_rows(ctx, w, Yt, m);
+  }
+  HIP_OK(hipMemcpy2DAsync(Y, ldy * sizeof(float), Yt, w.lp * sizeof(float), l * sizeof(float), yr,
+                          hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipGetLastError());
+  if (flags & RPCA_SYNC) HIP_OK(hipStreamSynchronize(st));
+  return RPCA_OK;
+}
+
+rpca_status rpca_op_renorm(rpca_ctx ctx, int kind, int64_t rows, int l, float* Y, int64_t ldy,
+                           int32_t* piv, double* R) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (!Y || rows < l || l < 1 || l > 128 || ldy < l)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "bad renorm arguments");
+  if (kind != 0 && kind != 1) return fail(ctx, RPCA_ERR_INVALID_ARG, "kind must be 0 or 1");
+  Work w;
+  rpca_status s = prepare(ctx, w, rows, l, l, false);
+  if (s != RPCA_OK) return s;
+  hipStream_t st = ctx->stream;
+  HIP_OK(hipMemsetAsync(w.Y, 0, (size_t)rows * w.lp * sizeof(float), st));
+  HIP_OK(hipMemcpy2DAsync(w.Y, w.lp * sizeof(float), Y, ldy * sizeof(float), l * sizeof(float),
+                          rows, hipMemcpyDeviceToDevice, st));
+  if (kind == 0) {
+    lu_renorm(ctx, w, w.Y, rows);
+    if (piv) HIP_OK(hipMemcpyAsync(piv, w.piv, l * sizeof(int), hipMemcpyDeviceToDevice, st));
+  } else {
+    orth_renorm(ctx, w, w.Y, rows, R != nullptr, 12345u);
+    if (R)
+      HIP_OK(hipMemcpy2DAsync(R, l * sizeof(double), w.Racc, w.lp * sizeof(double),
+                              l * sizeof(double), l, hipMemcpyDeviceToDevice, st));
+  }
+  HIP_OK(hipMemcpy2DAsync(Y, ldy * sizeof(float), w.Y, w.lp * sizeof(float), l * sizeof(float),
+                          rows, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipGetLastError());
+  return RPCA_OK;
+}
+
+rpca_status rpca_op_small_svd(rpca_ctx ctx, int l, const double* M, double* s, double* W,
+                              double* X) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (l < 1 || l > 128 || !M || !s || !W || !X) return fail(ctx, RPCA_ERR_INVALID_ARG, "bad arguments");
+  Work w;
+  rpca_status st_ = prepare(ctx, w, l, l, l, false);
+  if (st_ != RPCA_OK) return st_;
+  hipStream_t st = ctx->stream;
+  HIP_OK(hipMemsetAsync(w.G, 0, (size_t)w.lp * w.lp * sizeof(double), st));
+  HIP_OK(hipMemcpy2DAsync(w.G, w.lp * sizeof(double), M, l * sizeof(double), l * sizeof(double), l,
+                          hipMemcpyDeviceToDevice, st));
+  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
+  HIP_OK(hipMemcpyAsync(s, w.sv, l * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // M = Xn diag(s) Wacc^T: left vectors Xn, right vectors Wacc
+  HIP_OK(hipMemcpy2DAsync(W, l * sizeof(double), w.Xn, w.lp * sizeof(double), l * sizeof(double), l,
+                          hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipMemcpy2DAsync(X, l * sizeof(double), w.Wacc, w.lp * sizeof(double), l * sizeof(double),
+                          l, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipGetLastError());
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_timing(rpca_ctx ctx, int enable) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  return RPCA_OK;
+}
+
+rpca_status rpca_get_stats(rpca_ctx ctx, rpca_stats* out) {
+  if (!ctx || !out) return RPCA_ERR_INVALID_ARG;
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  for (auto& t : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      if (t.kind == 0) {
+        ctx->stats.ms_ax += ms;
+        ctx->stats.n_ax++;
+        ctx->stats.bytes_ax += t.bytes;
+      } else {
+        ctx->stats.ms_atx += ms;
+        ctx->stats.n_atx++;
+        ctx->stats.bytes_atx += t.bytes;
+      }
+      ctx->stats.timed_launches++;
+    }
+    ctx->event_pool.push_back(t.a);
+    ctx->event_pool.push_back(t.b);
+  }
+  ctx->pending.clear();
+  *out = ctx->stats;
+  return RPCA_OK;
+}
+
+rpca_status rpca_reset_stats(rpca_ctx ctx) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_stats tmp;
+  rpca_status s = rpca_get_stats(ctx, &tmp);
+  ctx->stats = rpca_stats{};
+  return s;
+}
+
+}  // extern "C"

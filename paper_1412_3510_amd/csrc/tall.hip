@@ -1,0 +1,381 @@
+// Kernels on tall-skinny float32 matrices (rows x lp, lp = 32, 64 or 128,
+// padding columns zero): column statistics for centering, the float64 Gram
+// matrix for Cholesky QR, the right triangular solve shared by the LU and
+// Cholesky-QR renormalizations and the Nystrom F = B1 C^-1, and the small
+// products U = Q W of the final step.
+#include "common.h"
+#include "kernels.h"
+
+namespace rpca {
+
+// ------------------------------------------------------------------------
+// column sums and sums of squares, float64 partials per row chunk
+// ------------------------------------------------------------------------
+static constexpr int kColChunk = 512;
+
+int colmean_blocks(int64_t rows) { return (int)ceil_div(rows > 0 ? rows : 1, kColChunk); }
+
+__global__ void __launch_bounds__(256) colstats_kernel(const float* __restrict__ X, int64_t ldx,
+                                                       int64_t rows, int cols,
+                                                       double* __restrict__ psum,
+                                                       double* __restrict__ psq) {
+  // thread -> (column c, row phase); 256 threads cover 256/ cpw columns
+  const int cpw = (cols <= 32) ? 32 : (cols <= 64 ? 64 : 128);
+  const int ph = 256 / cpw;
+  const int c = threadIdx.x % cpw, p = threadIdx.x / cpw;
+  const int64_t r0 = (int64_t)blockIdx.x * kColChunk;
+  double s = 0.0, q = 0.0;
+  if (c < cols) {
+    for (int64_t r = r0 + p; r < r0 + kColChunk && r < rows; r += ph) {
+      const double v = X[r * ldx + c];
+      s += v;
+      q += v * v;
+    }
+  }
+  __shared__ double ss[256], sq[256];
+  ss[threadIdx.x] = s;
+  sq[threadIdx.x] = q;
+  __syncthreads();
+  if (p == 0 && c < cols) {
+    for (int k = 1; k < ph; ++k) {
+      s += ss[k * cpw + c];
+      q += sq[k * cpw + c];
+    }
+    psum[(int64_t)blockIdx.x * 128 + c] = s;
+    if (psq) psq[(int64_t)blockIdx.x * 128 + c] = q;
+  }
+}
+
+__global__ void colmean_final_kernel(const double* __restrict__ psum, int nblk, int64_t rows,
+                                     int cols, float* __restrict__ mu) {
+  const int c = threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += psum[(int64_t)b * 128 + c];
+  mu[c] = (float)(s / (double)rows);
+}
+
+void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
+                    double* partial, int nblk_max, float* mu) {
+  const int nblk = colmean_blocks(rows);
+  (void)nblk_max;
+  hipLaunchKernelGGL(colstats_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, rows, cols, partial,
+                     (double*)nullptr);
+  hipLaunchKernelGGL(colmean_final_kernel, dim3(1), dim3(128), 0, st, partial, nblk, rows, cols, mu);
+}
+
+__global__ void __launch_bounds__(256) sub_rowvec_kernel(float* __restrict__ X, int64_t ldx,
+                                                         int64_t rows, int cols,
+                                                         const float* __restrict__ mu) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = e / cols;
+  const int c = (int)(e % cols);
+  if (r < rows) X[r * ldx + c] -= mu[c];
+}
+
+void launch_sub_rowvec(hipStream_t st, float* X, int64_t ldx, int64_t rows, int cols,
+                       const float* mu) {
+  const int64_t total = rows * cols;
+  if (total == 0) return;
+  hipLaunchKernelGGL(sub_rowvec_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, X,
+                     ldx, rows, cols, mu);
+}
+
+// sum of squares of all entries (float64) -> single value fro2[0]
+__global__ void fro2_final_kernel(const double* __restrict__ psq, int nblk, int cols,
+                                  double* __restrict__ fro2) {
+  __shared__ double sh[128];
+  const int c = threadIdx.x;
+  double s = 0.0;
+  if (c < cols)
+    for (int b = 0; b < nblk; ++b) s += psq[(int64_t)b * 128 + c];
+  sh[c] = s;
+  __syncthreads();
+  if (c == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 128; ++i) t += sh[i];
+    fro2[0] = t;
+  }
+}
+
+void launch_fro2_d(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
+                   double* psum, double* psq, double* fro2) {
+  const int nblk = colmean_blocks(rows);
+  hipLaunchKernelGGL(colstats_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, rows, cols, psum, psq);
+  hipLaunchKernelGGL(fro2_final_kernel, dim3(1), dim3(128), 0, st, psq, nblk, cols, fro2);
+}
+
+// ------------------------------------------------------------------------
+// Gram matrix G = X^T X2 in float64 (X2 = X when null).  Each workgroup
+// accumulates a 256-row block; a 16 x 16 grid of threads owns T x T tiles of
+// the lp x lp result (T = lp / 16).  Rows are staged in LDS 32 at a time.
+// ------------------------------------------------------------------------
+static constexpr int kGramRows = 256;
+
+int gram_blocks(int64_t rows) { return (int)ceil_div(rows > 0 ? rows : 1, kGramRows); }
+
+template <int LP>
+__global__ void __launch_bounds__(256) gram_kernel(const float* __restrict__ X, int64_t ldx,
+                                                   const float* __restrict__ X2, int64_t ldx2,
+                                                   int64_t rows, double* __restrict__ partial,
+                                                   const int* __restrict__ skip_flag) {
+  if (skip_flag && *skip_flag == 0) return;
+  constexpr int T = LP / 16;
+  __shared__ float sa[32][LP];
+  __shared__ float sb[32][LP];
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+  double acc[T][T];
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
+  const bool same = (X2 == nullptr);
+  for (int64_t rc = r0; rc < r0 + kGramRows && rc < rows; rc += 32) {
+    for (int e = tid; e < 32 * LP; e += 256) {
+      const int rr = e / LP, c = e % LP;
+      const int64_t r = rc + rr;
+      sa[rr][c] = (r < rows) ? X[r * ldx + c] : 0.f;
+      if (!same) sb[rr][c] = (r < rows) ? X2[r * ldx2 + c] : 0.f;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 32; ++rr) {
+      double a[T], b[T];
+#pragma unroll
+      for (int u = 0; u < T; ++u) {
+        a[u] = sa[rr][ti * T + u];
+        b[u] = same ? sa[rr][tj * T + u] : sb[rr][tj * T + u];
+      }
+#pragma unroll
+      for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.x * LP * LP;
+#pragma unroll
+  for (int u = 0; u < T; ++u)
+#pragma unroll
+    for (int v = 0; v < T; ++v) out[(ti * T + u) * LP + tj * T + v] = acc[u][v];
+}
+
+__global__ void __launch_bounds__(256) gram_reduce_kernel(const double* __restrict__ partial,
+                                                          int nblk, int lp2,
+                                                          double* __restrict__ G,
+                                                          const int* __restrict__ skip_flag) {
+  if (skip_flag && *skip_flag == 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= lp2) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * lp2 + e];
+  G[e] = s;
+}
+
+void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int lp,
+                 const float* X2, int64_t ldx2, double* partial, double* G,
+                 const int* skip_flag) {
+  const int nblk = gram_blocks(rows);
+  switch (lp) {
+    case 32: hipLaunchKernelGGL(gram_kernel<32>, dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2, rows, partial, skip_flag); break;
+    case 64: hipLaunchKernelGGL(gram_kernel<64>, dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2, rows, partial, skip_flag); break;
+    case 128: hipLaunchKernelGGL(gram_kernel<128>, dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2, rows, partial, skip_flag); break;
+    default: return;
+  }
+  const int lp2 = lp * lp;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div(lp2, 256)), dim3(256), 0, st,
+                     partial, nblk, lp2, G, skip_flag);
+}
+
+// ------------------------------------------------------------------------
+// In-place right triangular solve X <- (X + nu * addX) U^-1, U upper
+// triangular float32 (lp x lp, row-major).  A zero diagonal U[j][j] marks a
+// zero pivot of the LU renormalization: column j of the result is then the
+// unit vector of the pivot row piv[j] (LAPACK getrf leaves L's column as
+// e_j when the pivot is zero).  A nonzero *skip_flag == 0 skips the launch's
+// work (conditional third Cholesky-QR pass).  One thread per row.
+// ------------------------------------------------------------------------
+template <int LP>
+__global__ void __launch_bounds__(256) trsm_kernel(float* __restrict__ X, int64_t ldx, int64_t rows,
+                                                   int l, const float* __restrict__ Ut,
+                                                   const int* __restrict__ piv,
+                                                   const int* __restrict__ skip_flag,
+                                                   const float* __restrict__ nu,
+                                                   const float* __restrict__ addX, int64_t ldadd) {
+  if (skip_flag && *skip_flag == 0) return;
+  __shared__ float sU[LP * LP];
+  __shared__ float sd[LP];
+  __shared__ int sp[LP];
+  for (int e = threadIdx.x; e < LP * LP; e += 256) sU[e] = Ut[e];
+  if (threadIdx.x < LP) {
+    const int j = threadIdx.x;
+    const float d = (j < l) ? Ut[j * LP + j] : 0.f;
+    sd[j] = (d != 0.f) ? 1.0f / d : 0.f;
+    sp[j] = (piv && j < l) ? piv[j] : -1;
+  }
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= rows) return;
+  float x[LP];
+  const float* src = X + row * ldx;
+#pragma unroll
+  for (int c = 0; c < LP; c += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src + c);
+    x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
+  }
+  if (addX) {
+    const float s = *nu;
+    const float* a = addX + row * ldadd;
+#pragma unroll
+    for (int c = 0; c < LP; c += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(a + c);
+      x[c] += s * v.x; x[c + 1] += s * v.y; x[c + 2] += s * v.z; x[c + 3] += s * v.w;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < LP; ++j) {
+    if (j < l) {
+      float s = x[j];
+#pragma unroll
+      for (int i = 0; i < j; ++i) s -= x[i] * sU[i * LP + j];
+      const float d = sd[j];
+      x[j] = (d != 0.f) ? s * d : ((row == sp[j]) ? 1.f : 0.f);
+    } else {
+      x[j] = 0.f;
+    }
+  }
+  float* dst = X + row * ldx;
+#pragma unroll
+  for (int c = 0; c < LP; c += 4)
+    *reinterpret_cast<float4*>(dst + c) = make_float4(x[c], x[c + 1], x[c + 2], x[c + 3]);
+}
+
+void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int lp,
+                 const float* Ut, const int* piv, const int* skip_flag, const float* nu,
+                 const float* addX, int64_t ldadd) {
+  if (rows == 0) return;
+  const dim3 grid((unsigned)ceil_div(rows, 256));
+  switch (lp) {
+    case 32: hipLaunchKernelGGL(trsm_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
+    case 64: hipLaunchKernelGGL(trsm_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
+    case 128: hipLaunchKernelGGL(trsm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Y (rows x k) = X (rows x lp) W (lp x k), W float64 rounded to float32 in
+// LDS.  One thread per row.
+// ------------------------------------------------------------------------
+template <int LP>
+__global__ void __launch_bounds__(256) small_gemm_kernel(const float* __restrict__ X, int64_t ldx,
+                                                         int64_t rows, int l,
+                                                         const double* __restrict__ W, int ldw,
+                                                         int k, float* __restrict__ Y,
+                                                         int64_t ldy) {
+  __shared__ float sW[LP * LP];
+  for (int e = threadIdx.x; e < LP * k; e += 256) {
+    const int i = e / k, c = e % k;
+    sW[i * LP + c] = (i < l) ? (float)W[i * ldw + c] : 0.f;
+  }
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= rows) return;
+  float x[LP];
+  const float* src = X + row * ldx;
+#pragma unroll
+  for (int c = 0; c < LP; c += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src + c);
+    x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
+  }
+  for (int c = 0; c < k; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < LP; ++i) s += x[i] * sW[i * LP + c];
+    Y[row * ldy + c] = s;
+  }
+}
+
+void launch_small_gemm(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,
+                       const double* W, int ldw, int k, float* Y, int64_t ldy) {
+  if (rows == 0) return;
+  const dim3 grid((unsigned)ceil_div(rows, 256));
+  const int lp = (int)ldx;  // X is stored with ld = lp
+  switch (lp) {
+    case 32: hipLaunchKernelGGL(small_gemm_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy); break;
+    case 64: hipLaunchKernelGGL(small_gemm_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy); break;
+    case 128: hipLaunchKernelGGL(small_gemm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Sign convention for the output: the largest-|.| entry of each column of U
+// is made positive (ties go to the smallest row index); V's column follows.
+// ------------------------------------------------------------------------
+static constexpr int kSignChunk = 512;
+
+__global__ void __launch_bounds__(128) colabsmax_kernel(const float* __restrict__ U, int64_t ldu,
+                                                        int64_t m, int k, float* __restrict__ pval,
+                                                        int64_t* __restrict__ pidx) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  const int64_t r0 = (int64_t)blockIdx.x * kSignChunk;
+  float best = -1.f, bval = 0.f;
+  int64_t bidx = -1;
+  for (int64_t r = r0; r < r0 + kSignChunk && r < m; ++r) {
+    const float v = U[r * ldu + c];
+    if (fabsf(v) > best) {
+      best = fabsf(v);
+      bval = v;
+      bidx = r;
+    }
+  }
+  pval[(int64_t)blockIdx.x * 128 + c] = (bidx >= 0) ? bval : 0.f;
+  pidx[(int64_t)blockIdx.x * 128 + c] = bidx;
+}
+
+__global__ void sign_final_kernel(const float* __restrict__ pval, const int64_t* __restrict__ pidx,
+                                  int nblk, int k, float* __restrict__ sgn) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  float best = -1.f, bval = 0.f;
+  for (int b = 0; b < nblk; ++b) {  // blocks in row order: strict > keeps the first maximum
+    const float v = pval[(int64_t)b * 128 + c];
+    if (pidx[(int64_t)b * 128 + c] >= 0 && fabsf(v) > best) {
+      best = fabsf(v);
+      bval = v;
+    }
+  }
+  sgn[c] = (bval < 0.f) ? -1.f : 1.f;
+}
+
+__global__ void __launch_bounds__(256) flip_kernel(float* __restrict__ X, int64_t ldx, int64_t rows,
+                                                   int k, const float* __restrict__ sgn) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = e / k;
+  const int c = (int)(e % k);
+  if (r < rows && sgn[c] < 0.f) X[r * ldx + c] = -X[r * ldx + c];
+}
+
+size_t sign_work_bytes(int64_t m) {
+  const int nblk = (int)ceil_div(m > 0 ? m : 1, kSignChunk);
+  return (size_t)nblk * 128 * (sizeof(float) + sizeof(int64_t)) + 128 * sizeof(float);
+}
+
+void launch_sign_fix(hipStream_t st, float* U, int64_t ldu, int64_t m, int k, float* V,
+                     int64_t ldv, int64_t n, int* work) {
+  const int nblk = (int)ceil_div(m > 0 ? m : 1, kSignChunk);
+  float* pval = reinterpret_cast<float*>(work);
+  int64_t* pidx = reinterpret_cast<int64_t*>(pval + (size_t)nblk * 128 + ((nblk * 128) & 1));
+  float* sgn = reinterpret_cast<float*>(pidx + (size_t)nblk * 128);
+  hipLaunchKernelGGL(colabsmax_kernel, dim3(nblk), dim3(128), 0, st, U, ldu, m, k, pval, pidx);
+  hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(128), 0, st, pval, pidx, nblk, k, sgn);
+  hipLaunchKernelGGL(flip_kernel, dim3((unsigned)ceil_div(m * k, 256)), dim3(256), 0, st, U, ldu,
+                     m, k, sgn);
+  if (V)
+    hipLaunchKernelGGL(flip_kernel, dim3((unsigned)ceil_div(n * k, 256)), dim3(256), 0, st, V, ldv,
+                       n, k, sgn);
+}
+
+}  // namespace rpca
