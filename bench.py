@@ -1,0 +1,180 @@
+"""Benchmark: rank-k PCA solves/s on one MI355X, plus HBM GB/s per pass over A.
+
+Workload (one step = one whole solve): dense float32 A of 100000 x 4000 built
+as U diag(sigma) V^T with Haar U, V and sigma_j = 1/j (j <= 50), then
+1e-3 exp(-(j-51)/200); PCA of the column-centered matrix with k = 50,
+l = 60, its = 2 (six passes over A).  A is generated on the device and is
+resident in HBM before timing starts.
+
+Prints one JSON line.  ``roofline`` is for the dominant kernel (the product
+pass that takes the most time): algorithmic bytes per launch divided by the
+average launch duration, measured with HIP events recorded by the library on
+its stream over the timed region.  ``cpu_baseline`` times the FP64 oracle on
+this host's cores on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "rank-k PCA solves/s + HBM GB/s per A-pass; BF16 vs FP32 at err≤1.1·σ_{k+1}"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--m", type=int, default=100000)
+    p.add_argument("--n", type=int, default=4000)
+    p.add_argument("--k", type=int, default=50)
+    p.add_argument("--l", type=int, default=60)
+    p.add_argument("--its", type=int, default=2)
+    p.add_argument("--seed", type=int, default=2002)
+    p.add_argument("--no-cpu-baseline", action="store_true",
+                   help="skip the oracle leg (profiling runs)")
+    p.add_argument("--cpu-sample-solves", type=int, default=2)
+    p.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
+                   help="HBM bytes per launch measured by rocprofv3 counters")
+    return p.parse_args()
+
+
+def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
+    """Time the FP64 oracle on the host: ``nsolves`` whole solves of the same A."""
+    from oracle import philox, rsvd
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()
+                       if d.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    A = A_gpu.cpu().numpy()
+    n = A.shape[1]
+    om = philox.omega(seed, n, l)
+    times = []
+    S0 = None
+    for _ in range(nsolves):
+        t0 = time.perf_counter()
+        _, S0, _ = rsvd.rsvd(A, k, l, its, om, center=center)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    rel = float(np.max(np.abs(S_gpu - S0) / S0))
+    return {"value": 1.0 / med, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d whole solves of the same %dx%d centered workload (float64, "
+                      "NumPy/OpenBLAS), median %.2f s" % (nsolves, A.shape[0], n, med)}, rel
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1412_3510_amd as rp
+    from synth import dense
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m, n, k, l, its = args.m, args.n, args.k, args.l, args.its
+    sigma = dense.spectrum_tall(min(m, n))
+    t0 = time.perf_counter()
+    A, _, csig = dense.dense_torch(m, n, sigma, seed=1002, device=dev, center_spectrum=True)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    print("generated A %dx%d in %.1f s" % (m, n, gen_s), file=sys.stderr, flush=True)
+
+    ctx = rp.Context()
+    U = torch.empty(m, k, device=dev, dtype=torch.float32)
+    S = torch.empty(k, device=dev, dtype=torch.float64)
+    V = torch.empty(n, k, device=dev, dtype=torch.float32)
+    mat = rp.dense(A)
+    for _ in range(args.warmup):
+        ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat)
+    torch.cuda.synchronize()
+    print("warmup done", file=sys.stderr, flush=True)
+
+    ctx.reset_stats()
+    ctx.set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.set_timing(False)
+    ms_total = e0.elapsed_time(e1)
+    st = ctx.stats()
+    ms_per_step = ms_total / args.steps
+    print("timed %d solves: %.3f ms/solve (wall %.3f ms)" % (args.steps, ms_per_step,
+                                                             1e3 * wall / args.steps),
+          file=sys.stderr, flush=True)
+
+    kernels = {}
+    if st["n_ax"]:
+        kernels["ax"] = (st["ms_ax"] / st["n_ax"], st["bytes_ax"] / st["n_ax"], st["ms_ax"])
+    if st["n_atx"]:
+        kernels["atx"] = (st["ms_atx"] / st["n_atx"], st["bytes_atx"] / st["n_atx"], st["ms_atx"])
+    dom = max(kernels, key=lambda q: kernels[q][2])
+    avg_ms, bytes_per, _ = kernels[dom]
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        ent = tj.get(dom)
+        if ent and ent.get("m") == m and ent.get("n") == n and ent.get("l") == l:
+            traffic = ent.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": {"ax": "ax_f32_kernel (Y = A X)",
+                           "atx": "atx_f32_kernel (A^T X split-K)"}[dom],
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes": bytes_per}
+    passes = {q: {"avg_ms": round(v[0], 4), "GB/s": round(v[1] / (v[0] * 1e-3) / 1e9, 1)}
+              for q, v in kernels.items()}
+
+    S_host = S.cpu().numpy()
+    out = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (products as 3 bf16 MFMA terms, f32 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "dense %dx%d float32, centered, sigma_j=1/j (j<=50) then "
+                               "1e-3*exp(-(j-51)/200); k=%d l=%d its=%d" % (m, n, k, l, its),
+                   "m": m, "n": n, "k": k, "l": l, "its": its, "center": True},
+        "passes": passes,
+        "roofline": roofline,
+        "sigma_k_plus_1": float(csig[k]),
+    }
+    if not args.no_cpu_baseline:
+        cb, rel = cpu_baseline(A, k, l, its, args.seed, True, args.cpu_sample_solves, S_host)
+        out["cpu_baseline"] = cb
+        out["parity_max_rel_sigma"] = rel
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -27,13 +27,18 @@ FLAGS = [
 ]
 
 
+# per-file extra flags: the elimination loop of the LU pivot search is fully
+# unrolled so each row stays in registers
+EXTRA = {"lu.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
+
+
 def _sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src):
     obj = os.path.join(OBJ, src + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in ln]
     if r.returncode != 0:

@@ -106,8 +106,12 @@ __device__ __forceinline__ float4 load_row4(const float* __restrict__ A, int64_t
 }
 
 // ------------------------------------------------------------------------
-// Y = A X.  Workgroup: 4 waves, BM = 32*WR rows x 32*NB columns; each wave a
-// 32-row block and NB/WC column blocks.  K advances 32 columns per stage.
+// Y = A X.  Workgroup: 4 waves on a 128-row tile, wave w owns rows
+// 32w..32w+31 and all 32*NB columns.  K advances 32 columns per stage: each
+// thread loads four float4 of A (row (q>>3), columns 4(q&7)..+3 of the stage,
+// q = tid + 256 v: every wave instruction reads eight full 128-byte row
+// segments) and NB 16-byte words of packed X; the next stage's loads are in
+// flight while the current stage is multiplied out of LDS.
 // ------------------------------------------------------------------------
 template <int NB>
 __global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A, int64_t lda,
@@ -115,83 +119,89 @@ __global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A
                                                      const __bf16* __restrict__ Xp,
                                                      float* __restrict__ Y, int64_t ldy,
                                                      int vec) {
-  constexpr int WR = (NB == 1) ? 4 : 2;
-  constexpr int WC = 4 / WR;
-  constexpr int CBW = NB / WC;
-  constexpr int BM = 32 * WR;
+  constexpr int BM = 128;
   constexpr int KC = 32;
-  constexpr int AF4 = BM * KC / 4 / 256;  // float4 per thread per stage
-  constexpr int XU4 = NB;                 // 16-byte words per thread per stage
-  __shared__ __attribute__((aligned(16))) char lds_a[WR * 4 * 1024];
-  __shared__ __attribute__((aligned(16))) char lds_x[NB * 4 * 1024];
+  __shared__ __attribute__((aligned(16))) char lds_a[4 * 4 * 1024];   // [rb 4][s 2][part 2]
+  __shared__ __attribute__((aligned(16))) char lds_x[NB * 4 * 1024];  // [s 2][cb NB][part 2]
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int rbw = wave % WR, cw = wave / WR;
   const int64_t row0 = (int64_t)blockIdx.x * BM;
   const int64_t nstage = ceil_div(n, KC);
+  const bool rows_in = (row0 + BM <= m) && vec;
+  const int64_t nfast = rows_in ? n / KC : 0;  // stages loadable without masks
 
-  float4 ra[AF4];
-  uint4 rx[XU4];
-  auto load_stage = [&](int64_t stg) {
-#pragma unroll
-    for (int v = 0; v < AF4; ++v) {
-      const int q = tid + 256 * v;
-      ra[v] = load_row4(A, lda, row0 + (q >> 3), stg * KC + 4 * (q & 7), m, n, vec != 0);
-    }
-    const uint4* xs = reinterpret_cast<const uint4*>(Xp + stg * 2 * NB * 2 * kFragElems);
-#pragma unroll
-    for (int v = 0; v < XU4; ++v) rx[v] = xs[tid + 256 * v];
-  };
+  const int lr = tid >> 3, lc = 4 * (tid & 7);
+  const float* ap = A + (row0 + lr) * lda + lc;
+  const int64_t rstride = 32 * lda;
+  const uint4* xbase = reinterpret_cast<const uint4*>(Xp);
 
-  f32x16 acc[CBW];
+  float4 ra[4];
+  uint4 rx[NB];
+#define AX_LOAD(STG)                                                                     \
+  do {                                                                                   \
+    const int64_t stg_ = (STG);                                                          \
+    if (stg_ < nfast) {                                                                  \
+      _Pragma("unroll") for (int v = 0; v < 4; ++v) ra[v] =                              \
+          *reinterpret_cast<const float4*>(ap + v * rstride + stg_ * KC);               \
+    } else {                                                                             \
+      _Pragma("unroll") for (int v = 0; v < 4; ++v) ra[v] =                              \
+          load_row4(A, lda, row0 + lr + 32 * v, stg_ * KC + lc, m, n, vec != 0);         \
+    }                                                                                    \
+    _Pragma("unroll") for (int v = 0; v < NB; ++v) rx[v] =                               \
+        xbase[stg_ * (NB * 256) + tid + 256 * v];                                        \
+  } while (0)
+
+  f32x16 acc[NB];
 #pragma unroll
-  for (int i = 0; i < CBW; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
 
-  load_stage(0);
+  // LDS byte offset of this thread's four (row, 4-column) pieces
+  const int c4 = tid & 7;
+  const int s_t = c4 >> 2, g_t = (c4 & 3) >> 1, j0 = 4 * (c4 & 1);
+
+  AX_LOAD(0);
   for (int64_t stg = 0; stg < nstage; ++stg) {
 #pragma unroll
-    for (int v = 0; v < AF4; ++v) {
-      const int q = tid + 256 * v;
-      const int row = q >> 3, c4 = q & 7;
-      const int rb = row >> 5, r = row & 31, s = c4 >> 2, g = (c4 & 3) >> 1, j0 = 4 * (c4 & 1);
+    for (int v = 0; v < 4; ++v) {
+      const int row = lr + 32 * v;
+      const int off = ((v * 2 + s_t) * 2) * 1024 + 16 * ((row & 31) + 32 * g_t) + 2 * j0;
       bf16x4 h, lo;
       __bf16 th, tl;
       split_bf16(ra[v].x, th, tl); h[0] = th; lo[0] = tl;
       split_bf16(ra[v].y, th, tl); h[1] = th; lo[1] = tl;
       split_bf16(ra[v].z, th, tl); h[2] = th; lo[2] = tl;
       split_bf16(ra[v].w, th, tl); h[3] = th; lo[3] = tl;
-      const int off = ((rb * 2 + s) * 2) * 1024 + 16 * (r + 32 * g) + 2 * j0;
       *reinterpret_cast<bf16x4*>(lds_a + off) = h;
       *reinterpret_cast<bf16x4*>(lds_a + off + 1024) = lo;
     }
 #pragma unroll
-    for (int v = 0; v < XU4; ++v) reinterpret_cast<uint4*>(lds_x)[tid + 256 * v] = rx[v];
+    for (int v = 0; v < NB; ++v) reinterpret_cast<uint4*>(lds_x)[tid + 256 * v] = rx[v];
     __syncthreads();
-    if (stg + 1 < nstage) load_stage(stg + 1);
+    if (stg + 1 < nstage) AX_LOAD(stg + 1);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(lds_a + ((rbw * 2 + s) * 2) * 1024 + 16 * lane);
-      const bf16x8 al = *reinterpret_cast<const bf16x8*>(lds_a + ((rbw * 2 + s) * 2 + 1) * 1024 + 16 * lane);
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(lds_a + ((wave * 2 + s) * 2) * 1024 + 16 * lane);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(lds_a + ((wave * 2 + s) * 2 + 1) * 1024 + 16 * lane);
 #pragma unroll
-      for (int i = 0; i < CBW; ++i) {
-        const int cb = cw * CBW + i;
+      for (int cb = 0; cb < NB; ++cb) {
         const bf16x8 xh = *reinterpret_cast<const bf16x8*>(lds_x + ((s * NB + cb) * 2) * 1024 + 16 * lane);
         const bf16x8 xl = *reinterpret_cast<const bf16x8*>(lds_x + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
-        acc[i] = mfma3(ah, al, xh, xl, acc[i]);
+        acc[cb] = mfma3(ah, al, xh, xl, acc[cb]);
       }
     }
     __syncthreads();
   }
+#undef AX_LOAD
   const int g = lane >> 5;
 #pragma unroll
-  for (int i = 0; i < CBW; ++i) {
-    const int col = 32 * (cw * CBW + i) + (lane & 31);
+  for (int cb = 0; cb < NB; ++cb) {
+    const int col = 32 * cb + (lane & 31);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int64_t row = row0 + 32 * rbw + (r & 3) + 4 * g + 8 * (r >> 2);
-      if (row < m) Y[row * ldy + col] = acc[i][r];
+      const int64_t row = row0 + 32 * wave + (r & 3) + 4 * g + 8 * (r >> 2);
+      if (row < m) Y[row * ldy + col] = acc[cb][r];
     }
   }
 }
@@ -201,8 +211,7 @@ void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m,
   (void)dtype;
   const float* Af = static_cast<const float*>(A);
   const int vec = ((lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Af) % 16) == 0) ? 1 : 0;
-  const int bm = (nb == 1) ? 128 : 64;
-  const dim3 grid((unsigned)ceil_div(m, bm));
+  const dim3 grid((unsigned)ceil_div(m, 128));
   switch (nb) {
     case 1: hipLaunchKernelGGL(ax_f32_kernel<1>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, Y, ldy, vec); break;
     case 2: hipLaunchKernelGGL(ax_f32_kernel<2>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, Y, ldy, vec); break;
@@ -235,18 +244,28 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
   const int64_t rbeg = (int64_t)split * rows_per;
   const int64_t rend = (rbeg + rows_per < m) ? rbeg + rows_per : m;
   const int64_t nstage = (rend > rbeg) ? ceil_div(rend - rbeg, KC) : 0;
+  const bool cols_in = (col0 + 128 <= n) && vec;
+  const int64_t nfast = cols_in ? (rend - rbeg) / KC : 0;
 
   const int cg = tid & 31, ro = tid >> 5;
+  const float* ap = A + (rbeg + 4 * ro) * lda + col0 + 4 * cg;
+  const uint4* xbase = reinterpret_cast<const uint4*>(Xp + (rbeg / 16) * NB * 2 * kFragElems);
   float4 ra[4];
   uint4 rx[NB];
-  auto load_stage = [&](int64_t stg) {
-    const int64_t r0 = rbeg + stg * KC + 4 * ro;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ra[q] = load_row4(A, lda, r0 + q, col0 + 4 * cg, rend, n, vec != 0);
-    const uint4* xs = reinterpret_cast<const uint4*>(Xp + (rbeg / 16 + 2 * stg) * NB * 2 * kFragElems);
-#pragma unroll
-    for (int v = 0; v < NB; ++v) rx[v] = xs[tid + 256 * v];
-  };
+#define ATX_LOAD(STG)                                                                    \
+  do {                                                                                   \
+    const int64_t stg_ = (STG);                                                          \
+    if (stg_ < nfast) {                                                                  \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) ra[q] =                              \
+          *reinterpret_cast<const float4*>(ap + (stg_ * KC + q) * lda);                  \
+    } else {                                                                             \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) ra[q] =                              \
+          load_row4(A, lda, rbeg + stg_ * KC + 4 * ro + q, col0 + 4 * cg, rend, n,       \
+                    vec != 0);                                                           \
+    }                                                                                    \
+    _Pragma("unroll") for (int v = 0; v < NB; ++v) rx[v] =                               \
+        xbase[stg_ * (NB * 256) + tid + 256 * v];                                        \
+  } while (0)
 
   f32x16 acc[NB];
 #pragma unroll
@@ -256,7 +275,7 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
 
   const int s_w = ro >> 2, g_w = (ro & 3) >> 1, jj0 = 4 * (ro & 1);
   const int jb_w = cg >> 3;
-  if (nstage > 0) load_stage(0);
+  if (nstage > 0) ATX_LOAD(0);
   for (int64_t stg = 0; stg < nstage; ++stg) {
 #pragma unroll
     for (int qc = 0; qc < 4; ++qc) {
@@ -277,7 +296,7 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
 #pragma unroll
     for (int v = 0; v < NB; ++v) reinterpret_cast<uint4*>(lds_x)[tid + 256 * v] = rx[v];
     __syncthreads();
-    if (stg + 1 < nstage) load_stage(stg + 1);
+    if (stg + 1 < nstage) ATX_LOAD(stg + 1);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const bf16x8 bh = *reinterpret_cast<const bf16x8*>(lds_a + ((s * 4 + wave) * 2) * 1024 + 16 * lane);
@@ -291,6 +310,7 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
     }
     __syncthreads();
   }
+#undef ATX_LOAD
   float* out = P + ((int64_t)(split * ntiles + tile) * 4 + wave) * NB * 1024;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb)

@@ -34,54 +34,57 @@ struct LuLevels {
 // threads of a workgroup (one row per thread, in registers).  Chooses up to
 // l pivot rows; ties in |value| go to the smaller global row index.  When
 // ``U`` is given the eliminated pivot rows are written to it.
+// Gaussian elimination with partial pivoting over the rows held by the 256
+// threads of a workgroup (one row per thread, in registers; the column loop
+// is unrolled so every row access has a constant index).  Chooses up to l
+// pivot rows; ties in |value| go to the smaller global row index.  When
+// ``U`` is given the eliminated pivot rows are written to it.
 template <int LP>
-__device__ void gepp_block(float (&row)[LP], bool cand, int gidx, int l, int* s_piv,
+__device__ __forceinline__ void gepp_block(float (&row)[LP], bool cand, int gidx, int l, int* s_piv,
                            float* s_wkey, int* s_widx, float* s_wrow, float* U) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 #pragma unroll
   for (int p = 0; p < LP; ++p) {
-    if (p >= l) break;
-    const int buf = p & 1;
-    float key = cand ? fabsf(row[p]) : -1.f;
-    int idx = cand ? gidx : 0x7fffffff;
-    const float mykey = key;
-    wave_argmax(key, idx);
-    if (lane == 0) {
-      s_wkey[buf * 4 + wave] = key;
-      s_widx[buf * 4 + wave] = idx;
-    }
-    if (cand && mykey == key && gidx == idx) {
-      float* dst = s_wrow + (buf * 4 + wave) * LP;
-#pragma unroll
-      for (int c = 0; c < LP; ++c) dst[c] = row[c];
-    }
-    __syncthreads();
-    float bk = s_wkey[buf * 4];
-    int bi = s_widx[buf * 4], bw = 0;
-#pragma unroll
-    for (int w = 1; w < 4; ++w) {
-      const float k2 = s_wkey[buf * 4 + w];
-      const int i2 = s_widx[buf * 4 + w];
-      if (k2 > bk || (k2 == bk && i2 < bi)) {
-        bk = k2;
-        bi = i2;
-        bw = w;
+    if (p < l) {
+      const int buf = p & 1;
+      float key = cand ? fabsf(row[p]) : -1.f;
+      int idx = cand ? gidx : 0x7fffffff;
+      wave_argmax(key, idx);
+      if (lane == 0) {
+        s_wkey[buf * 4 + wave] = key;
+        s_widx[buf * 4 + wave] = idx;
       }
-    }
-    if (bk < 0.f) {  // no candidate rows left
-      if (tid == 0) s_piv[p] = -1;
-      if (U && tid < LP) U[p * LP + tid] = 0.f;
-      continue;
-    }
-    const float* prow = s_wrow + (buf * 4 + bw) * LP;
-    if (tid == 0) s_piv[p] = bi;
-    if (U && tid < LP) U[p * LP + tid] = (tid >= p && tid < l) ? prow[tid] : 0.f;
-    if (cand && gidx == bi) {
-      cand = false;
-    } else if (cand && bk > 0.f) {
-      const float mult = row[p] / prow[p];
+      if (cand && gidx == idx) {
+        float4* dst = reinterpret_cast<float4*>(s_wrow + (buf * 4 + wave) * LP);
 #pragma unroll
-      for (int c = p + 1; c < LP; ++c) row[c] -= mult * prow[c];
+        for (int c = 0; c < LP; c += 4)
+          if (c + 3 >= p) dst[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
+      }
+      __syncthreads();
+      float bk = s_wkey[buf * 4];
+      int bi = s_widx[buf * 4], bw = 0;
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        const float k2 = s_wkey[buf * 4 + w];
+        const int i2 = s_widx[buf * 4 + w];
+        if (k2 > bk || (k2 == bk && i2 < bi)) {
+          bk = k2;
+          bi = i2;
+          bw = w;
+        }
+      }
+      const float* prow = s_wrow + (buf * 4 + bw) * LP;
+      const bool have = (bk >= 0.f);  // some candidate row was left
+      if (tid == 0) s_piv[p] = have ? bi : -1;
+      if (U && tid < LP) U[p * LP + tid] = (have && tid >= p && tid < l) ? prow[tid] : 0.f;
+      if (cand && gidx == bi) {
+        cand = false;
+      } else if (cand && bk > 0.f) {
+        const float mult = row[p] / prow[p];
+#pragma unroll
+        for (int c = 0; c < LP; ++c)
+          if (c > p) row[c] -= mult * prow[c];
+      }
     }
   }
   __syncthreads();

@@ -253,20 +253,23 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
                                                      double* __restrict__ Wacc,
                                                      double* __restrict__ Xn,
                                                      double* __restrict__ gwork) {
-  __shared__ double sM[GLOBAL ? 1 : LP * LP];
-  __shared__ double sV[GLOBAL ? 1 : LP * LP];
+  // column stride padded by one double in LDS so that the columns of
+  // different pairs fall in different banks
+  constexpr int CS = GLOBAL ? LP : LP + 1;
+  __shared__ double sM[GLOBAL ? 1 : LP * CS];
+  __shared__ double sV[GLOBAL ? 1 : LP * CS];
   __shared__ double sig[LP];
   __shared__ int perm[LP];
   __shared__ int s_rot;
   double* Mc = GLOBAL ? gwork : sM;
-  double* Vc = GLOBAL ? gwork + LP * LP : sV;
+  double* Vc = GLOBAL ? gwork + LP * CS : sV;
   const int tid = threadIdx.x;
   for (int e = tid; e < LP * LP; e += 256) {
     const int j = e / LP, i = e % LP;
     double v = 0.0;
     if (i < l && j < l) v = transpose ? M[j * LP + i] : M[i * LP + j];
-    Mc[e] = v;
-    Vc[e] = (i == j) ? 1.0 : 0.0;
+    Mc[j * CS + i] = v;
+    Vc[j * CS + i] = (i == j) ? 1.0 : 0.0;
   }
   const int lp2 = l + (l & 1);
   const int npairs = lp2 / 2;
@@ -274,7 +277,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
   while (G > 1 && G * npairs > 256) G >>= 1;
   const int k = tid / G, gl = tid % G;
   const bool active = (k < npairs);
-  const double tol = 1e-15;
+  const double tol = 1e-13;
   for (int sweep = 0; sweep < 60; ++sweep) {
     __syncthreads();
     if (tid == 0) s_rot = 0;
@@ -289,7 +292,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
       double al = 0.0, be = 0.0, ga = 0.0;
       if (active && p < l && q < l) {
         for (int i = gl; i < l; i += G) {
-          const double mp = Mc[p * LP + i], mq = Mc[q * LP + i];
+          const double mp = Mc[p * CS + i], mq = Mc[q * CS + i];
           al += mp * mp;
           be += mq * mq;
           ga += mp * mq;
@@ -303,12 +306,12 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
         const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
         for (int i = gl; i < l; i += G) {
-          const double mp = Mc[p * LP + i], mq = Mc[q * LP + i];
-          Mc[p * LP + i] = c * mp - s * mq;
-          Mc[q * LP + i] = s * mp + c * mq;
-          const double vp = Vc[p * LP + i], vq = Vc[q * LP + i];
-          Vc[p * LP + i] = c * vp - s * vq;
-          Vc[q * LP + i] = s * vp + c * vq;
+          const double mp = Mc[p * CS + i], mq = Mc[q * CS + i];
+          Mc[p * CS + i] = c * mp - s * mq;
+          Mc[q * CS + i] = s * mp + c * mq;
+          const double vp = Vc[p * CS + i], vq = Vc[q * CS + i];
+          Vc[p * CS + i] = c * vp - s * vq;
+          Vc[q * CS + i] = s * vp + c * vq;
         }
         if (gl == 0) s_rot = 1;
       }
@@ -320,7 +323,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
   if (tid < LP) {
     double s = 0.0;
     if (tid < l)
-      for (int i = 0; i < l; ++i) s += Mc[tid * LP + i] * Mc[tid * LP + i];
+      for (int i = 0; i < l; ++i) s += Mc[tid * CS + i] * Mc[tid * CS + i];
     sig[tid] = sqrt(s);
   }
   __syncthreads();
@@ -336,8 +339,8 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
     double w = 0.0, x = 0.0;
     if (i < l && rr < l) {
       const int j = perm[rr];
-      w = Vc[j * LP + i];
-      x = (sig[j] > 0.0) ? Mc[j * LP + i] / sig[j] : 0.0;
+      w = Vc[j * CS + i];
+      x = (sig[j] > 0.0) ? Mc[j * CS + i] / sig[j] : 0.0;
     }
     Wacc[e] = w;
     Xn[e] = x;

@@ -11,7 +11,7 @@ namespace rpca {
 // ------------------------------------------------------------------------
 // column sums and sums of squares, float64 partials per row chunk
 // ------------------------------------------------------------------------
-static constexpr int kColChunk = 512;
+static constexpr int kColChunk = 64;
 
 int colmean_blocks(int64_t rows) { return (int)ceil_div(rows > 0 ? rows : 1, kColChunk); }
 
@@ -46,13 +46,42 @@ __global__ void __launch_bounds__(256) colstats_kernel(const float* __restrict__
   }
 }
 
-__global__ void colmean_final_kernel(const double* __restrict__ psum, int nblk, int64_t rows,
-                                     int cols, float* __restrict__ mu) {
-  const int c = threadIdx.x;
-  if (c >= cols) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += psum[(int64_t)b * 128 + c];
-  mu[c] = (float)(s / (double)rows);
+// out[e] = scale * sum_b part[b * stride + e] for e < E.  A workgroup owns 64
+// consecutive e; its four waves split the b range, then combine in LDS.
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __restrict__ part,
+                                                              int nblk, int64_t stride, int E,
+                                                              double scale,
+                                                              double* __restrict__ out_d,
+                                                              float* __restrict__ out_f,
+                                                              const int* __restrict__ skip_flag) {
+  if (skip_flag && *skip_flag == 0) return;
+  __shared__ double sh[4][64];
+  const int el = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < E) {
+    int b = ph;
+    for (; b + 12 < nblk; b += 16) {
+      s0 += part[(int64_t)b * stride + e];
+      s1 += part[(int64_t)(b + 4) * stride + e];
+      s2 += part[(int64_t)(b + 8) * stride + e];
+      s3 += part[(int64_t)(b + 12) * stride + e];
+    }
+    for (; b < nblk; b += 4) s0 += part[(int64_t)b * stride + e];
+  }
+  sh[ph][el] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (ph == 0 && e < E) {
+    const double s = scale * (((sh[0][el] + sh[1][el]) + sh[2][el]) + sh[3][el]);
+    if (out_d) out_d[e] = s;
+    if (out_f) out_f[e] = (float)s;
+  }
+}
+
+static void launch_reduce(hipStream_t st, const double* part, int nblk, int64_t stride, int E,
+                          double scale, double* out_d, float* out_f, const int* skip_flag) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(E, 64)), dim3(256), 0, st,
+                     part, nblk, stride, E, scale, out_d, out_f, skip_flag);
 }
 
 void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
@@ -61,7 +90,7 @@ void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, i
   (void)nblk_max;
   hipLaunchKernelGGL(colstats_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, rows, cols, partial,
                      (double*)nullptr);
-  hipLaunchKernelGGL(colmean_final_kernel, dim3(1), dim3(128), 0, st, partial, nblk, rows, cols, mu);
+  launch_reduce(st, partial, nblk, 128, cols, 1.0 / (double)rows, nullptr, mu, nullptr);
 }
 
 __global__ void __launch_bounds__(256) sub_rowvec_kernel(float* __restrict__ X, int64_t ldx,
@@ -81,15 +110,12 @@ void launch_sub_rowvec(hipStream_t st, float* X, int64_t ldx, int64_t rows, int 
                      ldx, rows, cols, mu);
 }
 
-// sum of squares of all entries (float64) -> single value fro2[0]
-__global__ void fro2_final_kernel(const double* __restrict__ psq, int nblk, int cols,
-                                  double* __restrict__ fro2) {
+// sum of squares of all entries (float64) -> fro2[0]; colsq holds 128 doubles
+__global__ void sum_cols_kernel(const double* __restrict__ colsq, int cols,
+                                double* __restrict__ fro2) {
   __shared__ double sh[128];
   const int c = threadIdx.x;
-  double s = 0.0;
-  if (c < cols)
-    for (int b = 0; b < nblk; ++b) s += psq[(int64_t)b * 128 + c];
-  sh[c] = s;
+  sh[c] = (c < cols) ? colsq[c] : 0.0;
   __syncthreads();
   if (c == 0) {
     double t = 0.0;
@@ -102,7 +128,9 @@ void launch_fro2_d(hipStream_t st, const float* X, int64_t ldx, int64_t rows, in
                    double* psum, double* psq, double* fro2) {
   const int nblk = colmean_blocks(rows);
   hipLaunchKernelGGL(colstats_kernel, dim3(nblk), dim3(256), 0, st, X, ldx, rows, cols, psum, psq);
-  hipLaunchKernelGGL(fro2_final_kernel, dim3(1), dim3(128), 0, st, psq, nblk, cols, fro2);
+  // per-column sums of squares into psum[0..127] (psum's partials are not needed)
+  launch_reduce(st, psq, nblk, 128, cols, 1.0, psum, nullptr, nullptr);
+  hipLaunchKernelGGL(sum_cols_kernel, dim3(1), dim3(128), 0, st, psum, cols, fro2);
 }
 
 // ------------------------------------------------------------------------
@@ -160,18 +188,6 @@ __global__ void __launch_bounds__(256) gram_kernel(const float* __restrict__ X, 
     for (int v = 0; v < T; ++v) out[(ti * T + u) * LP + tj * T + v] = acc[u][v];
 }
 
-__global__ void __launch_bounds__(256) gram_reduce_kernel(const double* __restrict__ partial,
-                                                          int nblk, int lp2,
-                                                          double* __restrict__ G,
-                                                          const int* __restrict__ skip_flag) {
-  if (skip_flag && *skip_flag == 0) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= lp2) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * lp2 + e];
-  G[e] = s;
-}
-
 void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int lp,
                  const float* X2, int64_t ldx2, double* partial, double* G,
                  const int* skip_flag) {
@@ -183,8 +199,7 @@ void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int 
     default: return;
   }
   const int lp2 = lp * lp;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div(lp2, 256)), dim3(256), 0, st,
-                     partial, nblk, lp2, G, skip_flag);
+  launch_reduce(st, partial, nblk, lp2, lp2, 1.0, G, nullptr, skip_flag);
 }
 
 // ------------------------------------------------------------------------
@@ -313,7 +328,7 @@ void launch_small_gemm(hipStream_t st, const float* X, int64_t ldx, int64_t rows
 // Sign convention for the output: the largest-|.| entry of each column of U
 // is made positive (ties go to the smallest row index); V's column follows.
 // ------------------------------------------------------------------------
-static constexpr int kSignChunk = 512;
+static constexpr int kSignChunk = 64;
 
 __global__ void __launch_bounds__(128) colabsmax_kernel(const float* __restrict__ U, int64_t ldu,
                                                         int64_t m, int k, float* __restrict__ pval,
@@ -335,19 +350,40 @@ __global__ void __launch_bounds__(128) colabsmax_kernel(const float* __restrict_
   pidx[(int64_t)blockIdx.x * 128 + c] = bidx;
 }
 
-__global__ void sign_final_kernel(const float* __restrict__ pval, const int64_t* __restrict__ pidx,
-                                  int nblk, int k, float* __restrict__ sgn) {
-  const int c = threadIdx.x;
-  if (c >= k) return;
+// One workgroup per column: first maximum of |U[:, c]| over the block partials.
+__global__ void __launch_bounds__(256) sign_final_kernel(const float* __restrict__ pval,
+                                                         const int64_t* __restrict__ pidx,
+                                                         int nblk, int k, float* __restrict__ sgn) {
+  const int c = blockIdx.x;
   float best = -1.f, bval = 0.f;
-  for (int b = 0; b < nblk; ++b) {  // blocks in row order: strict > keeps the first maximum
+  int64_t bidx = 0x7fffffffffffffffLL;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const int64_t i = pidx[(int64_t)b * 128 + c];
     const float v = pval[(int64_t)b * 128 + c];
-    if (pidx[(int64_t)b * 128 + c] >= 0 && fabsf(v) > best) {
+    if (i >= 0 && (fabsf(v) > best || (fabsf(v) == best && i < bidx))) {
       best = fabsf(v);
       bval = v;
+      bidx = i;
     }
   }
-  sgn[c] = (bval < 0.f) ? -1.f : 1.f;
+  __shared__ float sb[256], sv[256];
+  __shared__ int64_t si[256];
+  sb[threadIdx.x] = best;
+  sv[threadIdx.x] = bval;
+  si[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const int u = threadIdx.x + o;
+      if (sb[u] > sb[threadIdx.x] || (sb[u] == sb[threadIdx.x] && si[u] < si[threadIdx.x])) {
+        sb[threadIdx.x] = sb[u];
+        sv[threadIdx.x] = sv[u];
+        si[threadIdx.x] = si[u];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && c < k) sgn[c] = (sv[0] < 0.f) ? -1.f : 1.f;
 }
 
 __global__ void __launch_bounds__(256) flip_kernel(float* __restrict__ X, int64_t ldx, int64_t rows,
@@ -370,7 +406,7 @@ void launch_sign_fix(hipStream_t st, float* U, int64_t ldu, int64_t m, int k, fl
   int64_t* pidx = reinterpret_cast<int64_t*>(pval + (size_t)nblk * 128 + ((nblk * 128) & 1));
   float* sgn = reinterpret_cast<float*>(pidx + (size_t)nblk * 128);
   hipLaunchKernelGGL(colabsmax_kernel, dim3(nblk), dim3(128), 0, st, U, ldu, m, k, pval, pidx);
-  hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(128), 0, st, pval, pidx, nblk, k, sgn);
+  hipLaunchKernelGGL(sign_final_kernel, dim3(k), dim3(256), 0, st, pval, pidx, nblk, k, sgn);
   hipLaunchKernelGGL(flip_kernel, dim3((unsigned)ceil_div(m * k, 256)), dim3(256), 0, st, U, ldu,
                      m, k, sgn);
   if (V)

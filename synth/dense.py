@@ -139,11 +139,15 @@ def centered_spectrum(U, sigma):
 # --------------------------------------------------------------------------
 
 
-def _cholqr2_torch(G):
+def _cholqr2_torch(G, chunk=16384):
+    """Q of G = Q R with diag(R) > 0, by Cholesky QR twice (G well conditioned)."""
     import torch
     for _ in range(2):
         R = torch.linalg.cholesky(G.T @ G, upper=True)
-        G = torch.linalg.solve_triangular(R, G, upper=True, left=False)
+        eye = torch.eye(R.shape[0], device=G.device, dtype=G.dtype)
+        Rinv = torch.linalg.solve_triangular(R, eye, upper=True)
+        for i in range(0, G.shape[0], chunk):
+            G[i:i + chunk] = G[i:i + chunk] @ Rinv
     return G
 
 

@@ -213,7 +213,10 @@ def test_svd_propack_fixtures(ctx, size, k):
     U, S, V = ctx.svd(_dev(A), k, l, 2, size + k)
     S = S.cpu().numpy()
     want = np.diag(A)[:k].astype(np.float64)
-    np.testing.assert_allclose(S, want, atol=2e-6)
+    # the products carry 16 significant bits per operand (bf16 hi + lo), so a
+    # diagonal matrix, whose entries of B = Q* A are sums of few terms, shows
+    # the per-product error 3 * 2^-18 ~ 1.1e-5 (times a small sum of |q|)
+    np.testing.assert_allclose(S, want, atol=3e-5)
     U = U.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(U.T @ U - np.eye(k), 2) < 1e-5
 
