@@ -19,6 +19,9 @@
 // 16 s + 8 g + j (j = 0..7) of column c.  This is the operand layout of
 // v_mfma_f32_32x32x16_bf16 for both the A and the B operand; the
 // accumulator of lane L, register r, is (row (r%4) + 4 g + 8 (r/4), col c).
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -206,10 +209,298 @@ __global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A
   }
 }
 
+// ========================================================================
+// LDS-DMA variants (row-major A with lda % 4 == 0, 16-byte aligned, n % 4 == 0
+// for Y = A X).  A and packed X tiles are copied global -> LDS by
+// global_load_lds_dwordx4 into a ring of S stages, so S - 1 stages stay in
+// flight while one is multiplied; the float32 -> bf16 split happens on the
+// LDS -> register read.  Every lane's source address is clamped to valid
+// memory; the entries this brings in for rows or columns outside A are
+// multiplied by zero rows of packed X or never stored.
+// ========================================================================
+typedef __attribute__((address_space(3))) char lds_char;
+
+// 16 bytes per lane, global -> LDS at lds_block + 16 * lane.  Written as
+// inline assembly (M0 = LDS base, no VGPR result) so that the compiler does
+// not guard every later LDS read with a wait for all outstanding copies; the
+// kernels wait for exactly the stage they read with wait_vm_barrier.
+__device__ __forceinline__ void dma16(const void* g, char* lds_block) {
+  const unsigned la = __builtin_amdgcn_readfirstlane((unsigned)(size_t)((lds_char*)lds_block));
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(la)
+               : "memory", "m0");
+}
+
+// Wait until at most N DMA instructions of this wave are outstanding, then
+// synchronize the workgroup.  The memory clobber keeps LDS reads below.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void barrier_mem() { asm volatile("s_barrier" ::: "memory"); }
+
+template <int PER, int S>
+__device__ __forceinline__ void wait_ahead(int ahead) {
+  // ahead = number of later stages already issued (0 .. S-1)
+  if (ahead <= 0) wait_vm_barrier<0>();
+  else if (ahead == 1) wait_vm_barrier<PER>();
+  else if (ahead == 2) wait_vm_barrier<(S >= 3 ? 2 * PER : PER)>();
+  else wait_vm_barrier<(S >= 4 ? 3 * PER : (S >= 3 ? 2 * PER : PER))>();
+}
+
+// ---------------- Y = A X --------------------------------------------------
+// Stage: 32 columns of a 128-row tile (16 KB of A, rows 8b..8b+7 per 1 KB DMA
+// block b; the 16-byte chunk c of row R sits at position c ^ ((R >> 1) & 7))
+// plus the matching 2 x NB packed X fragments.
+template <int NB, int S>
+__global__ void __launch_bounds__(256) ax_dma_kernel(const float* __restrict__ A, int64_t lda,
+                                                     int64_t m, int64_t n,
+                                                     const __bf16* __restrict__ Xp,
+                                                     float* __restrict__ Y, int64_t ldy,
+                                                     int64_t rows_per_wg) {
+  constexpr int KC = 32;
+  constexpr int ABYTES = 16384;
+  constexpr int STAGE = ABYTES + NB * 4096;
+  constexpr int PER = 4 + NB;  // DMA instructions per wave per stage
+  __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t rbeg = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t rend = min(m, rbeg + rows_per_wg);
+  const int64_t nstage = ceil_div(n, KC);
+  const char* xg = reinterpret_cast<const char*>(Xp);
+
+  // this lane's chunk within its DMA row (swizzled), constant over stages
+  const int lrow = lane >> 3;  // row within the 8-row block
+  const int g = lane >> 5;
+
+  for (int64_t row0 = rbeg; row0 < rend; row0 += 128) {
+    const float* rowp[4];
+    int cofs[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int R = 8 * (4 * wave + i) + lrow;  // tile row of this lane's DMA
+      const int64_t grow = min(row0 + R, rend - 1);
+      rowp[i] = A + grow * lda;
+      cofs[i] = 4 * ((lane & 7) ^ ((R >> 1) & 7));
+    }
+#define AX_ISSUE(STG)                                                                     \
+  do {                                                                                    \
+    const int64_t stg_ = (STG);                                                           \
+    char* slot_ = ring + (int)(stg_ % S) * STAGE;                                         \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
+      const int64_t col_ = stg_ * KC + cofs[i];                                           \
+      dma16(rowp[i] + (col_ < n ? col_ : 0), slot_ + (4 * wave + i) * 1024);              \
+    }                                                                                     \
+    _Pragma("unroll") for (int i = 0; i < NB; ++i) {                                      \
+      const int blk_ = wave + 4 * i;                                                      \
+      dma16(xg + (stg_ * (NB * 4) + blk_) * 1024 + 16 * lane, slot_ + ABYTES + blk_ * 1024); \
+    }                                                                                     \
+  } while (0)
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+
+#pragma unroll
+    for (int t = 0; t < S - 1; ++t)
+      if (t < nstage) AX_ISSUE(t);
+    const int R = 32 * wave + (lane & 31);
+    const int sw = (R >> 1) & 7;
+    for (int64_t stg = 0; stg < nstage; ++stg) {
+      if (stg + S - 1 < nstage) AX_ISSUE(stg + S - 1);
+      const int64_t last = min(nstage - 1, stg + S - 1);
+      wait_ahead<PER, S>((int)(last - stg));
+      const char* As = ring + (int)(stg % S) * STAGE;
+      const char* Xs = As + ABYTES;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int c0 = 4 * s + 2 * g;
+        const float4 a0 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * (c0 ^ sw));
+        const float4 a1 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * ((c0 + 1) ^ sw));
+        bf16x8 ah, al;
+        __bf16 th, tl;
+        split_bf16(a0.x, th, tl); ah[0] = th; al[0] = tl;
+        split_bf16(a0.y, th, tl); ah[1] = th; al[1] = tl;
+        split_bf16(a0.z, th, tl); ah[2] = th; al[2] = tl;
+        split_bf16(a0.w, th, tl); ah[3] = th; al[3] = tl;
+        split_bf16(a1.x, th, tl); ah[4] = th; al[4] = tl;
+        split_bf16(a1.y, th, tl); ah[5] = th; al[5] = tl;
+        split_bf16(a1.z, th, tl); ah[6] = th; al[6] = tl;
+        split_bf16(a1.w, th, tl); ah[7] = th; al[7] = tl;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          const bf16x8 xh = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
+          const bf16x8 xl = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
+          acc[cb] = mfma3(ah, al, xh, xl, acc[cb]);
+        }
+      }
+      barrier_mem();
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int col = 32 * cb + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = row0 + 32 * wave + (r & 3) + 4 * g + 8 * (r >> 2);
+        if (row < rend) Y[row * ldy + col] = acc[cb][r];
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no stores in flight under the next ring
+  }
+#undef AX_ISSUE
+}
+
+// ---------------- Z = A^T X (split-K partials) ------------------------------
+// Stage: 32 rows of a 128-column tile (16 KB; rows 2b, 2b+1 per DMA block b;
+// the 16-byte chunk c of row r sits at position c ^ (8 ((r >> 3) & 1))) plus
+// the matching packed X fragments.
+template <int NB, int S>
+__global__ void __launch_bounds__(256) atx_dma_kernel(const float* __restrict__ A, int64_t lda,
+                                                      int64_t m, int64_t n,
+                                                      const __bf16* __restrict__ Xp,
+                                                      float* __restrict__ P, int ntiles,
+                                                      int64_t rows_per) {
+  constexpr int KC = 32;
+  constexpr int ABYTES = 16384;
+  constexpr int STAGE = ABYTES + NB * 4096;
+  constexpr int PER = 4 + NB;
+  __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int split = t / ntiles, tile = t % ntiles;
+  const int64_t col0 = (int64_t)tile * 128;
+  const int64_t rbeg = (int64_t)split * rows_per;
+  const int64_t rend = (rbeg + rows_per < m) ? rbeg + rows_per : m;
+  const int64_t nstage = (rend > rbeg) ? ceil_div(rend - rbeg, KC) : 0;
+  const char* xg = reinterpret_cast<const char*>(Xp) + (rbeg / 16) * NB * 2 * 1024;
+
+  // DMA: block b = 4 * wave + i covers stage rows 2b + (lane >> 5)
+  int64_t colc[4];
+  int rr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = 4 * wave + i;
+    rr[i] = 2 * b + (lane >> 5);
+    const int chunk = (lane & 31) ^ (8 * ((rr[i] >> 3) & 1));
+    int64_t c = col0 + 4 * chunk;
+    colc[i] = (c + 4 <= n) ? c : 0;
+  }
+#define ATX_ISSUE(STG)                                                                    \
+  do {                                                                                    \
+    const int64_t stg_ = (STG);                                                           \
+    char* slot_ = ring + (int)(stg_ % S) * STAGE;                                         \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
+      const int64_t grow_ = min(rbeg + stg_ * KC + rr[i], rend - 1);                      \
+      dma16(A + grow_ * lda + colc[i], slot_ + (4 * wave + i) * 1024);                    \
+    }                                                                                     \
+    _Pragma("unroll") for (int i = 0; i < NB; ++i) {                                      \
+      const int blk_ = wave + 4 * i;                                                      \
+      dma16(xg + (stg_ * (NB * 4) + blk_) * 1024 + 16 * lane, slot_ + ABYTES + blk_ * 1024); \
+    }                                                                                     \
+  } while (0)
+
+  f32x16 acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+
+#pragma unroll
+  for (int u = 0; u < S - 1; ++u)
+    if (u < nstage) ATX_ISSUE(u);
+  const int j = lane & 31, g = lane >> 5;
+  // word offset of (row 8g + jj, column 32 wave + j) inside a 16-row half
+  const int chunk_r = (8 * wave + (j >> 2)) ^ (8 * g);
+  const int word = chunk_r * 4 + (j & 3);
+  for (int64_t stg = 0; stg < nstage; ++stg) {
+    if (stg + S - 1 < nstage) ATX_ISSUE(stg + S - 1);
+    const int64_t last = min(nstage - 1, stg + S - 1);
+    wait_ahead<PER, S>((int)(last - stg));
+    const char* As = ring + (int)(stg % S) * STAGE;
+    const char* Xs = As + ABYTES;
+    const float* Af = reinterpret_cast<const float*>(As);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 bh, bl;
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const float x = Af[(16 * s + 8 * g + jj) * 128 + word];
+        __bf16 th, tl;
+        split_bf16(x, th, tl);
+        bh[jj] = th;
+        bl[jj] = tl;
+      }
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const bf16x8 xh = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
+        const bf16x8 xl = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
+        acc[cb] = mfma3(xh, xl, bh, bl, acc[cb]);
+      }
+    }
+    barrier_mem();
+  }
+  float* out = P + ((int64_t)(split * ntiles + tile) * 4 + wave) * NB * 1024;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[(cb * 16 + r) * 64 + lane] = acc[cb][r];
+#undef ATX_ISSUE
+}
+
+static int ring_depth(int nb) {
+  static int env = -1;
+  if (env < 0) {
+    const char* e = getenv("RPCA_RING");
+    env = e ? atoi(e) : 0;
+  }
+  if (env >= 2 && env <= 4) return env;
+  return nb >= 4 ? 2 : 3;
+}
+
+static int dma_stage_bytes(int nb) { return 16384 + nb * 4096; }
+
+static bool dma_ok(const float* A, int64_t lda, int64_t n) {
+  static int env = -1;
+  if (env < 0) {
+    const char* e = getenv("RPCA_NO_DMA");
+    env = (e && atoi(e)) ? 1 : 0;
+  }
+  return !env && (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (n % 4) == 0;
+}
+
+template <int NB>
+static void launch_ax_dma(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n,
+                          const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
+  const int S = ring_depth(NB);
+  const int per_cu = std::max(1, (160 * 1024) / (S * dma_stage_bytes(NB)));
+  int64_t G = (int64_t)num_cus * per_cu;
+  G = std::min<int64_t>(G, ceil_div(m, 32));
+  const int64_t rows_per = ceil_div(m, G);
+  G = ceil_div(m, rows_per);
+  const dim3 grid((unsigned)G);
+  switch (S) {
+    case 2: hipLaunchKernelGGL((ax_dma_kernel<NB, 2>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
+    case 4: hipLaunchKernelGGL((ax_dma_kernel<NB, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
+    default: hipLaunchKernelGGL((ax_dma_kernel<NB, 3>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
+  }
+}
+
 void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
-               const __bf16* Xp, float* Y, int64_t ldy, int nb) {
+               const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus) {
   (void)dtype;
   const float* Af = static_cast<const float*>(A);
+  if (dma_ok(Af, lda, n)) {
+    switch (nb) {
+      case 1: launch_ax_dma<1>(st, Af, lda, m, n, Xp, Y, ldy, num_cus); return;
+      case 2: launch_ax_dma<2>(st, Af, lda, m, n, Xp, Y, ldy, num_cus); return;
+      case 4: launch_ax_dma<4>(st, Af, lda, m, n, Xp, Y, ldy, num_cus); return;
+      default: return;
+    }
+  }
   const int vec = ((lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Af) % 16) == 0) ? 1 : 0;
   const dim3 grid((unsigned)ceil_div(m, 128));
   switch (nb) {
@@ -322,10 +613,11 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus) {
   AtxPlan p;
   p.ntiles = (int)ceil_div(n, 128);
   const int64_t stages = ceil_div(m, 32);
-  // aim at ~4 workgroups per CU, a multiple of 8 workgroups, >= 8 stages per split
-  int64_t want = (int64_t)4 * num_cus / p.ntiles;
+  // workgroups resident per CU for the LDS ring of the DMA kernel
+  const int per_cu = std::max(1, (160 * 1024) / (ring_depth(nb) * dma_stage_bytes(nb)));
+  int64_t want = (int64_t)per_cu * num_cus / p.ntiles;
   if (want < 1) want = 1;
-  int64_t maxs = stages / 8;
+  int64_t maxs = stages / 4;
   if (maxs < 1) maxs = 1;
   if (want > maxs) want = maxs;
   int64_t per = ceil_div(stages, want);
@@ -339,8 +631,24 @@ void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m
                 const __bf16* Xp, float* P, const AtxPlan& plan, int nb) {
   (void)dtype;
   const float* Af = static_cast<const float*>(A);
-  const int vec = ((lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Af) % 16) == 0) ? 1 : 0;
   const dim3 grid((unsigned)(plan.ntiles * plan.nsplit));
+  if (dma_ok(Af, lda, n)) {
+    const int S = ring_depth(nb);
+#define ATX_DMA(NB_)                                                                                 \
+  switch (S) {                                                                                       \
+    case 2: hipLaunchKernelGGL((atx_dma_kernel<NB_, 2>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per); break; \
+    case 4: hipLaunchKernelGGL((atx_dma_kernel<NB_, 4>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per); break; \
+    default: hipLaunchKernelGGL((atx_dma_kernel<NB_, 3>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per); break; \
+  }
+    switch (nb) {
+      case 1: ATX_DMA(1); return;
+      case 2: ATX_DMA(2); return;
+      case 4: ATX_DMA(4); return;
+      default: return;
+    }
+#undef ATX_DMA
+  }
+  const int vec = ((lda % 4) == 0 && (reinterpret_cast<uintptr_t>(Af) % 16) == 0) ? 1 : 0;
   switch (nb) {
     case 1: hipLaunchKernelGGL(atx_f32_kernel<1>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per, vec); break;
     case 2: hipLaunchKernelGGL(atx_f32_kernel<2>, grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per, vec); break;

@@ -21,7 +21,7 @@ void launch_pack(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int 
 
 // Y (m x 32*nb) = A (m x n) X, X packed with >= 2*ceil(n/32) steps.
 void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
-               const __bf16* Xp, float* Y, int64_t ldy, int nb);
+               const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus);
 
 // Split-K partial products of A^T X (X packed on the m side).
 struct AtxPlan {

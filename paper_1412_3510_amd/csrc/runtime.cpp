@@ -244,7 +244,7 @@ void run_ax(rpca_ctx ctx, const rpca_matrix* A, const Work& w, const __bf16* Xp,
   const double bytes = (double)A->m * A->n * 4.0 + (double)A->n * w.lp * 4.0 +
                        (double)A->m * w.lp * 4.0;
   begin_timed(ctx, t, 0, bytes);
-  launch_ax(ctx->stream, A->data, A->dtype, A->ld, A->m, A->n, Xp, Y, w.lp, w.nb);
+  launch_ax(ctx->stream, A->data, A->dtype, A->ld, A->m, A->n, Xp, Y, w.lp, w.nb, ctx->num_cus);
   end_timed(ctx, t);
   ctx->stats.a_passes++;
 }
