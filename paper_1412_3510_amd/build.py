@@ -27,9 +27,8 @@ FLAGS = [
 ]
 
 
-# per-file extra flags: the elimination loop of the LU pivot search is fully
-# unrolled so each row stays in registers
-EXTRA = {"lu.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
+# per-file extra flags
+EXTRA = {}
 
 
 def _sources():

@@ -48,5 +48,35 @@ __device__ __forceinline__ void wave_argmax(float& key, int& idx) {
   }
 }
 
+// The same argmax with DPP lane permutations: quad swaps, half-row and row
+// mirrors inside each 16-lane row, then row_bcast:15 / row_bcast:31 across
+// rows; lane 63 ends with the wave's result, read back with one readlane.
+// Branch-free (selects), so the chain is a few dozen dependent VALU ops.
+__device__ __forceinline__ int dpp_sel(int v, int ctrl_sel) {
+  switch (ctrl_sel) {
+    case 0: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 1: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 2: return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    case 3: return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    case 4: return __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    default: return __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false); // row_bcast:31
+  }
+}
+
+__device__ __forceinline__ void argmax_combine(float& key, int& idx, int ctrl_sel) {
+  const float k2 = __int_as_float(dpp_sel(__float_as_int(key), ctrl_sel));
+  const int i2 = dpp_sel(idx, ctrl_sel);
+  const bool take = (k2 > key) | ((k2 == key) & (i2 < idx));
+  key = take ? k2 : key;
+  idx = take ? i2 : idx;
+}
+
+__device__ __forceinline__ void wave_argmax_fast(float& key, int& idx) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) argmax_combine(key, idx, s);
+  key = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(key), 63));
+  idx = __builtin_amdgcn_readlane(idx, 63);
+}
+
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

@@ -85,12 +85,12 @@ void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, i
                     const LuPlan& plan, int* cand, unsigned* counters, float* U, int* piv);
 
 // ---- small dense float64 kernels (small.hip) ---------------------------------
-// One Cholesky-QR step on the Gram G (lp x lp): upper R (float32 copy ``Rf``
-// for the solve), optional accumulation Racc <- R Racc (float64).  Passes 1
-// and 2 always run; passes 3 and 4 only when state[1] is set (a shifted
-// factorization or dependent columns met).  See small.hip for ``state``.
+// One Cholesky-QR step on the Gram G (lp x lp): upper R as float32 ``Rf``
+// for the solve.  Passes 1 and 2 always run; passes 3 and 4 only when
+// state[1] is set (a shifted factorization or dependent columns met).  See
+// small.hip for ``state``.
 void launch_chol_qr_step(hipStream_t st, const double* G, int l, int lp, int pass, float* Rf,
-                         double* Racc, int* state);
+                         int* state);
 // Replace the dependent columns flagged in ``state`` by Gaussian columns.
 void launch_complete(hipStream_t st, float* Q, int64_t ldq, int64_t rows, int l, const int* state,
                      uint64_t seed);

@@ -5,9 +5,10 @@
 //
 // Tall Y (up to 10^6 rows) cannot be factored column by column with a
 // grid-wide argmax per column, so pivots are chosen by tournament (Grigori,
-// Demmel and Xiang's CALU): every 256-row block runs Gaussian elimination
-// with partial pivoting on its own rows and nominates its l pivot rows; the
-// nominated original rows of F = 256/lp blocks are merged by the same
+// Demmel and Xiang's CALU): every block of NT rows (NT = 512 by default;
+// one row per thread) runs Gaussian elimination with
+// partial pivoting on its own rows and nominates its l pivot rows; the
+// nominated original rows of F = NT/lp blocks are merged by the same
 // elimination, level after level, until one set of l rows is left; its
 // elimination gives U.  The levels run inside one launch: the last
 // workgroup to finish a group (an atomic arrival counter) merges it, so no
@@ -18,6 +19,8 @@
 // zero, the first unused row is taken as pivot, U[j][j] = 0, and nothing is
 // eliminated; the solve then makes column j of P L the unit vector of that
 // row, so span(P L) contains span(Y).
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -30,78 +33,121 @@ struct LuLevels {
   int cnt_off[16];
 };
 
-// Gaussian elimination with partial pivoting over the rows held by the 256
-// threads of a workgroup (one row per thread, in registers).  Chooses up to
-// l pivot rows; ties in |value| go to the smaller global row index.  When
-// ``U`` is given the eliminated pivot rows are written to it.
-// Gaussian elimination with partial pivoting over the rows held by the 256
-// threads of a workgroup (one row per thread, in registers; the column loop
-// is unrolled so every row access has a constant index).  Chooses up to l
-// pivot rows; ties in |value| go to the smaller global row index.  When
-// ``U`` is given the eliminated pivot rows are written to it.
+template <int LP, int NT_>
+struct LuCfg {
+  static constexpr int NT = NT_;       // threads = rows per block
+  static constexpr int NW = NT / 64;   // waves
+  static constexpr int F = NT / LP;    // candidate sets merged per block
+};
+
+// row[c] <- row[c+1] - mult * prow[c+1] for c < W - 1 (the moving frame, see
+// gepp_block), prow streamed from LDS four values at a time.
+template <int W, int LP>
+__device__ __forceinline__ void shift_update(float (&row)[LP], float mult, const float* prow) {
+  static_assert(W <= LP && W % 4 == 0, "width");
+  float4 cur = *reinterpret_cast<const float4*>(prow);
+#pragma unroll
+  for (int c = 0; c < W; c += 4) {
+    const float4 nxt = (c + 4 < W) ? *reinterpret_cast<const float4*>(prow + c + 4)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    row[c] = row[c + 1] - mult * cur.y;
+    row[c + 1] = row[c + 2] - mult * cur.z;
+    row[c + 2] = row[c + 3] - mult * cur.w;
+    if (c + 4 < W) row[c + 3] = row[c + 4] - mult * nxt.x;
+    else row[c + 3] = 0.f;
+    cur = nxt;
+  }
+}
+
 template <int LP>
-__device__ __forceinline__ void gepp_block(float (&row)[LP], bool cand, int gidx, int l, int* s_piv,
-                           float* s_wkey, int* s_widx, float* s_wrow, float* U) {
+__device__ __forceinline__ void shift_bucket(float (&row)[LP], float mult, const float* prow,
+                                             int live) {
+  if (LP >= 128 && live > 96) shift_update<(LP >= 128 ? 128 : 16), LP>(row, mult, prow);
+  else if (LP >= 128 && live > 64) shift_update<(LP >= 128 ? 96 : 16), LP>(row, mult, prow);
+  else if (LP >= 64 && live > 48) shift_update<(LP >= 64 ? 64 : 16), LP>(row, mult, prow);
+  else if (LP >= 64 && live > 32) shift_update<(LP >= 64 ? 48 : 16), LP>(row, mult, prow);
+  else if (live > 16) shift_update<(LP >= 32 ? 32 : 16), LP>(row, mult, prow);
+  else shift_update<16, LP>(row, mult, prow);
+}
+
+// Gaussian elimination with partial pivoting over the rows held by the NT
+// threads of a workgroup (one row per thread, in registers).  The row is kept
+// in a moving frame: before step p, register c holds column p + c, and the
+// elimination update writes the shifted row, so the current column is always
+// row[0] and no register is addressed by a run-time index.  Per step: a DPP
+// argmax in each wave, the wave winners' rows to LDS, one barrier, a merge of
+// the wave results, the pivot row streamed from LDS into the update of the
+// live columns only.  Chooses up to l pivot rows; ties in |value| go to the
+// smaller global row index.  When ``U`` is given the eliminated pivot rows
+// (row p of U = pivot row in frame p) are written.
+template <int LP, int NT>
+__device__ __forceinline__ void gepp_block(float (&row)[LP], bool cand, int gidx, int l,
+                                           int* s_piv, float* s_wkey, int* s_widx,
+                                           float* s_wrow, float* U) {
+  constexpr int NW = LuCfg<LP, NT>::NW;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-#pragma unroll
-  for (int p = 0; p < LP; ++p) {
-    if (p < l) {
-      const int buf = p & 1;
-      float key = cand ? fabsf(row[p]) : -1.f;
-      int idx = cand ? gidx : 0x7fffffff;
-      wave_argmax(key, idx);
-      if (lane == 0) {
-        s_wkey[buf * 4 + wave] = key;
-        s_widx[buf * 4 + wave] = idx;
-      }
-      if (cand && gidx == idx) {
-        float4* dst = reinterpret_cast<float4*>(s_wrow + (buf * 4 + wave) * LP);
-#pragma unroll
-        for (int c = 0; c < LP; c += 4)
-          if (c + 3 >= p) dst[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
-      }
-      __syncthreads();
-      float bk = s_wkey[buf * 4];
-      int bi = s_widx[buf * 4], bw = 0;
-#pragma unroll
-      for (int w = 1; w < 4; ++w) {
-        const float k2 = s_wkey[buf * 4 + w];
-        const int i2 = s_widx[buf * 4 + w];
-        if (k2 > bk || (k2 == bk && i2 < bi)) {
-          bk = k2;
-          bi = i2;
-          bw = w;
-        }
-      }
-      const float* prow = s_wrow + (buf * 4 + bw) * LP;
-      const bool have = (bk >= 0.f);  // some candidate row was left
-      if (tid == 0) s_piv[p] = have ? bi : -1;
-      if (U && tid < LP) U[p * LP + tid] = (have && tid >= p && tid < l) ? prow[tid] : 0.f;
-      if (cand && gidx == bi) {
-        cand = false;
-      } else if (cand && bk > 0.f) {
-        const float mult = row[p] / prow[p];
-#pragma unroll
-        for (int c = 0; c < LP; ++c)
-          if (c > p) row[c] -= mult * prow[c];
-      }
+  for (int p = 0; p < l; ++p) {
+    const int buf = p & 1;
+    const int live = l - p;
+    float key = cand ? fabsf(row[0]) : -1.f;
+    int idx = cand ? gidx : 0x7fffffff;
+    wave_argmax_fast(key, idx);
+    if (lane == 0) {
+      s_wkey[buf * NW + wave] = key;
+      s_widx[buf * NW + wave] = idx;
     }
+    if (cand && gidx == idx) {
+      float4* dst = reinterpret_cast<float4*>(s_wrow + (buf * NW + wave) * LP);
+#pragma unroll
+      for (int c = 0; c < LP; c += 4)
+        if (c < live) dst[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
+    }
+    __syncthreads();
+    float wk[NW];
+    int wi[NW];
+#pragma unroll
+    for (int w = 0; w < NW; w += 4) {
+      const float4 k4 = *reinterpret_cast<const float4*>(s_wkey + buf * NW + w);
+      const int4 i4 = *reinterpret_cast<const int4*>(s_widx + buf * NW + w);
+      wk[w] = k4.x; wk[w + 1] = k4.y; wk[w + 2] = k4.z; wk[w + 3] = k4.w;
+      wi[w] = i4.x; wi[w + 1] = i4.y; wi[w + 2] = i4.z; wi[w + 3] = i4.w;
+    }
+    float bk = wk[0];
+    int bi = wi[0], bw = 0;
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const float k2 = wk[w];
+      const int i2 = wi[w];
+      const bool take = (k2 > bk) | ((k2 == bk) & (i2 < bi));
+      bk = take ? k2 : bk;
+      bi = take ? i2 : bi;
+      bw = take ? w : bw;
+    }
+    const float* prow = s_wrow + (buf * NW + bw) * LP;
+    const bool have = (bk >= 0.f);  // some candidate row was left
+    if (tid == 0) s_piv[p] = have ? bi : -1;
+    if (U && tid < LP) U[p * LP + tid] = (have && tid >= p && tid < l) ? prow[tid - p] : 0.f;
+    const float inv = (have && bk > 0.f) ? 1.0f / prow[0] : 0.f;
+    float mult = 0.f;
+    if (cand && gidx == bi) cand = false;
+    else if (cand) mult = row[0] * inv;
+    shift_bucket<LP>(row, mult, prow, live);
   }
   __syncthreads();
 }
 
-template <int LP>
-__global__ void __launch_bounds__(256) lu_tree_kernel(const float* __restrict__ X, int64_t ldx,
+template <int LP, int NT_>
+__global__ void __launch_bounds__(NT_) lu_tree_kernel(const float* __restrict__ X, int64_t ldx,
                                                       int64_t rows, int l, LuLevels lv,
                                                       int* __restrict__ cand,
                                                       unsigned* __restrict__ counters,
                                                       float* __restrict__ U,
                                                       int* __restrict__ piv) {
-  constexpr int F = 256 / LP;
+  constexpr int NT = LuCfg<LP, NT_>::NT, NW = LuCfg<LP, NT_>::NW, F = LuCfg<LP, NT_>::F;
   __shared__ int s_piv[LP];
-  __shared__ float s_wkey[8];
-  __shared__ int s_widx[8];
-  __shared__ __attribute__((aligned(16))) float s_wrow[8 * LP];
+  __shared__ __attribute__((aligned(16))) float s_wkey[2 * NW];
+  __shared__ __attribute__((aligned(16))) int s_widx[2 * NW];
+  __shared__ __attribute__((aligned(16))) float s_wrow[2 * NW * LP];
   __shared__ int s_last;
   const int tid = threadIdx.x;
   int level = 0, blk = blockIdx.x;
@@ -110,7 +156,7 @@ __global__ void __launch_bounds__(256) lu_tree_kernel(const float* __restrict__ 
     bool valid = false;
     int gidx = 0x7fffffff;
     if (level == 0) {
-      const int64_t r = (int64_t)blk * 256 + tid;
+      const int64_t r = (int64_t)blk * NT + tid;
       valid = r < rows;
       gidx = (int)r;
     } else {
@@ -136,10 +182,10 @@ __global__ void __launch_bounds__(256) lu_tree_kernel(const float* __restrict__ 
       for (int c = 0; c < LP; ++c) row[c] = 0.f;
     }
     const bool root = (lv.nblk[level] == 1);
-    gepp_block<LP>(row, valid, gidx, l, s_piv, s_wkey, s_widx, s_wrow, root ? U : nullptr);
+    gepp_block<LP, NT>(row, valid, gidx, l, s_piv, s_wkey, s_widx, s_wrow, root ? U : nullptr);
     if (root) {
       if (tid < LP) piv[tid] = (tid < l) ? s_piv[tid] : -1;
-      for (int e = l * LP + tid; e < LP * LP; e += 256) U[e] = 0.f;
+      for (int e = l * LP + tid; e < LP * LP; e += NT) U[e] = 0.f;
       return;
     }
     if (tid < LP) cand[lv.cand_off[level] + blk * LP + tid] = (tid < l) ? s_piv[tid] : -1;
@@ -162,11 +208,25 @@ __global__ void __launch_bounds__(256) lu_tree_kernel(const float* __restrict__ 
   }
 }
 
+// rows per block (= threads); RPCA_LU_NT overrides for tuning
+static int lu_block_rows(int lp) {
+  static int env = -1;
+  if (env < 0) {
+    const char* e = getenv("RPCA_LU_NT");
+    env = e ? atoi(e) : 0;
+  }
+  int nt = 512;
+  if (env == 256 || env == 512 || (env == 1024 && lp <= 64)) nt = env;
+  if (nt < 2 * lp) nt = 2 * lp;
+  return nt;
+}
+
 LuPlan plan_lu(int64_t rows, int lp) {
   LuPlan p{};
   p.lp = lp;
-  const int F = 256 / lp;
-  int nb = (int)ceil_div(rows, 256);
+  const int NT = lu_block_rows(lp);
+  const int F = NT / lp;
+  int nb = (int)ceil_div(rows, NT);
   int64_t coff = 0, koff = 0;
   p.levels = 0;
   while (true) {
@@ -197,12 +257,22 @@ void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, i
     if (i >= 1) acc += plan.nblk[i];
   }
   const dim3 grid((unsigned)plan.nblk[0]);
-  switch (plan.lp) {
-    case 32: hipLaunchKernelGGL(lu_tree_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, lv, cand, counters, U, piv); break;
-    case 64: hipLaunchKernelGGL(lu_tree_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, lv, cand, counters, U, piv); break;
-    case 128: hipLaunchKernelGGL(lu_tree_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, lv, cand, counters, U, piv); break;
-    default: break;
+  const int nt = lu_block_rows(plan.lp);
+#define LU_LAUNCH(LP_, NT_)                                                                  \
+  hipLaunchKernelGGL((lu_tree_kernel<LP_, NT_>), grid, dim3(NT_), 0, st, X, ldx, rows, l, lv, \
+                     cand, counters, U, piv)
+  if (plan.lp == 32) {
+    if (nt == 1024) LU_LAUNCH(32, 1024);
+    else if (nt == 512) LU_LAUNCH(32, 512);
+    else LU_LAUNCH(32, 256);
+  } else if (plan.lp == 64) {
+    if (nt == 1024) LU_LAUNCH(64, 1024);
+    else if (nt == 512) LU_LAUNCH(64, 512);
+    else LU_LAUNCH(64, 256);
+  } else if (plan.lp == 128) {
+    LU_LAUNCH(128, 512);
   }
+#undef LU_LAUNCH
 }
 
 }  // namespace rpca

@@ -132,6 +132,7 @@ struct Work {
   float* Y = nullptr;     // m x lp
   float* Z = nullptr;     // n x lp
   float* Y2 = nullptr;    // m x lp (second tall buffer, Nystrom)
+  float* Bk = nullptr;    // copy of the matrix being orthonormalized, for R = Q^T B
   __bf16* Xp = nullptr;   // packed operand (max of both sides)
   float* P = nullptr;     // A^T X partials
   float* mu = nullptr;    // lp
@@ -166,6 +167,7 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.Y = ar.take<float>((size_t)round_up(m, 32) * lp);
   w.Z = ar.take<float>((size_t)round_up(n, 32) * lp);
   if (need_y2) w.Y2 = ar.take<float>((size_t)round_up(m, 32) * lp);
+  w.Bk = ar.take<float>((size_t)round_up(rmax, 32) * lp);
   const int64_t steps = 2 * ceil_div(rmax, 32);
   w.Xp = ar.take<__bf16>(packed_bytes(steps, w.nb) / sizeof(__bf16));
   w.atx = plan_atx(m, n, w.nb, num_cus);
@@ -268,17 +270,21 @@ void lu_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
 
 // Y (rows x lp) <- Q with Y = Q R, Q orthonormal (Cholesky QR, float64 Gram,
 // shifted and completed when Y is numerically rank deficient).  With
-// ``Racc`` the product R is accumulated.
+// ``want_r`` the l x l factor R = Q^T Y_in is formed in float64 into w.G
+// (the exact projection of the input onto the final basis; upper triangular
+// up to rounding).
 void orth_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows, bool want_r, uint64_t seed) {
   hipStream_t st = ctx->stream;
-  double* Racc = want_r ? w.Racc : nullptr;
+  if (want_r)
+    (void)hipMemcpyAsync(w.Bk, Y, (size_t)rows * w.lp * sizeof(float), hipMemcpyDeviceToDevice, st);
   for (int pass = 1; pass <= 4; ++pass) {
     const int* skip = (pass >= 3) ? (w.state + 1) : nullptr;
     launch_gram(st, Y, w.lp, rows, w.lp, nullptr, 0, w.gpart, w.G, skip);
-    launch_chol_qr_step(st, w.G, w.l, w.lp, pass, w.Rf, Racc, w.state);
+    launch_chol_qr_step(st, w.G, w.l, w.lp, pass, w.Rf, w.state);
     launch_trsm(st, Y, w.lp, rows, w.l, w.lp, w.Rf, nullptr, skip, nullptr, nullptr, 0);
     if (pass == 2) launch_complete(st, Y, w.lp, rows, w.l, w.state, seed ^ 0x5bd1e995u);
   }
+  if (want_r) launch_gram(st, Y, w.lp, rows, w.lp, w.Bk, w.lp, w.gpart, w.G, nullptr);
 }
 
 void center_rows(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
@@ -453,7 +459,7 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   pack_m_side(ctx, w, w.Y, m, center);
   apply_at(ctx, A, w, w.Z);
   orth_renorm(ctx, w, w.Z, n, true, seed + 1);
-  launch_jacobi_svd(st, w.Racc, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
+  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
   // U = Q W, V = Q2 X, S = top k
   launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu);
   launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv);
@@ -504,7 +510,7 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
   launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp);
   orth_renorm(ctx, w, w.Y2, n, true, seed + 1);
-  launch_jacobi_svd(st, w.Racc, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork);
+  launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork);
   launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu);
   launch_finish_values(st, w.sv, k, w.scal + 1, lambda);
   launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
@@ -581,7 +587,7 @@ rpca_status rpca_op_renorm(rpca_ctx ctx, int kind, int64_t rows, int l, float* Y
   } else {
     orth_renorm(ctx, w, w.Y, rows, R != nullptr, 12345u);
     if (R)
-      HIP_OK(hipMemcpy2DAsync(R, l * sizeof(double), w.Racc, w.lp * sizeof(double),
+      HIP_OK(hipMemcpy2DAsync(R, l * sizeof(double), w.G, w.lp * sizeof(double),
                               l * sizeof(double), l, hipMemcpyDeviceToDevice, st));
   }
   HIP_OK(hipMemcpy2DAsync(Y, ldy * sizeof(float), w.Y, w.lp * sizeof(float), l * sizeof(float),

@@ -19,48 +19,78 @@ static constexpr double kTauRel = 1e-10;   // relative Cholesky pivot that marks
 static constexpr double kShiftRel = 1e-8;  // relative diagonal shift when dependence is met
 static constexpr double kJunkNorm2 = 1e-2; // squared column norm after a shifted pass
 
-// Cholesky G = R^T R of the leading l x l block held in LDS (row-major,
-// stride LP), in place (upper triangle).  Returns false at the first pivot
-// d_j <= tau * ref[j] (or non-finite); all threads agree.
+// Cholesky G + shift = R^T R (R upper) of the leading l x l block, one thread
+// per column.  Thread c keeps its column in registers in a moving frame
+// (before step j, reg[t] = A[j + t][c]), so the pivot row entry u_c of every
+// column is reg[0] and the update is a shifted register update.  The unscaled
+// pivot row u goes through a double-buffered LDS row, which also hands every
+// wave the pivot d = u_j; with R[j][c] = u_c / sqrt(d) the update is
+// reg[t] -= u_{j+1+t} (u_c / d).  The factor is written to Rs (LDS, row-major
+// stride LP).  Returns false at the first pivot d <= tau * diag[j] (or
+// non-finite); all threads read the same d, so all agree.
+// Pivot row buffer stride: the shifted update reads up to 31 entries past
+// column l - 1, which stay zero.
 template <int LP>
-__device__ bool chol_lds(double* A, int l, const double* ref, double tau, int* s_flag) {
-  const int tid = threadIdx.x;
+constexpr int kRowStride = LP + 32;
+
+template <int W, int LP>
+__device__ __forceinline__ void chol_shift(double (&reg)[LP], double coef, const double* row) {
+#pragma unroll
+  for (int t = 0; t + 1 < W; ++t) reg[t] = reg[t + 1] - row[t] * coef;
+  reg[W - 1] = 0.0;
+}
+
+template <int LP>
+__device__ bool chol_cols(const double* __restrict__ G, bool sym, int l, double srel, double sabs,
+                          const double* diag, double tau, double* Rs, double* rowbuf) {
+  const int c = threadIdx.x;  // column owned by this thread (blockDim.x == LP or 64)
+  double reg[LP];
+#pragma unroll
+  for (int t = 0; t < LP; ++t) {
+    double v = 0.0;
+    if (c < l && t < l) v = sym ? 0.5 * (G[t * LP + c] + G[c * LP + t]) : G[t * LP + c];
+    if (t == c && c < l) v += srel * diag[c] + sabs;
+    reg[t] = v;
+  }
   for (int j = 0; j < l; ++j) {
+    const int buf = j & 1;
+    const double u = (c >= j && c < l) ? reg[0] : 0.0;
+    if (c < LP) rowbuf[buf * kRowStride<LP> + c] = u;
     __syncthreads();
-    const double d = A[j * LP + j];
-    if (!(d > tau * ref[j]) || !(d > 0.0) || !(d < 1e300)) return false;
+    const double d = rowbuf[buf * kRowStride<LP> + j];
+    if (!(d > tau * diag[j]) || !(d > 0.0) || !(d < 1e300)) return false;
     const double r = sqrt(d);
-    const double ri = 1.0 / r;
-    __syncthreads();
-    for (int c = j + 1 + tid; c < l; c += blockDim.x) A[j * LP + c] *= ri;
-    if (tid == 0) A[j * LP + j] = r;
-    __syncthreads();
-    const int w = l - j - 1;
-    for (int e = tid; e < w * w; e += blockDim.x) {
-      const int i = j + 1 + e / w, c = j + 1 + e % w;
-      if (c >= i) A[i * LP + c] -= A[j * LP + i] * A[j * LP + c];
-    }
+    if (c < LP) Rs[j * LP + c] = (c == j) ? r : ((c > j) ? u / r : 0.0);
+    const double coef = (c > j) ? u / d : 0.0;
+    // reg[t] <- reg[t+1] - u_{j+1+t} u_c / d
+    const double* row = rowbuf + buf * kRowStride<LP> + j + 1;
+    const int live = l - j;
+    if (LP >= 128 && live > 96) chol_shift<(LP >= 128 ? 128 : 16), LP>(reg, coef, row);
+    else if (LP >= 128 && live > 64) chol_shift<(LP >= 128 ? 96 : 16), LP>(reg, coef, row);
+    else if (LP >= 64 && live > 48) chol_shift<(LP >= 64 ? 64 : 16), LP>(reg, coef, row);
+    else if (LP >= 64 && live > 32) chol_shift<(LP >= 64 ? 48 : 16), LP>(reg, coef, row);
+    else if (live > 16) chol_shift<(LP >= 32 ? 32 : 16), LP>(reg, coef, row);
+    else chol_shift<16, LP>(reg, coef, row);
   }
   __syncthreads();
-  (void)s_flag;
   return true;
 }
 
 template <int LP>
-__global__ void __launch_bounds__(256) chol_qr_kernel(const double* __restrict__ G, int l, int pass,
-                                                      float* __restrict__ Rf,
-                                                      double* __restrict__ Racc,
-                                                      int* __restrict__ state) {
+__global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_qr_kernel(const double* __restrict__ G,
+                                                                    int l, int pass,
+                                                                    float* __restrict__ Rf,
+                                                                    int* __restrict__ state) {
   if (pass >= 3 && state[1] == 0) return;
-  __shared__ double A[LP * LP];
+  constexpr int NT = LP < 64 ? 64 : LP;
+  __shared__ double Rs[LP * LP];
+  __shared__ double rowbuf[2 * kRowStride<LP>];
   __shared__ double diag[LP];
-  __shared__ int s_flag;
   const int tid = threadIdx.x;
-  if (pass == 1) {
-    __syncthreads();
-    if (tid < 12) state[tid] = 0;
-  }
-  for (int j = tid; j < LP; j += blockDim.x) diag[j] = (j < l) ? G[j * LP + j] : 0.0;
+  if (pass == 1 && tid < 12) state[tid] = 0;
+  for (int j = tid; j < LP; j += NT) diag[j] = (j < l) ? G[j * LP + j] : 0.0;
+  for (int e = tid; e < LP * LP; e += NT) Rs[e] = 0.0;
+  for (int e = tid; e < 2 * kRowStride<LP>; e += NT) rowbuf[e] = 0.0;
   __syncthreads();
   double maxd = 0.0;
   for (int j = 0; j < l; ++j) maxd = fmax(maxd, diag[j]);
@@ -69,18 +99,9 @@ __global__ void __launch_bounds__(256) chol_qr_kernel(const double* __restrict__
     __syncthreads();
     const double srel = attempt ? kShiftRel : 0.0;
     const double sabs = attempt ? (1e-30 * maxd + 1e-300) : 0.0;
-    for (int e = tid; e < LP * LP; e += blockDim.x) {
-      const int i = e / LP, c = e % LP;
-      double v = (i < l && c < l) ? G[e] : 0.0;
-      if (i == c && i < l) v += srel * diag[i] + sabs;
-      A[e] = v;
-    }
-    __syncthreads();
-    const bool ok = chol_lds<LP>(A, l, diag, attempt ? 0.0 : kTauRel, &s_flag);
+    const bool ok = chol_cols<LP>(G, false, l, srel, sabs, diag, attempt ? 0.0 : kTauRel, Rs, rowbuf);
     if (ok) break;
-    if (attempt == 1) {  // only non-finite input can get here
-      if (tid == 0) state[5] = 1;
-    }
+    if (attempt == 1 && tid == 0) state[5] = 1;  // only non-finite input gets here
     shifted = true;
   }
   __syncthreads();
@@ -103,55 +124,18 @@ __global__ void __launch_bounds__(256) chol_qr_kernel(const double* __restrict__
     }
   }
   // float32 copy of R for the solve
-  for (int e = tid; e < LP * LP; e += blockDim.x) {
+  for (int e = tid; e < LP * LP; e += NT) {
     const int i = e / LP, c = e % LP;
-    Rf[e] = (i < l && c < l && c >= i) ? (float)A[e] : 0.f;
-  }
-  if (Racc) {
-    __syncthreads();
-    if (pass == 1) {
-      for (int e = tid; e < LP * LP; e += blockDim.x) {
-        const int i = e / LP, c = e % LP;
-        Racc[e] = (i < l && c < l && c >= i) ? A[e] : 0.0;
-      }
-    } else {
-      // Racc <- R Racc (both upper triangular)
-      constexpr int PER = (LP * LP + 255) / 256;
-      double outv[PER];
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = tid + 256 * u;
-        double s = 0.0;
-        if (e < LP * LP) {
-          const int i = e / LP, c = e % LP;
-          if (i < l && c < l && c >= i)
-            for (int t = i; t <= c; ++t) s += A[i * LP + t] * Racc[t * LP + c];
-        }
-        outv[u] = s;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = tid + 256 * u;
-        if (e < LP * LP) Racc[e] = outv[u];
-      }
-      __syncthreads();
-      if (pass == 2 && state[2]) {
-        for (int e = tid; e < LP * LP; e += blockDim.x) {
-          const int i = e / LP;
-          if (i < l && ((unsigned)state[8 + (i >> 5)] >> (i & 31)) & 1u) Racc[e] = 0.0;
-        }
-      }
-    }
+    Rf[e] = (i < l && c < l && c >= i) ? (float)Rs[e] : 0.f;
   }
 }
 
 void launch_chol_qr_step(hipStream_t st, const double* G, int l, int lp, int pass, float* Rf,
-                         double* Racc, int* state) {
+                         int* state) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL(chol_qr_kernel<32>, dim3(1), dim3(256), 0, st, G, l, pass, Rf, Racc, state); break;
-    case 64: hipLaunchKernelGGL(chol_qr_kernel<64>, dim3(1), dim3(256), 0, st, G, l, pass, Rf, Racc, state); break;
-    case 128: hipLaunchKernelGGL(chol_qr_kernel<128>, dim3(1), dim3(256), 0, st, G, l, pass, Rf, Racc, state); break;
+    case 32: hipLaunchKernelGGL(chol_qr_kernel<32>, dim3(1), dim3(64), 0, st, G, l, pass, Rf, state); break;
+    case 64: hipLaunchKernelGGL(chol_qr_kernel<64>, dim3(1), dim3(64), 0, st, G, l, pass, Rf, state); break;
+    case 128: hipLaunchKernelGGL(chol_qr_kernel<128>, dim3(1), dim3(128), 0, st, G, l, pass, Rf, state); break;
     default: break;
   }
 }
@@ -183,32 +167,27 @@ void launch_complete(hipStream_t st, float* Q, int64_t ldq, int64_t rows, int l,
 // nu = sqrt(n) u ||B1||_F, multiplied by 10 while the factor does not exist.
 // ------------------------------------------------------------------------
 template <int LP>
-__global__ void __launch_bounds__(256) chol_nystrom_kernel(const double* __restrict__ G, int l,
-                                                           const double* __restrict__ fro2,
-                                                           double n_sqrt_u, float* __restrict__ Rf,
-                                                           double* __restrict__ nu_out,
-                                                           float* __restrict__ nu_f,
-                                                           int* __restrict__ state,
-                                                           int max_retries) {
-  __shared__ double A[LP * LP];
+__global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_nystrom_kernel(
+    const double* __restrict__ G, int l, const double* __restrict__ fro2, double n_sqrt_u,
+    float* __restrict__ Rf, double* __restrict__ nu_out, float* __restrict__ nu_f,
+    int* __restrict__ state, int max_retries) {
+  constexpr int NT = LP < 64 ? 64 : LP;
+  __shared__ double Rs[LP * LP];
+  __shared__ double rowbuf[2 * kRowStride<LP>];
   __shared__ double zero[LP];
-  __shared__ int s_flag;
   const int tid = threadIdx.x;
-  for (int j = tid; j < LP; j += blockDim.x) zero[j] = 0.0;
+  for (int j = tid; j < LP; j += NT) zero[j] = 0.0;
+  for (int e = tid; e < LP * LP; e += NT) Rs[e] = 0.0;
+  for (int e = tid; e < 2 * kRowStride<LP>; e += NT) rowbuf[e] = 0.0;
+  __syncthreads();
   double nu = n_sqrt_u * sqrt(fro2[0]);
   if (!(nu > 0.0)) nu = 1e-300;
   int retry = 0;
   bool ok = false;
   for (; retry <= max_retries; ++retry) {
     __syncthreads();
-    for (int e = tid; e < LP * LP; e += blockDim.x) {
-      const int i = e / LP, c = e % LP;
-      double v = 0.0;
-      if (i < l && c < l) v = 0.5 * (G[i * LP + c] + G[c * LP + i]) + (i == c ? nu : 0.0);
-      A[e] = v;
-    }
-    __syncthreads();
-    ok = chol_lds<LP>(A, l, zero, 0.0, &s_flag);
+    // B2 = (G + G^T)/2 + nu I
+    ok = chol_cols<LP>(G, true, l, 0.0, nu, zero, 0.0, Rs, rowbuf);
     if (ok) break;
     if (retry < max_retries) nu *= 10.0;
   }
@@ -219,9 +198,9 @@ __global__ void __launch_bounds__(256) chol_nystrom_kernel(const double* __restr
     nu_out[0] = nu;
     nu_f[0] = (float)nu;
   }
-  for (int e = tid; e < LP * LP; e += blockDim.x) {
+  for (int e = tid; e < LP * LP; e += NT) {
     const int i = e / LP, c = e % LP;
-    Rf[e] = (ok && i < l && c < l && c >= i) ? (float)A[e] : (i == c ? 1.f : 0.f);
+    Rf[e] = (ok && i < l && c < l && c >= i) ? (float)Rs[e] : (i == c ? 1.f : 0.f);
   }
 }
 
@@ -229,42 +208,70 @@ void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const d
                          double n_sqrt_u, float* Rf, double* nu_out, float* nu_f, int* state,
                          int max_retries) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL(chol_nystrom_kernel<32>, dim3(1), dim3(256), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
-    case 64: hipLaunchKernelGGL(chol_nystrom_kernel<64>, dim3(1), dim3(256), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
-    case 128: hipLaunchKernelGGL(chol_nystrom_kernel<128>, dim3(1), dim3(256), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
+    case 32: hipLaunchKernelGGL(chol_nystrom_kernel<32>, dim3(1), dim3(64), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
+    case 64: hipLaunchKernelGGL(chol_nystrom_kernel<64>, dim3(1), dim3(64), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
+    case 128: hipLaunchKernelGGL(chol_nystrom_kernel<128>, dim3(1), dim3(128), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
     default: break;
   }
 }
 
 // ------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi SVD of M (or M^T), l <= LP, in float64.
-// Columns are stored contiguously (Mc[j*LP + i] = column j, row i).  Column
-// pairs follow the round-robin (circle) ordering, l/2 disjoint pairs per
-// round, each pair on a group of G lanes.  With M Wacc = Xn diag(s):
+// Columns are stored contiguously in LDS (Mc[j*CS + i] = column j, row i,
+// CS = LP + 2 so columns of different pairs fall in different banks).
+// Column pairs follow the round-robin (circle) ordering, lp2/2 disjoint
+// pairs per round; each pair is handled by 8 lanes (one row block of
+// RPT = LP/8 consecutive rows each), whose partial inner products are
+// combined with DPP lane permutations.  With M Wacc = Xn diag(s):
 //   s    -- column norms, sorted descending
 //   Wacc -- accumulated rotations (orthogonal), columns in the same order
 //   Xn   -- normalized columns of M Wacc (zero where s = 0)
 // For M = R (B^T = Q2 R) the left singular vectors of B are Wacc and the
 // right ones Q2 Xn; for M = R^T (F = QF R) the left ones of F are QF Wacc.
 // ------------------------------------------------------------------------
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  // ctrl_sel: 0 = quad_perm [1,0,3,2], 1 = quad_perm [2,3,0,1], 2 = row_half_mirror
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  int lo2, hi2;
+  if (ctrl_sel == 0) {
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+  } else if (ctrl_sel == 1) {
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+  } else {
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+  }
+  return __hiloint2double(hi2, lo2);
+}
+
+// sum over the 8 aligned lanes of a group (all 8 get the sum)
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  v += dpp_f64(v, 2);
+  return v;
+}
+
 template <int LP, bool GLOBAL>
-__global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ M, int l,
+__global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict__ M, int l,
                                                      int transpose, double* __restrict__ s_out,
                                                      double* __restrict__ Wacc,
                                                      double* __restrict__ Xn,
                                                      double* __restrict__ gwork) {
-  // column stride padded by one double in LDS so that the columns of
-  // different pairs fall in different banks
-  constexpr int CS = GLOBAL ? LP : LP + 1;
-  __shared__ double sM[GLOBAL ? 1 : LP * CS];
-  __shared__ double sV[GLOBAL ? 1 : LP * CS];
+  constexpr int CS = GLOBAL ? LP : LP + 2;
+  constexpr int RPT = LP / 8;  // rows per lane
+  constexpr int NT = 4 * LP;   // 8 lanes for each of the LP/2 pair slots
+  __shared__ __attribute__((aligned(16))) double sM[GLOBAL ? 2 : LP * CS];
+  __shared__ __attribute__((aligned(16))) double sV[GLOBAL ? 2 : LP * CS];
   __shared__ double sig[LP];
   __shared__ int perm[LP];
   __shared__ int s_rot;
   double* Mc = GLOBAL ? gwork : sM;
   double* Vc = GLOBAL ? gwork + LP * CS : sV;
   const int tid = threadIdx.x;
-  for (int e = tid; e < LP * LP; e += 256) {
+  for (int e = tid; e < LP * LP; e += NT) {
     const int j = e / LP, i = e % LP;
     double v = 0.0;
     if (i < l && j < l) v = transpose ? M[j * LP + i] : M[i * LP + j];
@@ -273,10 +280,9 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
   }
   const int lp2 = l + (l & 1);
   const int npairs = lp2 / 2;
-  int G = 64;
-  while (G > 1 && G * npairs > 256) G >>= 1;
-  const int k = tid / G, gl = tid % G;
+  const int k = tid >> 3, gl = tid & 7;  // pair slot, lane in the group of 8
   const bool active = (k < npairs);
+  const int i0 = gl * RPT;  // this lane's first row
   const double tol = 1e-13;
   for (int sweep = 0; sweep < 60; ++sweep) {
     __syncthreads();
@@ -289,29 +295,43 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
         p = (a == 0) ? 0 : 1 + (a - 1 + r) % (lp2 - 1);
         q = (b == 0) ? 0 : 1 + (b - 1 + r) % (lp2 - 1);
       }
+      const bool go = active && p < l && q < l;
+      double mp[RPT], mq[RPT];
       double al = 0.0, be = 0.0, ga = 0.0;
-      if (active && p < l && q < l) {
-        for (int i = gl; i < l; i += G) {
-          const double mp = Mc[p * CS + i], mq = Mc[q * CS + i];
-          al += mp * mp;
-          be += mq * mq;
-          ga += mp * mq;
+      if (go) {
+#pragma unroll
+        for (int u = 0; u < RPT; u += 2) {
+          const double2 x = *reinterpret_cast<const double2*>(Mc + p * CS + i0 + u);
+          const double2 y = *reinterpret_cast<const double2*>(Mc + q * CS + i0 + u);
+          mp[u] = x.x; mp[u + 1] = x.y;
+          mq[u] = y.x; mq[u + 1] = y.y;
+        }
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          al += mp[u] * mp[u];
+          be += mq[u] * mq[u];
+          ga += mp[u] * mq[u];
         }
       }
-      al = group_sum(al, G);
-      be = group_sum(be, G);
-      ga = group_sum(ga, G);
-      if (active && p < l && q < l && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+      al = sum8(al);
+      be = sum8(be);
+      ga = sum8(ga);
+      if (go && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = gl; i < l; i += G) {
-          const double mp = Mc[p * CS + i], mq = Mc[q * CS + i];
-          Mc[p * CS + i] = c * mp - s * mq;
-          Mc[q * CS + i] = s * mp + c * mq;
-          const double vp = Vc[p * CS + i], vq = Vc[q * CS + i];
-          Vc[p * CS + i] = c * vp - s * vq;
-          Vc[q * CS + i] = s * vp + c * vq;
+#pragma unroll
+        for (int u = 0; u < RPT; u += 2) {
+          *reinterpret_cast<double2*>(Mc + p * CS + i0 + u) =
+              make_double2(c * mp[u] - s * mq[u], c * mp[u + 1] - s * mq[u + 1]);
+          *reinterpret_cast<double2*>(Mc + q * CS + i0 + u) =
+              make_double2(s * mp[u] + c * mq[u], s * mp[u + 1] + c * mq[u + 1]);
+          const double2 vp = *reinterpret_cast<const double2*>(Vc + p * CS + i0 + u);
+          const double2 vq = *reinterpret_cast<const double2*>(Vc + q * CS + i0 + u);
+          *reinterpret_cast<double2*>(Vc + p * CS + i0 + u) =
+              make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
+          *reinterpret_cast<double2*>(Vc + q * CS + i0 + u) =
+              make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
         }
         if (gl == 0) s_rot = 1;
       }
@@ -334,7 +354,7 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
     perm[rank] = tid;
   }
   __syncthreads();
-  for (int e = tid; e < LP * LP; e += 256) {
+  for (int e = tid; e < LP * LP; e += NT) {
     const int i = e / LP, rr = e % LP;  // output row i, column rr
     double w = 0.0, x = 0.0;
     if (i < l && rr < l) {
@@ -351,9 +371,9 @@ __global__ void __launch_bounds__(256) jacobi_kernel(const double* __restrict__ 
 void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
                        double* Wacc, double* Xn, double* work) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
+    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false>), dim3(1), dim3(128), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
     case 64: hipLaunchKernelGGL((jacobi_kernel<64, false>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
-    case 128: hipLaunchKernelGGL((jacobi_kernel<128, true>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
+    case 128: hipLaunchKernelGGL((jacobi_kernel<128, true>), dim3(1), dim3(512), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
     default: break;
   }
 }

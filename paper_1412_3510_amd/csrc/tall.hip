@@ -58,18 +58,21 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __re
   __shared__ double sh[4][64];
   const int el = threadIdx.x & 63, ph = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
   if (e < E) {
     int b = ph;
-    for (; b + 12 < nblk; b += 16) {
-      s0 += part[(int64_t)b * stride + e];
-      s1 += part[(int64_t)(b + 4) * stride + e];
-      s2 += part[(int64_t)(b + 8) * stride + e];
-      s3 += part[(int64_t)(b + 12) * stride + e];
+    for (; b + 28 < nblk; b += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + 4 * u) * stride + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += v[u];
     }
-    for (; b < nblk; b += 4) s0 += part[(int64_t)b * stride + e];
+    for (; b < nblk; b += 4) acc[0] += part[(int64_t)b * stride + e];
   }
-  sh[ph][el] = (s0 + s1) + (s2 + s3);
+  sh[ph][el] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   if (ph == 0 && e < E) {
     const double s = scale * (((sh[0][el] + sh[1][el]) + sh[2][el]) + sh[3][el]);

@@ -128,7 +128,8 @@ def test_orth_renorm(ctx, rows, l, cond):
     Q = Q.cpu().numpy().astype(np.float64)
     R = R.cpu().numpy()
     assert np.linalg.norm(Q.T @ Q - np.eye(l), 2) < 5e-6
-    assert np.max(np.abs(np.tril(R, -1))) == 0
+    # R = Q^T Y: upper triangular up to the rounding of Q
+    assert np.max(np.abs(np.tril(R, -1))) < 1e-5 * np.abs(R).max()
     if cond < 1e8:
         res = np.linalg.norm(Q @ R - Y) / np.linalg.norm(Y)
         assert res < 1e-5
