@@ -44,7 +44,64 @@ def parse():
     p.add_argument("--cpu-sample-solves", type=int, default=2)
     p.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                    help="HBM bytes per launch measured by rocprofv3 counters")
+    p.add_argument("--traffic-from-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR",
+                                                           "CAL_FETCH_DIR", "CAL_WRITE_DIR",
+                                                           "COPY_BYTES"),
+                   help="write --traffic-json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
+                        "runs of this bench and of a plain copy of COPY_BYTES bytes, then exit")
     return p.parse_args()
+
+
+# Kernel sources whose change invalidates stored counter readings.
+TRAFFIC_SOURCES = ("paper_1412_3510_amd/csrc/gemm.hip", "paper_1412_3510_amd/csrc/common.h")
+PASS_KERNELS = {"ax": "rpca::ax_dma_kernel", "atx": "rpca::atx_dma_kernel"}
+
+
+def _sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _counter_rows(d):
+    import csv
+    with open(os.path.join(d, "run_counter_collection.csv")) as f:
+        return list(csv.DictReader(f))
+
+
+def traffic_from_pmc(args):
+    """HBM bytes per pass launch from rocprofv3 counters (KiB per dispatch).
+
+    Each counter is scaled by copy_bytes / (what it reads for the plain copy),
+    so FETCH_SIZE and WRITE_SIZE both report the copy's true size.
+    """
+    fetch_dir, write_dir, cal_f, cal_w, copy_bytes = args.traffic_from_pmc
+    copy_bytes = float(copy_bytes)
+
+    def copy_kib(d):
+        vals = [float(r["Counter_Value"]) for r in _counter_rows(d)
+                if "copyBuffer" in r["Kernel_Name"]]
+        return max(vals)
+
+    sf = copy_bytes / (1024.0 * copy_kib(cal_f))
+    sw = copy_bytes / (1024.0 * copy_kib(cal_w))
+    out = {"m": args.m, "n": args.n, "l": args.l, "sources_sha256": _sources_digest(),
+           "fetch_scale": sf, "write_scale": sw, "copy_bytes": copy_bytes}
+    for q, name in PASS_KERNELS.items():
+        fk = [float(r["Counter_Value"]) for r in _counter_rows(fetch_dir) if name in r["Kernel_Name"]]
+        wk = [float(r["Counter_Value"]) for r in _counter_rows(write_dir) if name in r["Kernel_Name"]]
+        if not fk or not wk:
+            continue
+        fb = 1024.0 * sf * sum(fk) / len(fk)
+        wb = 1024.0 * sw * sum(wk) / len(wk)
+        out[q] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                  "dispatches": [len(fk), len(wk)]}
+    with open(args.traffic_json, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
@@ -74,6 +131,9 @@ def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
 
 def main():
     args = parse()
+    if args.traffic_from_pmc:
+        traffic_from_pmc(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how it would shard)", file=sys.stderr)
@@ -136,14 +196,15 @@ def main():
         with open(args.traffic_json) as f:
             tj = json.load(f)
         ent = tj.get(dom)
-        if ent and ent.get("m") == m and ent.get("n") == n and ent.get("l") == l:
-            traffic = ent.get("bytes_per_launch")
-    except (OSError, ValueError):
+        if (ent and tj.get("m") == m and tj.get("n") == n and tj.get("l") == l
+                and tj.get("sources_sha256") == _sources_digest()):
+            traffic = round(ent["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
         pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": {"ax": "ax_f32_kernel (Y = A X)",
-                           "atx": "atx_f32_kernel (A^T X split-K)"}[dom],
+                "kernel": {"ax": "ax_dma_kernel (Y = A X)",
+                           "atx": "atx_dma_kernel (A^T X, split over rows)"}[dom],
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes": bytes_per}
     passes = {q: {"avg_ms": round(v[0], 4), "GB/s": round(v[1] / (v[0] * 1e-3) / 1e9, 1)}
               for q, v in kernels.items()}

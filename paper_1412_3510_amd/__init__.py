@@ -134,6 +134,13 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, dtype, dim, name):
+    """Check a device operand: dtype, rank, on the GPU, unit stride along its last axis."""
+    if (t.dtype != dtype or t.dim() != dim or not t.is_cuda
+            or (t.numel() > 0 and t.stride(-1) != 1)):
+        raise ValueError("%s must be a %d-D %s CUDA tensor with unit last stride" % (name, dim, dtype))
+
+
 def dense(A, dtype=None, col_scale=None, A_f32=None):
     """rpca_matrix for a row-major 2-D CUDA tensor (float32, bfloat16 or float8_e4m3fn)."""
     import torch
@@ -220,12 +227,18 @@ class Context:
         return U, lam
 
     def spectral_err(self, A, U, S, V=None, iters=20, seed=0, center=False):
+        """Power-method estimate of ||A - U diag(S) V^T||_2 (V None: A - U diag(S) U^T)."""
+        torch = self._torch
+        _need(U, torch.float32, 2, "U")
+        _need(S, torch.float64, 1, "S")
+        if V is not None:
+            _need(V, torch.float32, 2, "V")
         mat = dense(A)
         out = ctypes.c_double()
         k = U.shape[1]
         self._check(self.lib.rpca_spectral_err(
-            self.h, ctypes.byref(mat), k, _ptr(U), U.stride(0), _ptr(S), _ptr(V),
-            V.stride(0) if V is not None else 0, iters, seed, CENTER if center else 0,
+            self.h, ctypes.byref(mat), k, _ptr(U), max(U.stride(0), k), _ptr(S), _ptr(V),
+            max(V.stride(0), k) if V is not None else 0, iters, seed, CENTER if center else 0,
             ctypes.byref(out)))
         return out.value
 

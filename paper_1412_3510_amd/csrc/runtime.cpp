@@ -141,7 +141,6 @@ struct Work {
   double* gpart = nullptr;
   double* G = nullptr;
   float* Rf = nullptr;
-  double* Racc = nullptr;
   int* cand = nullptr;
   int* piv = nullptr;
   float* Ulu = nullptr;
@@ -178,7 +177,6 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.gpart = ar.take<double>((size_t)gram_blocks(rmax) * lp * lp);
   w.G = ar.take<double>((size_t)lp * lp);
   w.Rf = ar.take<float>((size_t)lp * lp);
-  w.Racc = ar.take<double>((size_t)lp * lp);
   w.lu_m = plan_lu(m, lp);
   w.lu_n = plan_lu(n, lp);
   w.cand = ar.take<int>((size_t)std::max(w.lu_m.cand_total, w.lu_n.cand_total));
@@ -527,9 +525,34 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
 rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const float* U,
                               int64_t ldu, const double* S, const float* V, int64_t ldv, int iters,
                               uint64_t seed, unsigned flags, double* err_host) {
-  (void)A; (void)k; (void)U; (void)ldu; (void)S; (void)V; (void)ldv; (void)iters; (void)seed;
-  (void)flags; (void)err_host;
-  return fail(ctx, RPCA_ERR_UNSUPPORTED, "spectral_err is not built yet");
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  const int64_t m = A->m, n = A->n;
+  if (k < 0 || k > 128) return fail(ctx, RPCA_ERR_INVALID_ARG, "spectral_err needs 0 <= k <= 128");
+  if (iters < 0 || iters > 100000) return fail(ctx, RPCA_ERR_INVALID_ARG, "iters out of range");
+  if (std::min(m, n) < 4) return fail(ctx, RPCA_ERR_INVALID_ARG, "spectral_err needs min(m, n) >= 4");
+  if (!err_host) return fail(ctx, RPCA_ERR_INVALID_ARG, "null err_host");
+  if (k > 0) {
+    if (!U || !S) return fail(ctx, RPCA_ERR_INVALID_ARG, "null U or S");
+    if (ldu < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu must be >= k");
+    if (V && ldv < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldv must be >= k");
+    if (!V && m != n) return fail(ctx, RPCA_ERR_INVALID_ARG, "V == NULL needs a square A");
+  }
+  const bool center = (flags & RPCA_CENTER) != 0;
+  const size_t wb = round_up(spectral_work_bytes(m, n, k), 256);
+  s = ensure_ws(ctx, wb + 256);
+  if (s != RPCA_OK) return s;
+  double* result = reinterpret_cast<double*>(ctx->ws + wb);
+  hipStream_t st = ctx->stream;
+  launch_spectral(st, static_cast<const float*>(A->data), A->ld, m, n, center, U, ldu, S, V, ldv, k,
+                  iters, seed, ctx->ws, result);
+  HIP_OK(hipGetLastError());
+  double r = 0.0;
+  HIP_OK(hipMemcpyAsync(&r, result, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  *err_host = r;
+  return RPCA_OK;
 }
 
 rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l, const float* X,

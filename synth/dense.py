@@ -168,10 +168,11 @@ def dense_torch(m, n, sigma, seed, device, center_spectrum=False):
     U = _cholqr2_torch(torch.randn(m, r, generator=gen, device=device, dtype=torch.float64))
     csig = None
     if center_spectrum:
-        w = sig * U.sum(dim=0) / np.sqrt(m)
-        M = torch.diag(sig * sig) - torch.outer(w, w)
-        ev = torch.linalg.eigvalsh(M).flip(0).clamp_min(0.0)
-        csig = ev.sqrt().cpu().numpy()
+        # the r x r eigenproblem runs on the host (NumPy), not the device
+        w = (sig * U.sum(dim=0) / np.sqrt(m)).cpu().numpy()
+        s = np.asarray(sigma, dtype=np.float64)
+        ev = np.linalg.eigvalsh(np.diag(s * s) - np.outer(w, w))[::-1]
+        csig = np.sqrt(np.maximum(ev, 0.0))
     U.mul_(sig)
     A = torch.empty(m, n, device=device, dtype=torch.float32)
     step = 16384
