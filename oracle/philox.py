@@ -33,6 +33,13 @@ forms (golden ratio and sqrt(3)), bijectivity of the round on a small word
 sample, bit balance and avalanche of the output, uniformity of the words
 (chi-square), and the first four moments and a Kolmogorov-Smirnov test of the
 Gaussian map.  Published known-answer vectors are not used.
+
+Parity unpinned: the exact Philox4x32-10 word stream is not checked against
+the generator's published known-answer vectors (none are available here).
+These pins would not catch, say, a permutation of the output words; the
+method itself only needs i.i.d. N(0, 1) draws, which the statistical pins
+cover.  The library's generator is an independent implementation compared
+with this one bit for bit.
 """
 
 import numpy as np
