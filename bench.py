@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true",
                    help="skip the oracle leg (profiling runs)")
     p.add_argument("--cpu-sample-solves", type=int, default=2)
+    p.add_argument("--no-precision", action="store_true",
+                   help="skip the bfloat16 / E4M3 precision-form measurement")
+    p.add_argument("--precision-steps", type=int, default=10)
     p.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                    help="HBM bytes per launch measured by rocprofv3 counters")
     p.add_argument("--traffic-from-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR",
@@ -129,6 +132,64 @@ def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
                       "NumPy/OpenBLAS), median %.2f s" % (nsolves, A.shape[0], n, med)}, rel
 
 
+def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup):
+    """Warm up, then time ``steps`` solves on the stream with events; returns
+    (ms per solve, library stats over the timed solves)."""
+    import torch
+    for _ in range(warmup):
+        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    return e0.elapsed_time(e1) / steps, ctx.stats()
+
+
+def pass_rates(st, suffix=""):
+    out = {}
+    for q in ("ax", "atx"):
+        n_ = st["n_" + q + suffix]
+        if n_:
+            ms = st["ms_" + q + suffix] / n_
+            b = st["bytes_" + q + suffix] / n_
+            out[q] = {"avg_ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
+def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps):
+    """bfloat16 and E4M3 copies of A for the range finder, float32 A for the
+    Rayleigh-Ritz product: solves/s, pass rates and err / sigma_{k+1}."""
+    import torch
+    import paper_1412_3510_amd as rp
+    m, n = A.shape
+    res = {"f32": {"ms_per_step": round(ms_f32, 4), "err_over_sigma_k1": round(err_f32 / sk1, 5)}}
+    for kind in ("bf16", "fp8"):
+        q, sc = ctx.quantize(A, kind)
+        mat = rp.dense(q, col_scale=sc, A_f32=A)
+        U = torch.empty(m, k, device=A.device, dtype=torch.float32)
+        S = torch.empty(k, device=A.device, dtype=torch.float64)
+        V = torch.empty(n, k, device=A.device, dtype=torch.float32)
+        ms, st = time_solves(ctx, q, k, l, its, seed, (U, S, V), mat, steps, 2)
+        err = ctx.spectral_err(q, U, S, V, iters=30, seed=7, center=True, mat=mat)
+        res[kind] = {"solves_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 4),
+                     "speedup_vs_f32": round(ms_f32 / ms, 3),
+                     "err_over_sigma_k1": round(err / sk1, 5),
+                     "meets_1.1_bound": bool(err <= 1.1 * sk1),
+                     "passes_low_precision": pass_rates(st, "_lp"),
+                     "passes_f32_rayleigh_ritz": pass_rates(st)}
+        del q, sc, mat
+    return res
+
+
 def main():
     args = parse()
     if args.traffic_from_pmc:
@@ -210,6 +271,12 @@ def main():
               for q, v in kernels.items()}
 
     S_host = S.cpu().numpy()
+    sk1 = float(csig[k])
+    err_f32 = ctx.spectral_err(A, U, S, V, iters=30, seed=7, center=True)
+    prec = None
+    if not args.no_precision:
+        prec = precision_form(ctx, A, k, l, its, args.seed, sk1, ms_per_step, err_f32,
+                              args.precision_steps)
     out = {
         "metric": METRIC,
         "value": round(1e3 / ms_per_step, 3),
@@ -228,8 +295,11 @@ def main():
                    "m": m, "n": n, "k": k, "l": l, "its": its, "center": True},
         "passes": passes,
         "roofline": roofline,
-        "sigma_k_plus_1": float(csig[k]),
+        "sigma_k_plus_1": sk1,
+        "err_over_sigma_k1": round(err_f32 / sk1, 5),
     }
+    if prec is not None:
+        out["precision_form"] = prec
     if not args.no_cpu_baseline:
         cb, rel = cpu_baseline(A, k, l, its, args.seed, True, args.cpu_sample_solves, S_host)
         out["cpu_baseline"] = cb

@@ -49,11 +49,19 @@ typedef enum { RPCA_F32 = 0, RPCA_BF16 = 1, RPCA_FP8_E4M3 = 2 } rpca_dtype;
 typedef enum { RPCA_DENSE_ROWMAJOR = 0, RPCA_SPARSE_CSR = 1 } rpca_format;
 
 /* A matrix operand.  For RPCA_DENSE_ROWMAJOR, ``data`` holds m rows of n
- * elements of ``dtype`` with leading dimension ``ld``.  ``col_scale`` (FP8
- * only, length n) gives the per-column scale: A = data * diag(col_scale).
- * ``data_f32``/``ld_f32`` optionally give the float32 matrix used for the
- * final Rayleigh-Ritz product when ``dtype`` is a reduced precision (the
- * precision form); NULL means the reduced-precision data is used there too.
+ * elements of ``dtype`` with leading dimension ``ld`` (elements), in device
+ * memory owned by the caller.  ``col_scale`` (E4M3 only, device, length n)
+ * gives the per-column scale: A = data * diag(col_scale).
+ *
+ * Precision form: with dtype RPCA_BF16 or RPCA_FP8_E4M3 every pass of the
+ * range finder reads the low-precision copy (products in bfloat16 on the
+ * matrix cores, float32 accumulation), and the Rayleigh-Ritz product B = Q* A
+ * (Section 2, (i3)), the Nystrom product B1 = A Q (Section 3, (start)) and
+ * rpca_spectral_err read ``data_f32``/``ld_f32``, the float32 A, when it is
+ * given; NULL means the low-precision copy is used there too (spectral_err
+ * then returns RPCA_ERR_UNSUPPORTED).  Low-precision copies need n and ld to
+ * be multiples of 8 (bfloat16) or 16 (E4M3) and 16-byte-aligned data, else
+ * RPCA_ERR_UNSUPPORTED.  rpca_quantize prepares both copies.
  * The sparse fields are reserved for the CSR format. */
 typedef struct {
   int32_t format; /* rpca_format */
@@ -124,6 +132,18 @@ rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const f
                               int64_t ldu, const double* S, const float* V, int64_t ldv,
                               int iters, uint64_t seed, unsigned flags, double* err_host);
 
+/* Precision preparation, once per matrix (not part of a solve).  A is float32
+ * m x n row-major (device, leading dimension lda); ``out`` (device, leading
+ * dimension ldo elements) receives
+ *   RPCA_BF16:     bfloat16(a_ij), rounded to nearest even;
+ *   RPCA_FP8_E4M3: E4M3(a_ij / s_j), rounded to nearest even, with
+ *                  s_j = max_i |a_ij| / 448 (1 for a zero column) written to
+ *                  col_scale (device, length n), so |a_ij / s_j| <= 448.
+ * E4M3 is the OCP 8-bit format (bias 7, largest finite 448, no infinities).
+ * Stream-ordered; uses the context workspace for the E4M3 column maxima. */
+rpca_status rpca_quantize(rpca_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                          rpca_dtype dtype, void* out, int64_t ldo, float* col_scale);
+
 /* The Gaussian test matrix alone: out[i*ldo + j] = z[j*n + i] for i < n,
  * j < l, where z is Philox4x32-10 stream ``stream`` under key ``seed`` mapped
  * through the Box-Muller transform (evaluated in float64, rounded to float32).
@@ -166,6 +186,10 @@ typedef struct {
   double bytes_ax;        /* algorithmic bytes of the timed A X launches      */
   double bytes_atx;       /* algorithmic bytes of the timed A^T X launches    */
   int64_t shift_retries;  /* Nystrom shift retries (last call)               */
+  /* the same for passes over a bfloat16 / E4M3 copy of A                    */
+  double ms_ax_lp, ms_atx_lp;
+  int64_t n_ax_lp, n_atx_lp;
+  double bytes_ax_lp, bytes_atx_lp;
 } rpca_stats;
 
 /* Record HIP events around every A-pass kernel launch (on the context

@@ -20,9 +20,11 @@ Modules
   nystrom   -- shift-stabilized Nystrom method for PSD matrices (Section 3).
   spectral  -- spectral-norm error: exact and randomized power method
                (Section 4).
+  precision -- bfloat16 and E4M3 (column-scaled) copies of A for the
+               precision form of the range finder.
 
 Parity status: every function is pinned by CPU tests in ``tests/`` against
 brute force, closed forms and invariants; see the header of each module.
 """
 
-from . import philox, rsvd, nystrom, spectral  # noqa: F401
+from . import philox, precision, rsvd, nystrom, spectral  # noqa: F401

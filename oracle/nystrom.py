@@ -55,9 +55,11 @@ def shift0(B1, n, u_A):
     return float(np.sqrt(n) * u_A * np.linalg.norm(B1))
 
 
-def eig_psd(A, k, l, its, omega, u_A=2.0 ** -24, max_retries=10):
+def eig_psd(A, k, l, its, omega, u_A=2.0 ** -24, max_retries=10, A_range=None):
     """Rank-k approximation U diag(lam) U^T of the PSD matrix A.
 
+    ``A_range`` (optional) is the matrix the range finder applies instead of
+    A (a rounded copy, see ``oracle.precision``); B1 = A Q always uses A.
     Returns (U n x k, lam length k, nu used, retries).
     Raises np.linalg.LinAlgError if the shifted B2 is never positive definite.
     """
@@ -67,7 +69,7 @@ def eig_psd(A, k, l, its, omega, u_A=2.0 ** -24, max_retries=10):
         raise ValueError("A must be square")
     if not (1 <= k <= l <= n):
         raise ValueError("need 1 <= k <= l <= n")
-    Q = range_psd(A, l, its, omega)
+    Q = range_psd(A if A_range is None else A_range, l, its, omega)
     B1 = A @ Q                                   # (start)
     nu = shift0(B1, n, u_A)
     for retry in range(max_retries + 1):

@@ -64,13 +64,16 @@ def sign_fix(U, V=None):
     return U, V * s
 
 
-def rsvd(A, k, l, its, omega, center=False, renorm="lu"):
+def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
     """Rank-k approximation U diag(S) V^T of A (or of its column-centered form).
 
-    A      -- m x n array (the exact values the device sees; upcast to float64)
-    omega  -- n x l test matrix (float32 values from ``oracle.philox.omega``)
-    renorm -- "lu" (the paper's choice) or "qr" (Householder everywhere; equal
-              to "lu" in exact arithmetic by span invariance)
+    A       -- m x n array (the exact values the device sees; upcast to float64)
+    omega   -- n x l test matrix (float32 values from ``oracle.philox.omega``)
+    renorm  -- "lu" (the paper's choice) or "qr" (Householder everywhere; equal
+               to "lu" in exact arithmetic by span invariance)
+    A_range -- optional m x n matrix the range finder applies instead of A
+               (a rounded copy of A, see ``oracle.precision``); the
+               Rayleigh-Ritz product B = Q* A always uses A
 
     Returns (U m x k, S length k, V n x k), all float64.
     """
@@ -78,20 +81,24 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu"):
     m, n = A.shape
     if not (1 <= k <= l <= min(m, n)):
         raise ValueError("need 1 <= k <= l <= min(m, n)")
+    R = A if A_range is None else np.asarray(A_range, dtype=np.float64)
+    if R.shape != A.shape:
+        raise ValueError("A_range must have the shape of A")
     if center:
         # PCA after subtracting from each column its mean (Section 2).
         A = A - A.mean(axis=0, keepdims=True)
+        R = A if A_range is None else R - R.mean(axis=0, keepdims=True)
     omega = np.asarray(omega, dtype=np.float64)
     mid = lu_renorm if renorm == "lu" else qr_renorm
 
     # Apply A to l random vectors (Section 2, range finder).
-    Y = A @ omega
+    Y = R @ omega
     Q = qr_renorm(Y) if its == 0 else mid(Y)
     for it in range(1, its + 1):
         # Apply A* as (Q* A)* without forming A* (Section 5).
-        Z = (Q.T @ A).T
+        Z = (Q.T @ R).T
         Q = mid(Z)
-        Y = A @ Q
+        Y = R @ Q
         # LU in all but the last iteration, QR in the last (Section 5).
         Q = mid(Y) if it < its else qr_renorm(Y)
 

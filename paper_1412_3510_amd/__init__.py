@@ -73,6 +73,12 @@ class Stats(ctypes.Structure):
         ("bytes_ax", ctypes.c_double),
         ("bytes_atx", ctypes.c_double),
         ("shift_retries", ctypes.c_int64),
+        ("ms_ax_lp", ctypes.c_double),
+        ("ms_atx_lp", ctypes.c_double),
+        ("n_ax_lp", ctypes.c_int64),
+        ("n_atx_lp", ctypes.c_int64),
+        ("bytes_ax_lp", ctypes.c_double),
+        ("bytes_atx_lp", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -94,6 +100,7 @@ _SIGS = {
     "rpca_spectral_err": [P, ctypes.POINTER(Matrix), I32, P, I64, P, P, I64, I32, U64,
                           ctypes.c_uint, ctypes.POINTER(D)],
     "rpca_gaussian": [P, U64, U32, I64, I64, P, I64, P],
+    "rpca_quantize": [P, P, I64, I64, I64, I32, P, I64, P],
     "rpca_op_matmul": [P, ctypes.POINTER(Matrix), I32, I32, P, I64, P, I64, ctypes.c_uint],
     "rpca_op_renorm": [P, I32, I64, I32, P, I64, P, P],
     "rpca_op_small_svd": [P, I32, P, P, P, P],
@@ -215,25 +222,25 @@ class Context:
                                       _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0)))
         return U, S, V
 
-    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False):
+    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None):
         torch = self._torch
         n = A.shape[0]
         l = k + 2 if l is None else l
         U = torch.empty(n, k, device=A.device, dtype=torch.float32)
         lam = torch.empty(k, device=A.device, dtype=torch.float64)
-        mat = dense(A)
+        mat = dense(A) if mat is None else mat
         self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed,
                                           SYNC if sync else 0, _ptr(U), U.stride(0), _ptr(lam)))
         return U, lam
 
-    def spectral_err(self, A, U, S, V=None, iters=20, seed=0, center=False):
+    def spectral_err(self, A, U, S, V=None, iters=20, seed=0, center=False, mat=None):
         """Power-method estimate of ||A - U diag(S) V^T||_2 (V None: A - U diag(S) U^T)."""
         torch = self._torch
         _need(U, torch.float32, 2, "U")
         _need(S, torch.float64, 1, "S")
         if V is not None:
             _need(V, torch.float32, 2, "V")
-        mat = dense(A)
+        mat = dense(A) if mat is None else mat
         out = ctypes.c_double()
         k = U.shape[1]
         self._check(self.lib.rpca_spectral_err(
@@ -241,6 +248,26 @@ class Context:
             max(V.stride(0), k) if V is not None else 0, iters, seed, CENTER if center else 0,
             ctypes.byref(out)))
         return out.value
+
+    def quantize(self, A, dtype):
+        """Low-precision copy of a float32 CUDA matrix: ``"bf16"`` -> (bfloat16 tensor, None),
+        ``"fp8"`` -> (float8_e4m3fn tensor, float32 column scales)."""
+        torch = self._torch
+        _need(A, torch.float32, 2, "A")
+        m, n = A.shape
+        if dtype == "bf16":
+            out = torch.empty(m, n, device=A.device, dtype=torch.bfloat16)
+            scale = None
+            code = BF16
+        elif dtype == "fp8":
+            out = torch.empty(m, n, device=A.device, dtype=torch.float8_e4m3fn)
+            scale = torch.empty(n, device=A.device, dtype=torch.float32)
+            code = FP8_E4M3
+        else:
+            raise ValueError("dtype must be 'bf16' or 'fp8'")
+        self._check(self.lib.rpca_quantize(self.h, _ptr(A), m, n, A.stride(0), code, _ptr(out),
+                                           out.stride(0), _ptr(scale)))
+        return out, scale
 
     # ---- single steps --------------------------------------------------
     def gaussian(self, seed, n, l, stream=0, words=False):
@@ -253,12 +280,12 @@ class Context:
                                            _ptr(w)))
         return (out, w) if words else out
 
-    def matmul(self, A, X, trans=False, center=False):
+    def matmul(self, A, X, trans=False, center=False, mat=None):
         torch = self._torch
         m, n = A.shape
         l = X.shape[1]
         Y = torch.empty(n if trans else m, l, device=A.device, dtype=torch.float32)
-        mat = dense(A)
+        mat = dense(A) if mat is None else mat
         self._check(self.lib.rpca_op_matmul(self.h, ctypes.byref(mat), 1 if trans else 0, l,
                                             _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
                                             CENTER if center else 0))

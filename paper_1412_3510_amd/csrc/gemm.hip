@@ -23,19 +23,10 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "dma.h"
 #include "kernels.h"
 
 namespace rpca {
-
-static constexpr int kFragElems = 512;  // bf16 per 1 KB fragment
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of logical tile ids so tiles that share operands share an
-// L2.
-__device__ __forceinline__ int xcd_remap(int b, int nwg) {
-  if (nwg % 8 != 0) return b;
-  return (b % 8) * (nwg / 8) + b / 8;
-}
 
 __device__ __forceinline__ f32x16 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
                                         const bf16x8& bl, f32x16 acc) {
@@ -218,36 +209,6 @@ __global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A
 // memory; the entries this brings in for rows or columns outside A are
 // multiplied by zero rows of packed X or never stored.
 // ========================================================================
-typedef __attribute__((address_space(3))) char lds_char;
-
-// 16 bytes per lane, global -> LDS at lds_block + 16 * lane.  Written as
-// inline assembly (M0 = LDS base, no VGPR result) so that the compiler does
-// not guard every later LDS read with a wait for all outstanding copies; the
-// kernels wait for exactly the stage they read with wait_vm_barrier.
-__device__ __forceinline__ void dma16(const void* g, char* lds_block) {
-  const unsigned la = __builtin_amdgcn_readfirstlane((unsigned)(size_t)((lds_char*)lds_block));
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(la)
-               : "memory", "m0");
-}
-
-// Wait until at most N DMA instructions of this wave are outstanding, then
-// synchronize the workgroup.  The memory clobber keeps LDS reads below.
-template <int N>
-__device__ __forceinline__ void wait_vm_barrier() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
-}
-__device__ __forceinline__ void barrier_mem() { asm volatile("s_barrier" ::: "memory"); }
-
-template <int PER, int S>
-__device__ __forceinline__ void wait_ahead(int ahead) {
-  // ahead = number of later stages already issued (0 .. S-1)
-  if (ahead <= 0) wait_vm_barrier<0>();
-  else if (ahead == 1) wait_vm_barrier<PER>();
-  else if (ahead == 2) wait_vm_barrier<(S >= 3 ? 2 * PER : PER)>();
-  else wait_vm_barrier<(S >= 4 ? 3 * PER : (S >= 3 ? 2 * PER : PER))>();
-}
-
 // ---------------- Y = A X --------------------------------------------------
 // Stage: 32 columns of a 128-row tile (16 KB of A, rows 8b..8b+7 per 1 KB DMA
 // block b; the 16-byte chunk c of row R sits at position c ^ ((R >> 1) & 7))
@@ -609,12 +570,14 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
     for (int r = 0; r < 16; ++r) out[(cb * 16 + r) * 64 + lane] = acc[cb][r];
 }
 
-AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus) {
+AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
   AtxPlan p;
   p.ntiles = (int)ceil_div(n, 128);
-  const int64_t stages = ceil_div(m, 32);
+  const int rs = dtype == 0 ? 32 : lp_rows_per_stage(dtype);  // rows per stage
+  const int64_t stages = ceil_div(m, rs);
   // workgroups resident per CU for the LDS ring of the DMA kernel
-  const int per_cu = std::max(1, (160 * 1024) / (ring_depth(nb) * dma_stage_bytes(nb)));
+  const int per_cu = dtype == 0 ? std::max(1, (160 * 1024) / (ring_depth(nb) * dma_stage_bytes(nb)))
+                                : lp_per_cu(nb, dtype);
   int64_t want = (int64_t)per_cu * num_cus / p.ntiles;
   if (want < 1) want = 1;
   int64_t maxs = stages / 4;
@@ -622,7 +585,7 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus) {
   if (want > maxs) want = maxs;
   int64_t per = ceil_div(stages, want);
   p.nsplit = (int)ceil_div(stages, per);
-  p.rows_per = per * 32;
+  p.rows_per = per * rs;
   p.partial_bytes = (size_t)p.nsplit * p.ntiles * 4 * nb * 1024 * sizeof(float);
   return p;
 }

@@ -30,13 +30,29 @@ struct AtxPlan {
   int64_t rows_per;  // rows per split (multiple of 32)
   size_t partial_bytes;
 };
-AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus);
+// dtype: 0 float32, 1 bfloat16, 2 E4M3 (the copy of A the pass reads)
+AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype);
 void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                 const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
 // Z (n x 32*nb) = sum of the partials (fixed order); ``cscale`` (nullable,
 // float[n]) multiplies row j of Z.
 void launch_atx_reduce(hipStream_t st, const float* P, const AtxPlan& plan, int nb, int64_t n,
                        const float* cscale, float* Z, int64_t ldz);
+
+// ---- passes over a bfloat16 / E4M3 copy of A (gemm_lp.hip) -------------------
+// Shape rule of the low-precision kernels: n and lda multiples of 16 bytes of
+// elements, A 16-byte aligned.
+bool lp_shape_ok(const void* A, int dtype, int64_t lda, int64_t n);
+int lp_rows_per_stage(int dtype);
+int lp_per_cu(int nb, int dtype);
+void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+                  const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus);
+void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+                   const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
+// float32 A -> bfloat16 (dtype 1) or E4M3 with column scales (dtype 2)
+size_t quantize_work_bytes(int64_t m, int64_t n);
+void launch_quantize(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, int dtype,
+                     void* out, int64_t ldo, float* scale, float* work);
 
 // ---- tall-skinny helpers (tall.hip) -------------------------------------------
 // mu[c] = mean over rows of X[:, c] for c < cols (float64 accumulation).

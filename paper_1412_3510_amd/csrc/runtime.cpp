@@ -20,7 +20,7 @@ namespace {
 
 struct TimedLaunch {
   hipEvent_t a, b;
-  int kind;  // 0 = A X, 1 = A^T X
+  int kind;  // 0 = A X, 1 = A^T X (float32 A); 2, 3 the same on a low-precision copy
   double bytes;
 };
 
@@ -152,11 +152,40 @@ struct Work {
   int* signwork = nullptr;
   double* scal = nullptr;  // [0] fro2, [1] nu
   float* nu_f = nullptr;
-  AtxPlan atx{};
+  AtxPlan atx{};     // plan for the copy of A the range finder reads
+  AtxPlan atx_rr{};  // plan for the float32 copy of the Rayleigh-Ritz pass
   LuPlan lu_m{}, lu_n{};
 };
 
-void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool need_y2) {
+// The copy of A one pass reads: float32, bfloat16 or E4M3 with column scales.
+struct AView {
+  const void* data;
+  int dtype;
+  int64_t ld, m, n;
+  const float* scale;  // E4M3: A = data diag(scale)
+};
+
+AView native_view(const rpca_matrix* A) {
+  return {A->data, (int)A->dtype, A->ld, A->m, A->n,
+          A->dtype == RPCA_FP8_E4M3 ? A->col_scale : nullptr};
+}
+
+// The Rayleigh-Ritz product (and the Nystrom B1 = A Q) read the float32 A of
+// a low-precision matrix when one is given.
+AView rr_view(const rpca_matrix* A) {
+  if (A->dtype != RPCA_F32 && A->data_f32)
+    return {A->data_f32, (int)RPCA_F32, A->ld_f32, A->m, A->n, nullptr};
+  return native_view(A);
+}
+
+int elem_bytes(int dtype) { return dtype == RPCA_F32 ? 4 : (dtype == RPCA_BF16 ? 2 : 1); }
+
+// packed-operand steps for ``rows`` rows: K16 steps rounded up to whole
+// stages of every pass kernel (8 steps = 128 rows)
+int64_t pack_steps(int64_t rows) { return round_up(ceil_div(rows, 16), 8); }
+
+void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool need_y2,
+            int dtype) {
   w.l = l;
   w.lp = lp_of(l);
   w.nb = w.lp / 32;
@@ -167,10 +196,10 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.Z = ar.take<float>((size_t)round_up(n, 32) * lp);
   if (need_y2) w.Y2 = ar.take<float>((size_t)round_up(m, 32) * lp);
   w.Bk = ar.take<float>((size_t)round_up(rmax, 32) * lp);
-  const int64_t steps = 2 * ceil_div(rmax, 32);
-  w.Xp = ar.take<__bf16>(packed_bytes(steps, w.nb) / sizeof(__bf16));
-  w.atx = plan_atx(m, n, w.nb, num_cus);
-  w.P = ar.take<float>(w.atx.partial_bytes / sizeof(float));
+  w.Xp = ar.take<__bf16>(packed_bytes(pack_steps(rmax), w.nb) / sizeof(__bf16));
+  w.atx = plan_atx(m, n, w.nb, num_cus, dtype);
+  w.atx_rr = plan_atx(m, n, w.nb, num_cus, RPCA_F32);
+  w.P = ar.take<float>(std::max(w.atx.partial_bytes, w.atx_rr.partial_bytes) / sizeof(float));
   w.mu = ar.take<float>(128);
   w.colpart = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
   w.colpart2 = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
@@ -192,21 +221,18 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.nu_f = ar.take<float>(4);
 }
 
-rpca_status prepare(rpca_ctx ctx, Work& w, int64_t m, int64_t n, int l, bool need_y2) {
+rpca_status prepare(rpca_ctx ctx, Work& w, int64_t m, int64_t n, int l, bool need_y2,
+                    int dtype = RPCA_F32) {
   Arena probe;
-  layout(probe, w, m, n, l, ctx->num_cus, need_y2);
+  layout(probe, w, m, n, l, ctx->num_cus, need_y2, dtype);
   rpca_status s = ensure_ws(ctx, probe.off + 256);
   if (s != RPCA_OK) return s;
   s = ensure_counters(ctx, (size_t)std::max(w.lu_m.counter_total, w.lu_n.counter_total) + 16);
   if (s != RPCA_OK) return s;
   Arena real;
   real.base = ctx->ws;
-  layout(real, w, m, n, l, ctx->num_cus, need_y2);
+  layout(real, w, m, n, l, ctx->num_cus, need_y2, dtype);
   return RPCA_OK;
-}
-
-bool dense_f32(const rpca_matrix* A) {
-  return A->format == RPCA_DENSE_ROWMAJOR && A->dtype == RPCA_F32;
 }
 
 rpca_status check_matrix(rpca_ctx ctx, const rpca_matrix* A) {
@@ -214,10 +240,18 @@ rpca_status check_matrix(rpca_ctx ctx, const rpca_matrix* A) {
   if (A->m <= 0 || A->n <= 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "A must have m, n >= 1");
   if (A->format != RPCA_DENSE_ROWMAJOR)
     return fail(ctx, RPCA_ERR_UNSUPPORTED, "only dense row-major A is supported in this build");
-  if (A->dtype != RPCA_F32)
-    return fail(ctx, RPCA_ERR_UNSUPPORTED, "only float32 A is supported in this build");
   if (!A->data) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->data is null");
   if (A->ld < A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->ld < n");
+  if (A->dtype == RPCA_BF16 || A->dtype == RPCA_FP8_E4M3) {
+    if (!lp_shape_ok(A->data, A->dtype, A->ld, A->n))
+      return fail(ctx, RPCA_ERR_UNSUPPORTED,
+                  "low-precision A needs n and ld multiples of 16 bytes and 16-byte alignment");
+    if (A->dtype == RPCA_FP8_E4M3 && !A->col_scale)
+      return fail(ctx, RPCA_ERR_INVALID_ARG, "E4M3 A needs col_scale");
+    if (A->data_f32 && A->ld_f32 < A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->ld_f32 < n");
+  } else if (A->dtype != RPCA_F32) {
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "unknown dtype");
+  }
   if (A->m > (int64_t)1 << 30 || A->n > (int64_t)1 << 30)
     return fail(ctx, RPCA_ERR_UNSUPPORTED, "dimensions above 2^30");
   return RPCA_OK;
@@ -239,22 +273,34 @@ void end_timed(rpca_ctx ctx, TimedLaunch& t) {
   ctx->pending.push_back(t);
 }
 
-void run_ax(rpca_ctx ctx, const rpca_matrix* A, const Work& w, const __bf16* Xp, float* Y) {
+// Algorithmic bytes of one pass: A once, the packed operand once (4 bytes a
+// value for the float32 kernels' hi/lo pairs, 2 for the high part alone),
+// the output once.
+void run_ax(rpca_ctx ctx, const AView& A, const Work& w, const __bf16* Xp, float* Y) {
   TimedLaunch t;
-  const double bytes = (double)A->m * A->n * 4.0 + (double)A->n * w.lp * 4.0 +
-                       (double)A->m * w.lp * 4.0;
-  begin_timed(ctx, t, 0, bytes);
-  launch_ax(ctx->stream, A->data, A->dtype, A->ld, A->m, A->n, Xp, Y, w.lp, w.nb, ctx->num_cus);
+  const double xb = (A.dtype == RPCA_F32) ? 4.0 : 2.0;
+  const double bytes = (double)A.m * A.n * elem_bytes(A.dtype) + (double)A.n * w.lp * xb +
+                       (double)A.m * w.lp * 4.0;
+  begin_timed(ctx, t, A.dtype == RPCA_F32 ? 0 : 2, bytes);
+  if (A.dtype == RPCA_F32)
+    launch_ax(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus);
+  else
+    launch_ax_lp(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus);
   end_timed(ctx, t);
   ctx->stats.a_passes++;
 }
 
-void run_atx(rpca_ctx ctx, const rpca_matrix* A, const Work& w, const __bf16* Qp) {
+void run_atx(rpca_ctx ctx, const AView& A, const Work& w, const __bf16* Qp) {
   TimedLaunch t;
-  const double bytes = (double)A->m * A->n * 4.0 + (double)A->m * w.lp * 4.0 +
-                       (double)w.atx.partial_bytes;
-  begin_timed(ctx, t, 1, bytes);
-  launch_atx(ctx->stream, A->data, A->dtype, A->ld, A->m, A->n, Qp, w.P, w.atx, w.nb);
+  const AtxPlan& plan = (A.dtype == RPCA_F32) ? w.atx_rr : w.atx;
+  const double xb = (A.dtype == RPCA_F32) ? 4.0 : 2.0;
+  const double bytes = (double)A.m * A.n * elem_bytes(A.dtype) + (double)A.m * w.lp * xb +
+                       (double)plan.partial_bytes;
+  begin_timed(ctx, t, A.dtype == RPCA_F32 ? 1 : 3, bytes);
+  if (A.dtype == RPCA_F32)
+    launch_atx(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Qp, w.P, plan, w.nb);
+  else
+    launch_atx_lp(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Qp, w.P, plan, w.nb);
   end_timed(ctx, t);
   ctx->stats.a_passes++;
 }
@@ -297,16 +343,18 @@ void pack_m_side(rpca_ctx ctx, Work& w, const float* Q, int64_t m, bool center) 
     launch_colmean(ctx->stream, Q, w.lp, m, w.l, w.colpart, 0, w.mu);
     mu = w.mu;
   }
-  launch_pack(ctx->stream, Q, w.lp, m, w.l, w.nb, mu, nullptr, w.Xp, 2 * ceil_div(m, 32));
+  launch_pack(ctx->stream, Q, w.lp, m, w.l, w.nb, mu, nullptr, w.Xp, pack_steps(m));
 }
 
-void pack_n_side(rpca_ctx ctx, Work& w, const float* X, int64_t n) {
-  launch_pack(ctx->stream, X, w.lp, n, w.l, w.nb, nullptr, nullptr, w.Xp, 2 * ceil_div(n, 32));
+// X (n side) -> packed operand for A X; E4M3 column scales fold into X's rows.
+void pack_n_side(rpca_ctx ctx, Work& w, const float* X, int64_t n, const AView& A) {
+  launch_pack(ctx->stream, X, w.lp, n, w.l, w.nb, nullptr, A.scale, w.Xp, pack_steps(n));
 }
 
-void apply_at(rpca_ctx ctx, const rpca_matrix* A, Work& w, float* Z) {
+void apply_at(rpca_ctx ctx, const AView& A, Work& w, float* Z) {
   run_atx(ctx, A, w, w.Xp);
-  launch_atx_reduce(ctx->stream, w.P, w.atx, w.nb, A->n, nullptr, Z, w.lp);
+  const AtxPlan& plan = (A.dtype == RPCA_F32) ? w.atx_rr : w.atx;
+  launch_atx_reduce(ctx->stream, w.P, plan, w.nb, A.n, A.scale, Z, w.lp);
 }
 
 rpca_status check_kl(rpca_ctx ctx, int k, int& l, int64_t m, int64_t n) {
@@ -401,8 +449,28 @@ rpca_status rpca_workspace_size(rpca_ctx ctx, const rpca_matrix* A, int k, int l
   if (s != RPCA_OK) return s;
   Work w;
   Arena probe;
-  layout(probe, w, A->m, A->n, l, ctx->num_cus, true);
+  layout(probe, w, A->m, A->n, l, ctx->num_cus, true, A->dtype);
   *bytes = probe.off + 256;
+  return RPCA_OK;
+}
+
+rpca_status rpca_quantize(rpca_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                          rpca_dtype dtype, void* out, int64_t ldo, float* col_scale) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (!A || !out || m < 1 || n < 1 || lda < n || ldo < n)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "bad quantize arguments");
+  if (dtype != RPCA_BF16 && dtype != RPCA_FP8_E4M3)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "quantize: dtype must be RPCA_BF16 or RPCA_FP8_E4M3");
+  if (dtype == RPCA_FP8_E4M3 && !col_scale)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "quantize: E4M3 needs col_scale");
+  if (m * n > ((int64_t)1 << 40)) return fail(ctx, RPCA_ERR_UNSUPPORTED, "quantize: too large");
+  if (dtype == RPCA_FP8_E4M3) {
+    rpca_status s = ensure_ws(ctx, quantize_work_bytes(m, n) + 256);
+    if (s != RPCA_OK) return s;
+  }
+  launch_quantize(ctx->stream, A, lda, m, n, dtype, out, ldo, col_scale,
+                  reinterpret_cast<float*>(ctx->ws));
+  HIP_OK(hipGetLastError());
   return RPCA_OK;
 }
 
@@ -427,35 +495,37 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   const int64_t m = A->m, n = A->n;
   const bool center = (flags & RPCA_CENTER) != 0;
   Work w;
-  s = prepare(ctx, w, m, n, l, false);
+  s = prepare(ctx, w, m, n, l, false, A->dtype);
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
   ctx->stats.calls++;
+  const AView Av = native_view(A);  // range finder
+  const AView Ar = rr_view(A);      // Rayleigh-Ritz product
 
   // Omega (n x l, zero padded to lp) -> packed right operand
   HIP_OK(hipMemsetAsync(w.Z, 0, (size_t)n * w.lp * sizeof(float), st));
   launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
-  pack_n_side(ctx, w, w.Z, n);
+  pack_n_side(ctx, w, w.Z, n, Av);
   // Y = A Omega
-  run_ax(ctx, A, w, w.Xp, w.Y);
+  run_ax(ctx, Av, w, w.Xp, w.Y);
   if (center) center_rows(ctx, w, w.Y, m);
   if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
   else lu_renorm(ctx, w, w.Y, m);
   for (int it = 1; it <= its; ++it) {
     // Z = A^T Q, renormalized by LU
     pack_m_side(ctx, w, w.Y, m, center);
-    apply_at(ctx, A, w, w.Z);
+    apply_at(ctx, Av, w, w.Z);
     lu_renorm(ctx, w, w.Z, n);
     // Y = A Q; LU except after the last application, which is orthonormalized
-    pack_n_side(ctx, w, w.Z, n);
-    run_ax(ctx, A, w, w.Xp, w.Y);
+    pack_n_side(ctx, w, w.Z, n, Av);
+    run_ax(ctx, Av, w, w.Xp, w.Y);
     if (center) center_rows(ctx, w, w.Y, m);
     if (it < its) lu_renorm(ctx, w, w.Y, m);
     else orth_renorm(ctx, w, w.Y, m, false, seed);
   }
   // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
   pack_m_side(ctx, w, w.Y, m, center);
-  apply_at(ctx, A, w, w.Z);
+  apply_at(ctx, Ar, w, w.Z);
   orth_renorm(ctx, w, w.Z, n, true, seed + 1);
   launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
   // U = Q W, V = Q2 X, S = top k
@@ -482,27 +552,30 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   if (flags & RPCA_CENTER) return fail(ctx, RPCA_ERR_INVALID_ARG, "centering does not apply to eig_psd");
   const int64_t n = A->n;
   Work w;
-  s = prepare(ctx, w, n, n, l, true);
+  s = prepare(ctx, w, n, n, l, true, A->dtype);
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
   ctx->stats.calls++;
+  const AView Av = native_view(A);  // the self-adjoint range finder
+  const AView Ar = rr_view(A);      // B1 = A Q
 
   // Q = Omega; its times Q = A Q renormalized (LU, QR after the last).
   HIP_OK(hipMemsetAsync(w.Y, 0, (size_t)n * w.lp * sizeof(float), st));
   launch_gaussian(st, seed, 0u, n, l, w.Y, w.lp, nullptr);
   if (its == 0) orth_renorm(ctx, w, w.Y, n, false, seed);
   for (int it = 1; it <= its; ++it) {
-    pack_n_side(ctx, w, w.Y, n);
-    run_ax(ctx, A, w, w.Xp, w.Y);
+    pack_n_side(ctx, w, w.Y, n, Av);
+    run_ax(ctx, Av, w, w.Xp, w.Y);
     if (it < its) lu_renorm(ctx, w, w.Y, n);
     else orth_renorm(ctx, w, w.Y, n, false, seed);
   }
   // B1 = A Q (start); B2 = Q* B1 (second), shifted; C = chol (Cholesky)
-  pack_n_side(ctx, w, w.Y, n);
-  run_ax(ctx, A, w, w.Xp, w.Y2);
+  pack_n_side(ctx, w, w.Y, n, Ar);
+  run_ax(ctx, Ar, w, w.Xp, w.Y2);
   launch_fro2_d(st, w.Y2, w.lp, n, l, w.colpart, w.colpart2, w.scal);
   launch_gram(st, w.Y, w.lp, n, w.lp, w.Y2, w.lp, w.gpart, w.G, nullptr);
-  const double u = std::ldexp(1.0, -24);
+  // unit roundoff of the copy of A that B1 was computed from
+  const double u = std::ldexp(1.0, Ar.dtype == RPCA_F32 ? -24 : (Ar.dtype == RPCA_BF16 ? -8 : -4));
   launch_chol_nystrom(st, w.G, l, w.lp, w.scal, std::sqrt((double)n) * u, w.Rf, w.scal + 1,
                       w.nu_f, w.state, 10);
   // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
@@ -540,12 +613,15 @@ rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const f
     if (!V && m != n) return fail(ctx, RPCA_ERR_INVALID_ARG, "V == NULL needs a square A");
   }
   const bool center = (flags & RPCA_CENTER) != 0;
+  const AView Ar = rr_view(A);
+  if (Ar.dtype != RPCA_F32)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "spectral_err reads float32 A (give data_f32)");
   const size_t wb = round_up(spectral_work_bytes(m, n, k), 256);
   s = ensure_ws(ctx, wb + 256);
   if (s != RPCA_OK) return s;
   double* result = reinterpret_cast<double*>(ctx->ws + wb);
   hipStream_t st = ctx->stream;
-  launch_spectral(st, static_cast<const float*>(A->data), A->ld, m, n, center, U, ldu, S, V, ldv, k,
+  launch_spectral(st, static_cast<const float*>(Ar.data), Ar.ld, m, n, center, U, ldu, S, V, ldv, k,
                   iters, seed, ctx->ws, result);
   HIP_OK(hipGetLastError());
   double r = 0.0;
@@ -567,9 +643,10 @@ rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l,
   if (ldx < l || ldy < l) return fail(ctx, RPCA_ERR_INVALID_ARG, "ld < l");
   const bool center = (flags & RPCA_CENTER) != 0;
   Work w;
-  s = prepare(ctx, w, m, n, l, false);
+  s = prepare(ctx, w, m, n, l, false, A->dtype);
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
+  const AView Av = native_view(A);
   // copy X into the lp-padded tall buffer
   float* Xt = trans ? w.Y : w.Z;
   HIP_OK(hipMemsetAsync(Xt, 0, (size_t)xr * w.lp * sizeof(float), st));
@@ -578,10 +655,10 @@ rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l,
   float* Yt = trans ? w.Z : w.Y;
   if (trans) {
     pack_m_side(ctx, w, Xt, m, center);
-    apply_at(ctx, A, w, Yt);
+    apply_at(ctx, Av, w, Yt);
   } else {
-    pack_n_side(ctx, w, Xt, n);
-    run_ax(ctx, A, w, w.Xp, Yt);
+    pack_n_side(ctx, w, Xt, n, Av);
+    run_ax(ctx, Av, w, w.Xp, Yt);
     if (center) center_rows(ctx, w, Yt, m);
   }
   HIP_OK(hipMemcpy2DAsync(Y, ldy * sizeof(float), Yt, w.lp * sizeof(float), l * sizeof(float), yr,
@@ -653,14 +730,11 @@ rpca_status rpca_get_stats(rpca_ctx ctx, rpca_stats* out) {
   for (auto& t : ctx->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-      if (t.kind == 0) {
-        ctx->stats.ms_ax += ms;
-        ctx->stats.n_ax++;
-        ctx->stats.bytes_ax += t.bytes;
-      } else {
-        ctx->stats.ms_atx += ms;
-        ctx->stats.n_atx++;
-        ctx->stats.bytes_atx += t.bytes;
+      switch (t.kind) {
+        case 0: ctx->stats.ms_ax += ms; ctx->stats.n_ax++; ctx->stats.bytes_ax += t.bytes; break;
+        case 1: ctx->stats.ms_atx += ms; ctx->stats.n_atx++; ctx->stats.bytes_atx += t.bytes; break;
+        case 2: ctx->stats.ms_ax_lp += ms; ctx->stats.n_ax_lp++; ctx->stats.bytes_ax_lp += t.bytes; break;
+        default: ctx->stats.ms_atx_lp += ms; ctx->stats.n_atx_lp++; ctx->stats.bytes_atx_lp += t.bytes; break;
       }
       ctx->stats.timed_launches++;
     }

@@ -24,7 +24,7 @@ def test_status_strings_and_struct_layout():
     assert lib.rpca_status_str(5).startswith(b"matrix not")
     # rpca_matrix: 2 int32 + 14 eight-byte fields
     assert ctypes.sizeof(rp.Matrix) == 8 + 14 * 8
-    assert ctypes.sizeof(rp.Stats) == 10 * 8
+    assert ctypes.sizeof(rp.Stats) == 16 * 8
 
 
 def test_null_context_rejected():

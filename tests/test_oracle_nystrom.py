@@ -90,3 +90,16 @@ def test_float32_input_error_near_optimal():
     assert r == 0
     err = spectral.spectral_err_exact(A, U, L)
     assert err <= 1.1 * lam[k]
+
+
+def test_range_matrix_enters_only_through_its_span():
+    # the self-adjoint range finder normalizes after each product, so a
+    # multiple of A gives the same Q; B1 = A Q always uses A
+    n, k, l = 120, 6, 10
+    lam = np.exp(-np.arange(1, n + 1) / 5.0)
+    A = dense.psd(n, lam, seed=41).astype(np.float64)
+    om = philox.omega(9, n, l)
+    U0, L0, _, _ = nystrom.eig_psd(A, k, l, 2, om)
+    U1, L1, _, _ = nystrom.eig_psd(A, k, l, 2, om, A_range=0.25 * A)
+    np.testing.assert_allclose(L1, L0, rtol=1e-10)
+    np.testing.assert_allclose(np.abs(U1.T @ U0), np.eye(k), atol=1e-8)

@@ -153,3 +153,23 @@ def test_argument_checks():
         rsvd.rsvd(A, 3, 2, 1, np.ones((4, 2)))
     with pytest.raises(ValueError):
         rsvd.rsvd(A, 2, 5, 1, np.ones((4, 5)))
+
+
+def test_range_matrix_enters_only_through_its_span():
+    # A_range = c A has the span of A at every step, so the result equals the
+    # plain one; a perturbed A_range changes only the range finder
+    rng = np.random.default_rng(31)
+    A = dense.dense(300, 120, dense.spectrum_small(120), seed=31)
+    om = philox.omega(5, 120, 14)
+    U0, S0, V0 = rsvd.rsvd(A, 10, 14, 2, om)
+    U1, S1, V1 = rsvd.rsvd(A, 10, 14, 2, om, A_range=3.0 * A.astype(np.float64))
+    np.testing.assert_allclose(S1, S0, rtol=1e-12)
+    np.testing.assert_allclose(np.abs(U1.T @ U0), np.eye(10), atol=1e-9)
+    Ap = A + 1e-9 * rng.standard_normal(A.shape)
+    U2, S2, V2 = rsvd.rsvd(A, 10, 14, 2, om, A_range=Ap, center=True)
+    U3, S3, V3 = rsvd.rsvd(A, 10, 14, 2, om, center=True)
+    np.testing.assert_allclose(S2, S3, rtol=1e-6)
+    # the Rayleigh-Ritz values are those of Q* A for the float A: interlacing holds
+    Ad = A.astype(np.float64)
+    s_true = np.linalg.svd(Ad - Ad.mean(axis=0), compute_uv=False)
+    assert np.all(S2 <= s_true[:10] * (1 + 1e-12))
