@@ -45,6 +45,9 @@ def parse():
     p.add_argument("--no-precision", action="store_true",
                    help="skip the bfloat16 / E4M3 precision-form measurement")
     p.add_argument("--precision-steps", type=int, default=10)
+    p.add_argument("--renorm", choices=("lu", "orth"), default="lu",
+                   help="renormalization between applications: pivoted LU (the paper's) "
+                        "or Cholesky QR")
     p.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                    help="HBM bytes per launch measured by rocprofv3 counters")
     p.add_argument("--traffic-from-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR",
@@ -132,12 +135,12 @@ def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
                       "NumPy/OpenBLAS), median %.2f s" % (nsolves, A.shape[0], n, med)}, rel
 
 
-def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup):
+def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="lu"):
     """Warm up, then time ``steps`` solves on the stream with events; returns
     (ms per solve, library stats over the timed solves)."""
     import torch
     for _ in range(warmup):
-        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat)
+        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat, renorm=renorm)
     torch.cuda.synchronize()
     ctx.reset_stats()
     ctx.set_timing(True)
@@ -147,7 +150,7 @@ def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup):
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat)
+        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat, renorm=renorm)
     e1.record(stream)
     torch.cuda.synchronize()
     ctx.set_timing(False)
@@ -165,7 +168,7 @@ def pass_rates(st, suffix=""):
     return out
 
 
-def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps):
+def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps, renorm):
     """bfloat16 and E4M3 copies of A for the range finder, float32 A for the
     Rayleigh-Ritz product: solves/s, pass rates and err / sigma_{k+1}."""
     import torch
@@ -178,7 +181,7 @@ def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps):
         U = torch.empty(m, k, device=A.device, dtype=torch.float32)
         S = torch.empty(k, device=A.device, dtype=torch.float64)
         V = torch.empty(n, k, device=A.device, dtype=torch.float32)
-        ms, st = time_solves(ctx, q, k, l, its, seed, (U, S, V), mat, steps, 2)
+        ms, st = time_solves(ctx, q, k, l, its, seed, (U, S, V), mat, steps, 2, renorm)
         err = ctx.spectral_err(q, U, S, V, iters=30, seed=7, center=True, mat=mat)
         res[kind] = {"solves_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 4),
                      "speedup_vs_f32": round(ms_f32 / ms, 3),
@@ -219,7 +222,7 @@ def main():
     V = torch.empty(n, k, device=dev, dtype=torch.float32)
     mat = rp.dense(A)
     for _ in range(args.warmup):
-        ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat)
+        ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat, renorm=args.renorm)
     torch.cuda.synchronize()
     print("warmup done", file=sys.stderr, flush=True)
 
@@ -232,7 +235,7 @@ def main():
     e0.record(stream)
     w0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat)
+        ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat, renorm=args.renorm)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -276,7 +279,7 @@ def main():
     prec = None
     if not args.no_precision:
         prec = precision_form(ctx, A, k, l, its, args.seed, sk1, ms_per_step, err_f32,
-                              args.precision_steps)
+                              args.precision_steps, args.renorm)
     out = {
         "metric": METRIC,
         "value": round(1e3 / ms_per_step, 3),
@@ -292,7 +295,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dense %dx%d float32, centered, sigma_j=1/j (j<=50) then "
                                "1e-3*exp(-(j-51)/200); k=%d l=%d its=%d" % (m, n, k, l, its),
-                   "m": m, "n": n, "k": k, "l": l, "its": its, "center": True},
+                   "m": m, "n": n, "k": k, "l": l, "its": its, "center": True, "renorm": args.renorm},
         "passes": passes,
         "roofline": roofline,
         "sigma_k_plus_1": sk1,

@@ -83,8 +83,12 @@ typedef struct {
 
 /* flags */
 enum {
-  RPCA_CENTER = 1u, /* PCA of the column-centered matrix (Sections 2 and 5) */
-  RPCA_SYNC = 2u    /* synchronize the stream before returning              */
+  RPCA_CENTER = 1u,     /* PCA of the column-centered matrix (Sections 2 and 5) */
+  RPCA_SYNC = 2u,       /* synchronize the stream before returning              */
+  RPCA_RENORM_ORTH = 4u /* renormalize by Cholesky QR after every application of
+                           A or A* instead of pivoted LU (Section 5 prefers LU
+                           for its cost; the span, and so the result in exact
+                           arithmetic, is the same)                           */
 };
 
 /* Create a context on the current HIP device, ordered on ``hip_stream``

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rpca.h")
 
 F32, BF16, FP8_E4M3 = 0, 1, 2
 DENSE_ROWMAJOR, SPARSE_CSR = 0, 1
-CENTER, SYNC = 1, 2
+CENTER, SYNC, RENORM_ORTH = 1, 2, 4
 
 STATUS = {
     0: "RPCA_OK",
@@ -205,8 +205,12 @@ class Context:
             raise RpcaError(st, msg)
 
     # ---- solvers -------------------------------------------------------
-    def svd(self, A, k, l=None, its=2, seed=0, center=False, sync=False, out=None, mat=None):
-        """U (m x k), S (k, float64), V (n x k) with U diag(S) V^T ~ A (or A - 1 c)."""
+    def svd(self, A, k, l=None, its=2, seed=0, center=False, sync=False, out=None, mat=None,
+            renorm="lu"):
+        """U (m x k), S (k, float64), V (n x k) with U diag(S) V^T ~ A (or A - 1 c).
+
+        renorm: "lu" (pivoted LU between applications, the paper's choice) or
+        "orth" (Cholesky QR every time)."""
         torch = self._torch
         m, n = A.shape
         l = k + 2 if l is None else l
@@ -218,19 +222,21 @@ class Context:
             U, S, V = out
         mat = dense(A) if mat is None else mat
         flags = (CENTER if center else 0) | (SYNC if sync else 0)
+        flags |= RENORM_ORTH if renorm == "orth" else 0
         self._check(self.lib.rpca_svd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                       _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0)))
         return U, S, V
 
-    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None):
+    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="lu"):
         torch = self._torch
         n = A.shape[0]
         l = k + 2 if l is None else l
         U = torch.empty(n, k, device=A.device, dtype=torch.float32)
         lam = torch.empty(k, device=A.device, dtype=torch.float64)
         mat = dense(A) if mat is None else mat
-        self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed,
-                                          SYNC if sync else 0, _ptr(U), U.stride(0), _ptr(lam)))
+        flags = (SYNC if sync else 0) | (RENORM_ORTH if renorm == "orth" else 0)
+        self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
+                                          _ptr(U), U.stride(0), _ptr(lam)))
         return U, lam
 
     def spectral_err(self, A, U, S, V=None, iters=20, seed=0, center=False, mat=None):

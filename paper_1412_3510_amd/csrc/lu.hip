@@ -74,62 +74,84 @@ __device__ __forceinline__ void shift_bucket(float (&row)[LP], float mult, const
 // threads of a workgroup (one row per thread, in registers).  The row is kept
 // in a moving frame: before step p, register c holds column p + c, and the
 // elimination update writes the shifted row, so the current column is always
-// row[0] and no register is addressed by a run-time index.  Per step: a DPP
-// argmax in each wave, the wave winners' rows to LDS, one barrier, a merge of
-// the wave results, the pivot row streamed from LDS into the update of the
-// live columns only.  Chooses up to l pivot rows; ties in |value| go to the
-// smaller global row index.  When ``U`` is given the eliminated pivot rows
-// (row p of U = pivot row in frame p) are written.
+// row[0] and no register is addressed by a run-time index.
+//
+// The pivot search works on one 32-bit key per row: the top bits of |row[0]|
+// (sign, exponent and 13 fraction bits) above NT - tid in the low KB bits,
+// 0 for rows that are no longer candidates.  The largest key is the largest
+// |value| up to 2^-13 relative (so |L| <= 1 + 2^-13), ties going to the lower
+// thread slot; |values| below 2^-100 count as zero; every key is distinct, so a wave maximum (six DPP max steps)
+// names its row.  Per step: the wave maximum, the wave winner's live row and
+// global index to LDS, one barrier, the maximum of the NW wave keys, the pivot
+// row streamed from LDS into the update of the live columns.  A key whose
+// value bits are all zero is a zero pivot (LAPACK getrf: nothing is
+// eliminated and U[p][p] = 0).  When ``U`` (LDS) is given the eliminated
+// pivot rows (row p of U = pivot row in frame p) are written to it.
+__device__ __forceinline__ unsigned dpp_max_u32(unsigned v, int sel) {
+  unsigned o;
+  switch (sel) {
+    case 0: o = __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+    case 1: o = __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+    case 2: o = __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    case 3: o = __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false); break;  // row_mirror
+    case 4: o = __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false); break;  // row_bcast:15
+    default: o = __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false); break; // row_bcast:31
+  }
+  return max(v, o);
+}
+
+__device__ __forceinline__ unsigned wave_max_key(unsigned k) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) k = dpp_max_u32(k, s);
+  return (unsigned)__builtin_amdgcn_readlane((int)k, 63);
+}
+
 template <int LP, int NT>
 __device__ __forceinline__ void gepp_block(float (&row)[LP], bool cand, int gidx, int l,
-                                           int* s_piv, float* s_wkey, int* s_widx,
+                                           int* s_piv, unsigned* s_wkey, int* s_widx,
                                            float* s_wrow, float* U) {
   constexpr int NW = LuCfg<LP, NT>::NW;
+  constexpr int KB = (NT <= 255) ? 8 : (NT <= 511 ? 9 : (NT <= 1023 ? 10 : 11));  // bits for NT - tid
+  constexpr unsigned KMASK = (1u << KB) - 1u;
+  static_assert(NT <= (int)KMASK, "slot bits");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const unsigned slot = (unsigned)(NT - tid);  // 1 .. NT
   for (int p = 0; p < l; ++p) {
     const int buf = p & 1;
     const int live = l - p;
-    float key = cand ? fabsf(row[0]) : -1.f;
-    int idx = cand ? gidx : 0x7fffffff;
-    wave_argmax_fast(key, idx);
-    if (lane == 0) {
-      s_wkey[buf * NW + wave] = key;
-      s_widx[buf * NW + wave] = idx;
-    }
-    if (cand && gidx == idx) {
+    // values below 2^-100 count as zero pivots (their reciprocal would overflow)
+    const float a0 = fabsf(row[0]);
+    const unsigned vbits = (a0 >= 7.8886091e-31f) ? (__float_as_uint(a0) & ~KMASK) : 0u;
+    const unsigned key = cand ? (vbits | slot) : 0u;
+    const unsigned wmax = wave_max_key(key);
+    if (wmax != 0u && key == wmax) {  // this wave's candidate for the pivot
+      s_wkey[buf * NW + wave] = wmax;
+      s_widx[buf * NW + wave] = gidx;
       float4* dst = reinterpret_cast<float4*>(s_wrow + (buf * NW + wave) * LP);
 #pragma unroll
       for (int c = 0; c < LP; c += 4)
         if (c < live) dst[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
+    } else if (wmax == 0u && lane == 0) {
+      s_wkey[buf * NW + wave] = 0u;
     }
     __syncthreads();
-    float wk[NW];
-    int wi[NW];
+    unsigned gk = 0u;
 #pragma unroll
     for (int w = 0; w < NW; w += 4) {
-      const float4 k4 = *reinterpret_cast<const float4*>(s_wkey + buf * NW + w);
-      const int4 i4 = *reinterpret_cast<const int4*>(s_widx + buf * NW + w);
-      wk[w] = k4.x; wk[w + 1] = k4.y; wk[w + 2] = k4.z; wk[w + 3] = k4.w;
-      wi[w] = i4.x; wi[w + 1] = i4.y; wi[w + 2] = i4.z; wi[w + 3] = i4.w;
+      const uint4 k4 = *reinterpret_cast<const uint4*>(s_wkey + buf * NW + w);
+      gk = max(gk, max(max(k4.x, k4.y), max(k4.z, k4.w)));
     }
-    float bk = wk[0];
-    int bi = wi[0], bw = 0;
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      const float k2 = wk[w];
-      const int i2 = wi[w];
-      const bool take = (k2 > bk) | ((k2 == bk) & (i2 < bi));
-      bk = take ? k2 : bk;
-      bi = take ? i2 : bi;
-      bw = take ? w : bw;
-    }
+    const bool have = gk != 0u;  // some candidate row was left
+    const int wt = NT - (int)(gk & KMASK);  // thread slot of the pivot row
+    const int bw = have ? (wt >> 6) : 0;
     const float* prow = s_wrow + (buf * NW + bw) * LP;
-    const bool have = (bk >= 0.f);  // some candidate row was left
-    if (tid == 0) s_piv[p] = have ? bi : -1;
-    if (U && tid < LP) U[p * LP + tid] = (have && tid >= p && tid < l) ? prow[tid - p] : 0.f;
-    const float inv = (have && bk > 0.f) ? 1.0f / prow[0] : 0.f;
+    const bool nonzero = (gk & ~KMASK) != 0u;
+    if (tid == 0) s_piv[p] = have ? s_widx[buf * NW + bw] : -1;
+    if (U && tid < LP)  // LDS
+      U[p * LP + tid] = (have && tid >= p && tid < l && (nonzero || tid > p)) ? prow[tid - p] : 0.f;
+    const float inv = nonzero ? __builtin_amdgcn_rcpf(prow[0]) : 0.f;
     float mult = 0.f;
-    if (cand && gidx == bi) cand = false;
+    if (cand && tid == wt) cand = false;
     else if (cand) mult = row[0] * inv;
     shift_bucket<LP>(row, mult, prow, live);
   }
@@ -145,9 +167,10 @@ __global__ void __launch_bounds__(NT_) lu_tree_kernel(const float* __restrict__ 
                                                       int* __restrict__ piv) {
   constexpr int NT = LuCfg<LP, NT_>::NT, NW = LuCfg<LP, NT_>::NW, F = LuCfg<LP, NT_>::F;
   __shared__ int s_piv[LP];
-  __shared__ __attribute__((aligned(16))) float s_wkey[2 * NW];
+  __shared__ __attribute__((aligned(16))) unsigned s_wkey[2 * NW];
   __shared__ __attribute__((aligned(16))) int s_widx[2 * NW];
   __shared__ __attribute__((aligned(16))) float s_wrow[2 * NW * LP];
+  __shared__ float s_U[LP * LP];  // U of the root block (global stores stay out of the steps)
   __shared__ int s_last;
   const int tid = threadIdx.x;
   int level = 0, blk = blockIdx.x;
@@ -182,10 +205,10 @@ __global__ void __launch_bounds__(NT_) lu_tree_kernel(const float* __restrict__ 
       for (int c = 0; c < LP; ++c) row[c] = 0.f;
     }
     const bool root = (lv.nblk[level] == 1);
-    gepp_block<LP, NT>(row, valid, gidx, l, s_piv, s_wkey, s_widx, s_wrow, root ? U : nullptr);
+    gepp_block<LP, NT>(row, valid, gidx, l, s_piv, s_wkey, s_widx, s_wrow, root ? s_U : nullptr);
     if (root) {
       if (tid < LP) piv[tid] = (tid < l) ? s_piv[tid] : -1;
-      for (int e = l * LP + tid; e < LP * LP; e += NT) U[e] = 0.f;
+      for (int e = tid; e < LP * LP; e += NT) U[e] = (e < l * LP) ? s_U[e] : 0.f;
       return;
     }
     if (tid < LP) cand[lv.cand_off[level] + blk * LP + tid] = (tid < l) ? s_piv[tid] : -1;

@@ -494,6 +494,7 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   if (ldu < k || ldv < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu/ldv must be >= k");
   const int64_t m = A->m, n = A->n;
   const bool center = (flags & RPCA_CENTER) != 0;
+  const bool orth_all = (flags & RPCA_RENORM_ORTH) != 0;
   Work w;
   s = prepare(ctx, w, m, n, l, false, A->dtype);
   if (s != RPCA_OK) return s;
@@ -501,6 +502,11 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   ctx->stats.calls++;
   const AView Av = native_view(A);  // range finder
   const AView Ar = rr_view(A);      // Rayleigh-Ritz product
+  // intermediate renormalization: pivoted LU (Section 5), or Cholesky QR
+  auto mid_renorm = [&](float* T, int64_t rows) {
+    if (orth_all) orth_renorm(ctx, w, T, rows, false, seed);
+    else lu_renorm(ctx, w, T, rows);
+  };
 
   // Omega (n x l, zero padded to lp) -> packed right operand
   HIP_OK(hipMemsetAsync(w.Z, 0, (size_t)n * w.lp * sizeof(float), st));
@@ -510,17 +516,17 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   run_ax(ctx, Av, w, w.Xp, w.Y);
   if (center) center_rows(ctx, w, w.Y, m);
   if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
-  else lu_renorm(ctx, w, w.Y, m);
+  else mid_renorm(w.Y, m);
   for (int it = 1; it <= its; ++it) {
     // Z = A^T Q, renormalized by LU
     pack_m_side(ctx, w, w.Y, m, center);
     apply_at(ctx, Av, w, w.Z);
-    lu_renorm(ctx, w, w.Z, n);
+    mid_renorm(w.Z, n);
     // Y = A Q; LU except after the last application, which is orthonormalized
     pack_n_side(ctx, w, w.Z, n, Av);
     run_ax(ctx, Av, w, w.Xp, w.Y);
     if (center) center_rows(ctx, w, w.Y, m);
-    if (it < its) lu_renorm(ctx, w, w.Y, m);
+    if (it < its) mid_renorm(w.Y, m);
     else orth_renorm(ctx, w, w.Y, m, false, seed);
   }
   // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
@@ -566,7 +572,7 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   for (int it = 1; it <= its; ++it) {
     pack_n_side(ctx, w, w.Y, n, Av);
     run_ax(ctx, Av, w, w.Xp, w.Y);
-    if (it < its) lu_renorm(ctx, w, w.Y, n);
+    if (it < its && !(flags & RPCA_RENORM_ORTH)) lu_renorm(ctx, w, w.Y, n);
     else orth_renorm(ctx, w, w.Y, n, false, seed);
   }
   // B1 = A Q (start); B2 = Q* B1 (second), shifted; C = chol (Cholesky)

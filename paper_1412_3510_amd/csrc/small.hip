@@ -19,92 +19,113 @@ static constexpr double kTauRel = 1e-10;   // relative Cholesky pivot that marks
 static constexpr double kShiftRel = 1e-8;  // relative diagonal shift when dependence is met
 static constexpr double kJunkNorm2 = 1e-2; // squared column norm after a shifted pass
 
-// Cholesky G + shift = R^T R (R upper) of the leading l x l block, one thread
-// per column.  Thread c keeps its column in registers in a moving frame
-// (before step j, reg[t] = A[j + t][c]), so the pivot row entry u_c of every
-// column is reg[0] and the update is a shifted register update.  The unscaled
-// pivot row u goes through a double-buffered LDS row, which also hands every
-// wave the pivot d = u_j; with R[j][c] = u_c / sqrt(d) the update is
-// reg[t] -= u_{j+1+t} (u_c / d).  The factor is written to Rs (LDS, row-major
-// stride LP).  Returns false at the first pivot d <= tau * diag[j] (or
-// non-finite); all threads read the same d, so all agree.
-// Pivot row buffer stride: the shifted update reads up to 31 entries past
-// column l - 1, which stay zero.
-template <int LP>
-constexpr int kRowStride = LP + 32;
+// Cholesky G + shift = R^T R (R upper) of the leading l x l block by one
+// workgroup of 1024 threads.  Thread (g, c) -- g = tid / LP, c = tid % LP --
+// keeps the entries (i, c), i = g + RG q (RG = 1024 / LP row groups), in
+// registers.  Step j: every thread reads the current row u = G[j][.] from a
+// double-buffered LDS row (published by its owners at the end of step j - 1)
+// and the pivot d = u[j]; row j of R, u[c] / sqrt(d), goes to the LDS factor
+// Rs (float32, row-major stride LP); the trailing entries are updated,
+// G[i][c] -= u[i] u[c] / d for j < i <= c; the owners of row j + 1 publish it;
+// one barrier.  1/sqrt(d) is v_rsq_f64 refined by two Newton steps, which
+// keeps division and square root off the step's critical path.  Nothing in
+// the loop touches global memory, so the barrier waits for LDS only.
+// Returns false at the first pivot d <= tau * diag[j] (or not finite): all
+// threads read the same d, so all agree.
+static constexpr int kCholThreads = 1024;
 
-template <int W, int LP>
-__device__ __forceinline__ void chol_shift(double (&reg)[LP], double coef, const double* row) {
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
-  for (int t = 0; t + 1 < W; ++t) reg[t] = reg[t + 1] - row[t] * coef;
-  reg[W - 1] = 0.0;
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+  }
+  return y;
 }
 
 template <int LP>
-__device__ bool chol_cols(const double* __restrict__ G, bool sym, int l, double srel, double sabs,
-                          const double* diag, double tau, double* Rs, double* rowbuf) {
-  const int c = threadIdx.x;  // column owned by this thread (blockDim.x == LP or 64)
-  double reg[LP];
+__device__ bool chol_par(const double* __restrict__ G, bool sym, int l, double srel, double sabs,
+                         const double* diag, double tau, float* Rs, double* ubuf) {
+  constexpr int RG = kCholThreads / LP;  // row groups
+  constexpr int RPT = LP / RG;           // rows per thread
+  const int tid = threadIdx.x, g = tid / LP, c = tid % LP;
+  double v[RPT];
 #pragma unroll
-  for (int t = 0; t < LP; ++t) {
-    double v = 0.0;
-    if (c < l && t < l) v = sym ? 0.5 * (G[t * LP + c] + G[c * LP + t]) : G[t * LP + c];
-    if (t == c && c < l) v += srel * diag[c] + sabs;
-    reg[t] = v;
+  for (int q = 0; q < RPT; ++q) {
+    const int i = g + RG * q;
+    double x = 0.0;
+    if (i < l && c < l) x = sym ? 0.5 * (G[i * LP + c] + G[c * LP + i]) : G[i * LP + c];
+    if (i == c && c < l) x += srel * diag[c] + sabs;
+    v[q] = x;
   }
-  for (int j = 0; j < l; ++j) {
-    const int buf = j & 1;
-    const double u = (c >= j && c < l) ? reg[0] : 0.0;
-    if (c < LP) rowbuf[buf * kRowStride<LP> + c] = u;
-    __syncthreads();
-    const double d = rowbuf[buf * kRowStride<LP> + j];
-    if (!(d > tau * diag[j]) || !(d > 0.0) || !(d < 1e300)) return false;
-    const double r = sqrt(d);
-    if (c < LP) Rs[j * LP + c] = (c == j) ? r : ((c > j) ? u / r : 0.0);
-    const double coef = (c > j) ? u / d : 0.0;
-    // reg[t] <- reg[t+1] - u_{j+1+t} u_c / d
-    const double* row = rowbuf + buf * kRowStride<LP> + j + 1;
-    const int live = l - j;
-    if (LP >= 128 && live > 96) chol_shift<(LP >= 128 ? 128 : 16), LP>(reg, coef, row);
-    else if (LP >= 128 && live > 64) chol_shift<(LP >= 128 ? 96 : 16), LP>(reg, coef, row);
-    else if (LP >= 64 && live > 48) chol_shift<(LP >= 64 ? 64 : 16), LP>(reg, coef, row);
-    else if (LP >= 64 && live > 32) chol_shift<(LP >= 64 ? 48 : 16), LP>(reg, coef, row);
-    else if (live > 16) chol_shift<(LP >= 32 ? 32 : 16), LP>(reg, coef, row);
-    else chol_shift<16, LP>(reg, coef, row);
-  }
+  if (g == 0) ubuf[c] = v[0];  // row 0
   __syncthreads();
+  for (int j = 0; j < l; ++j) {
+    const double* u = ubuf + (j & 1) * LP;
+    const double d = u[j];
+    if (!(d > tau * diag[j]) || !(d > 0.0) || !(d < 1e300)) return false;
+    const double uc = u[c];
+    const double y = rsqrt_nr(d);
+    const double f = uc * (y * y);
+    if (g == 0) Rs[j * LP + c] = (c < l && c >= j) ? (float)((c == j) ? d * y : uc * y) : 0.f;
+    double nxt = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = g + RG * q;
+      if (i > j && i <= c && c < l) v[q] -= u[i] * f;
+      if (i == j + 1) nxt = v[q];
+    }
+    if (g == (j + 1) % RG) ubuf[((j + 1) & 1) * LP + c] = (c > j && c < l) ? nxt : 0.0;
+    __syncthreads();
+  }
   return true;
 }
 
 template <int LP>
-__global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_qr_kernel(const double* __restrict__ G,
-                                                                    int l, int pass,
-                                                                    float* __restrict__ Rf,
-                                                                    int* __restrict__ state) {
+__global__ void __launch_bounds__(kCholThreads) chol_qr_kernel(const double* __restrict__ G,
+                                                               int l, int pass,
+                                                               float* __restrict__ Rf,
+                                                               int* __restrict__ state) {
   if (pass >= 3 && state[1] == 0) return;
-  constexpr int NT = LP < 64 ? 64 : LP;
-  __shared__ double Rs[LP * LP];
-  __shared__ double rowbuf[2 * kRowStride<LP>];
+  __shared__ double ubuf[2 * LP];
   __shared__ double diag[LP];
+  __shared__ float Rs[LP * LP];
+  __shared__ double s_maxd;
   const int tid = threadIdx.x;
   if (pass == 1 && tid < 12) state[tid] = 0;
-  for (int j = tid; j < LP; j += NT) diag[j] = (j < l) ? G[j * LP + j] : 0.0;
-  for (int e = tid; e < LP * LP; e += NT) Rs[e] = 0.0;
-  for (int e = tid; e < 2 * kRowStride<LP>; e += NT) rowbuf[e] = 0.0;
+  if (tid < LP) diag[tid] = (tid < l) ? G[tid * LP + tid] : 0.0;
   __syncthreads();
-  double maxd = 0.0;
-  for (int j = 0; j < l; ++j) maxd = fmax(maxd, diag[j]);
+  if (tid == 0) {
+    double maxd = 0.0;
+    for (int j = 0; j < l; ++j) maxd = fmax(maxd, diag[j]);
+    s_maxd = maxd;
+  }
+  __syncthreads();
+  const double maxd = s_maxd;
   bool shifted = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     __syncthreads();
     const double srel = attempt ? kShiftRel : 0.0;
     const double sabs = attempt ? (1e-30 * maxd + 1e-300) : 0.0;
-    const bool ok = chol_cols<LP>(G, false, l, srel, sabs, diag, attempt ? 0.0 : kTauRel, Rs, rowbuf);
+    const bool ok = chol_par<LP>(G, false, l, srel, sabs, diag, attempt ? 0.0 : kTauRel, Rs, ubuf);
     if (ok) break;
     if (attempt == 1 && tid == 0) state[5] = 1;  // only non-finite input gets here
     shifted = true;
   }
   __syncthreads();
+  // the float32 factor; rows l .. LP-1 are zero
+  for (int e = tid; e < LP * LP; e += kCholThreads) Rf[e] = (e < l * LP) ? Rs[e] : 0.f;
   if (tid == 0) {
     if (shifted) state[0] = 1;
     if (pass == 2) {
@@ -123,19 +144,14 @@ __global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_qr_kernel(const double
       state[1] = state[0] | any;
     }
   }
-  // float32 copy of R for the solve
-  for (int e = tid; e < LP * LP; e += NT) {
-    const int i = e / LP, c = e % LP;
-    Rf[e] = (i < l && c < l && c >= i) ? (float)Rs[e] : 0.f;
-  }
 }
 
 void launch_chol_qr_step(hipStream_t st, const double* G, int l, int lp, int pass, float* Rf,
                          int* state) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL(chol_qr_kernel<32>, dim3(1), dim3(64), 0, st, G, l, pass, Rf, state); break;
-    case 64: hipLaunchKernelGGL(chol_qr_kernel<64>, dim3(1), dim3(64), 0, st, G, l, pass, Rf, state); break;
-    case 128: hipLaunchKernelGGL(chol_qr_kernel<128>, dim3(1), dim3(128), 0, st, G, l, pass, Rf, state); break;
+    case 32: hipLaunchKernelGGL(chol_qr_kernel<32>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, Rf, state); break;
+    case 64: hipLaunchKernelGGL(chol_qr_kernel<64>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, Rf, state); break;
+    case 128: hipLaunchKernelGGL(chol_qr_kernel<128>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, Rf, state); break;
     default: break;
   }
 }
@@ -167,18 +183,15 @@ void launch_complete(hipStream_t st, float* Q, int64_t ldq, int64_t rows, int l,
 // nu = sqrt(n) u ||B1||_F, multiplied by 10 while the factor does not exist.
 // ------------------------------------------------------------------------
 template <int LP>
-__global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_nystrom_kernel(
+__global__ void __launch_bounds__(kCholThreads) chol_nystrom_kernel(
     const double* __restrict__ G, int l, const double* __restrict__ fro2, double n_sqrt_u,
     float* __restrict__ Rf, double* __restrict__ nu_out, float* __restrict__ nu_f,
     int* __restrict__ state, int max_retries) {
-  constexpr int NT = LP < 64 ? 64 : LP;
-  __shared__ double Rs[LP * LP];
-  __shared__ double rowbuf[2 * kRowStride<LP>];
+  __shared__ double ubuf[2 * LP];
   __shared__ double zero[LP];
+  __shared__ float Rs[LP * LP];
   const int tid = threadIdx.x;
-  for (int j = tid; j < LP; j += NT) zero[j] = 0.0;
-  for (int e = tid; e < LP * LP; e += NT) Rs[e] = 0.0;
-  for (int e = tid; e < 2 * kRowStride<LP>; e += NT) rowbuf[e] = 0.0;
+  if (tid < LP) zero[tid] = 0.0;
   __syncthreads();
   double nu = n_sqrt_u * sqrt(fro2[0]);
   if (!(nu > 0.0)) nu = 1e-300;
@@ -187,7 +200,7 @@ __global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_nystrom_kernel(
   for (; retry <= max_retries; ++retry) {
     __syncthreads();
     // B2 = (G + G^T)/2 + nu I
-    ok = chol_cols<LP>(G, true, l, 0.0, nu, zero, 0.0, Rs, rowbuf);
+    ok = chol_par<LP>(G, true, l, 0.0, nu, zero, 0.0, Rs, ubuf);
     if (ok) break;
     if (retry < max_retries) nu *= 10.0;
   }
@@ -198,9 +211,10 @@ __global__ void __launch_bounds__(LP < 64 ? 64 : LP) chol_nystrom_kernel(
     nu_out[0] = nu;
     nu_f[0] = (float)nu;
   }
-  for (int e = tid; e < LP * LP; e += NT) {
+  // rows l .. LP-1 zero; the identity where no factor was found
+  for (int e = tid; e < LP * LP; e += kCholThreads) {
     const int i = e / LP, c = e % LP;
-    Rf[e] = (ok && i < l && c < l && c >= i) ? (float)Rs[e] : (i == c ? 1.f : 0.f);
+    Rf[e] = ok ? ((i < l) ? Rs[e] : 0.f) : ((i == c && i < l) ? 1.f : 0.f);
   }
 }
 
@@ -208,9 +222,9 @@ void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const d
                          double n_sqrt_u, float* Rf, double* nu_out, float* nu_f, int* state,
                          int max_retries) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL(chol_nystrom_kernel<32>, dim3(1), dim3(64), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
-    case 64: hipLaunchKernelGGL(chol_nystrom_kernel<64>, dim3(1), dim3(64), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
-    case 128: hipLaunchKernelGGL(chol_nystrom_kernel<128>, dim3(1), dim3(128), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
+    case 32: hipLaunchKernelGGL(chol_nystrom_kernel<32>, dim3(1), dim3(kCholThreads), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
+    case 64: hipLaunchKernelGGL(chol_nystrom_kernel<64>, dim3(1), dim3(kCholThreads), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
+    case 128: hipLaunchKernelGGL(chol_nystrom_kernel<128>, dim3(1), dim3(kCholThreads), 0, st, G, l, fro2, n_sqrt_u, Rf, nu_out, nu_f, state, max_retries); break;
     default: break;
   }
 }
@@ -316,10 +330,16 @@ __global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict
       al = sum8(al);
       be = sum8(be);
       ga = sum8(ga);
-      if (go && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+      if (go && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
+        // Rutishauser's rotation; reciprocals and square roots from the
+        // hardware approximations refined by Newton steps (rcp_nr, rsqrt_nr)
+        const double zeta = (be - al) * (0.5 * rcp_nr(ga));
+        const double w = fma(zeta, zeta, 1.0);
+        // beyond |zeta| = 1e150, w would overflow; there t = 1 / (2 zeta) to
+        // working precision
+        const double t = (fabs(zeta) < 1e150) ? copysign(rcp_nr(fabs(zeta) + w * rsqrt_nr(w)), zeta)
+                                               : 0.5 * rcp_nr(zeta);
+        const double c = rsqrt_nr(fma(t, t, 1.0)), s = c * t;
 #pragma unroll
         for (int u = 0; u < RPT; u += 2) {
           *reinterpret_cast<double2*>(Mc + p * CS + i0 + u) =

@@ -160,13 +160,15 @@ def test_small_svd(ctx, l):
 
 
 # ---------------------------------------------------------------- end to end
-def _check_svd(ctx, A, k, l, its, seed, center=False, rel=1e-4, err_factor=1.1, sk1=None):
+def _check_svd(ctx, A, k, l, its, seed, center=False, rel=1e-4, err_factor=1.1, sk1=None,
+               renorm="lu"):
     m, n = A.shape
-    U, S, V = ctx.svd(_dev(A), k, l, its, seed, center=center)
+    U, S, V = ctx.svd(_dev(A), k, l, its, seed, center=center, renorm=renorm)
     torch.cuda.synchronize()
     U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
     om = philox.omega(seed, n, l)
-    U0, S0, V0 = rsvd.rsvd(A, k, l, its, om, center=center)
+    U0, S0, V0 = rsvd.rsvd(A, k, l, its, om, center=center,
+                           renorm="qr" if renorm == "orth" else "lu")
     np.testing.assert_allclose(S, S0, rtol=rel)
     assert np.linalg.norm(U.T.astype(np.float64) @ U - np.eye(k), 2) < 1e-5
     assert np.linalg.norm(V.T.astype(np.float64) @ V - np.eye(k), 2) < 1e-5
@@ -198,6 +200,15 @@ def test_svd_shapes(ctx, m, n, k, l, its):
     # its = 0 is the plain sketch, which the paper finds inaccurate (Section 7):
     # only parity with the oracle is asked of it
     _check_svd(ctx, A, k, l, its, 7 + its, sk1=sig[k] if its > 0 else None, err_factor=1.2)
+
+
+@pytest.mark.parametrize("m,n,k,l,its", [(3000, 200, 20, 30, 2), (4000, 400, 50, 60, 3),
+                                         (2000, 300, 90, 120, 2)])
+def test_svd_orth_renorm(ctx, m, n, k, l, its):
+    # Cholesky QR after every application; the oracle uses Householder QR there
+    sig = dense.spectrum_tall(min(m, n))
+    A = dense.dense(m, n, sig, seed=m + n + 1)
+    _check_svd(ctx, A, k, l, its, 17 + its, sk1=sig[k], err_factor=1.2, renorm="orth")
 
 
 def test_svd_centered(ctx):
