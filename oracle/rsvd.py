@@ -35,6 +35,7 @@ invariance); near-optimal error on the six spectra of Section 7.
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.sparse as sps
 
 
 def lu_renorm(Y):
@@ -67,7 +68,8 @@ def sign_fix(U, V=None):
 def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
     """Rank-k approximation U diag(S) V^T of A (or of its column-centered form).
 
-    A       -- m x n array (the exact values the device sees; upcast to float64)
+    A       -- m x n array (the exact values the device sees; upcast to float64),
+               or a scipy.sparse matrix
     omega   -- n x l test matrix (float32 values from ``oracle.philox.omega``)
     renorm  -- "lu" (the paper's choice) or "qr" (Householder everywhere; equal
                to "lu" in exact arithmetic by span invariance)
@@ -77,7 +79,14 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
 
     Returns (U m x k, S length k, V n x k), all float64.
     """
-    A = np.asarray(A, dtype=np.float64)
+    if sps.issparse(A):
+        # a sparse A is only ever multiplied (Section 8); the centered sparse
+        # form is not asked of the oracle
+        if center or A_range is not None:
+            raise ValueError("sparse A: no centering or range matrix")
+        A = sps.csr_matrix(A, dtype=np.float64)
+    else:
+        A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if not (1 <= k <= l <= min(m, n)):
         raise ValueError("need 1 <= k <= l <= min(m, n)")
@@ -96,14 +105,14 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
     Q = qr_renorm(Y) if its == 0 else mid(Y)
     for it in range(1, its + 1):
         # Apply A* as (Q* A)* without forming A* (Section 5).
-        Z = (Q.T @ R).T
+        Z = np.asarray(Q.T @ R).T
         Q = mid(Z)
         Y = R @ Q
         # LU in all but the last iteration, QR in the last (Section 5).
         Q = mid(Y) if it < its else qr_renorm(Y)
 
     # B = Q* A, formula (i2); its SVD W Sigma V* = B, formula (i3).
-    B = Q.T @ A
+    B = np.asarray(Q.T @ A)
     W, S, Vt = np.linalg.svd(B, full_matrices=False)
     # U = Q W, formula (i4).
     U = Q @ W

@@ -24,6 +24,7 @@ factorization.
 """
 
 import numpy as np
+import scipy.sparse as sps
 
 
 def residual(A, U, S, V=None, center=False):
@@ -54,11 +55,17 @@ def spectral_err_power(A, U, S, V, X0, iters, center=False):
 
     E is applied without being formed: E x = A x - U (S (V^T x)) and
     E^T y = A^T y - V (S (U^T y)) (with A replaced by A_c when centering).
+    A may be a scipy.sparse matrix (then without centering).
     X0 is the n x b start block.
     """
-    A = np.asarray(A, dtype=np.float64)
-    if center:
-        A = A - A.mean(axis=0, keepdims=True)
+    if sps.issparse(A):
+        if center:
+            raise ValueError("sparse A: no centering")
+        A = sps.csr_matrix(A, dtype=np.float64)
+    else:
+        A = np.asarray(A, dtype=np.float64)
+        if center:
+            A = A - A.mean(axis=0, keepdims=True)
     U = np.asarray(U, dtype=np.float64)
     V = U if V is None else np.asarray(V, dtype=np.float64)
     S = np.asarray(S, dtype=np.float64)

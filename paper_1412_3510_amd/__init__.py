@@ -173,6 +173,52 @@ def dense(A, dtype=None, col_scale=None, A_f32=None):
     return mat
 
 
+class SparseMatrix:
+    """A sparse A for the library: CSR arrays of A and, for products with A^T,
+    CSC arrays (the CSR of A^T), all int32 / float32 (or bfloat16) CUDA tensors.
+    Keeps the tensors alive while the matrix is used."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, col_ptr=None, row_idx=None, val_t=None):
+        import torch
+        self.shape = (int(m), int(n))
+        self._keep = [row_ptr, col_idx, val, col_ptr, row_idx, val_t]
+        for name, t, dt in (("row_ptr", row_ptr, torch.int32), ("col_idx", col_idx, torch.int32),
+                            ("col_ptr", col_ptr, torch.int32), ("row_idx", row_idx, torch.int32)):
+            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("%s must be a contiguous int32 CUDA tensor" % name)
+        if row_ptr.numel() != m + 1 or (col_ptr is not None and col_ptr.numel() != n + 1):
+            raise ValueError("row_ptr needs m + 1 entries, col_ptr n + 1")
+        code = {torch.float32: F32, torch.bfloat16: BF16}.get(val.dtype)
+        if code is None or (val_t is not None and val_t.dtype != val.dtype):
+            raise ValueError("values must be float32 or bfloat16 (both copies alike)")
+        mat = Matrix()
+        mat.format = SPARSE_CSR
+        mat.dtype = code
+        mat.m, mat.n = self.shape
+        mat.nnz = val.numel()
+        mat.row_ptr = row_ptr.data_ptr()
+        mat.col_idx = col_idx.data_ptr()
+        mat.val = val.data_ptr()
+        if col_ptr is not None:
+            mat.col_ptr = col_ptr.data_ptr()
+            mat.row_idx = row_idx.data_ptr()
+            mat.val_t = val_t.data_ptr()
+        self.mat = mat
+
+
+def csr(m, n, row_ptr, col_idx, val, col_ptr=None, row_idx=None, val_t=None):
+    """SparseMatrix from CUDA tensors (CSR of A, optionally CSC of A)."""
+    return SparseMatrix(m, n, row_ptr, col_idx, val, col_ptr, row_idx, val_t)
+
+
+def _as_mat(A, mat):
+    """(rpca_matrix, m, n) for a dense tensor or a SparseMatrix."""
+    if isinstance(A, SparseMatrix):
+        return A.mat, A.shape[0], A.shape[1]
+    m, n = A.shape
+    return (dense(A) if mat is None else mat), m, n
+
+
 class Context:
     """A library context bound to a torch CUDA stream (the current one by default)."""
 
@@ -212,15 +258,14 @@ class Context:
         renorm: "lu" (pivoted LU between applications, the paper's choice) or
         "orth" (Cholesky QR every time)."""
         torch = self._torch
-        m, n = A.shape
+        mat, m, n = _as_mat(A, mat)
         l = k + 2 if l is None else l
         if out is None:
-            U = torch.empty(m, k, device=A.device, dtype=torch.float32)
-            S = torch.empty(k, device=A.device, dtype=torch.float64)
-            V = torch.empty(n, k, device=A.device, dtype=torch.float32)
+            U = torch.empty(m, k, device="cuda", dtype=torch.float32)
+            S = torch.empty(k, device="cuda", dtype=torch.float64)
+            V = torch.empty(n, k, device="cuda", dtype=torch.float32)
         else:
             U, S, V = out
-        mat = dense(A) if mat is None else mat
         flags = (CENTER if center else 0) | (SYNC if sync else 0)
         flags |= RENORM_ORTH if renorm == "orth" else 0
         self._check(self.lib.rpca_svd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
@@ -229,11 +274,10 @@ class Context:
 
     def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="lu"):
         torch = self._torch
-        n = A.shape[0]
+        mat, n, _ = _as_mat(A, mat)
         l = k + 2 if l is None else l
-        U = torch.empty(n, k, device=A.device, dtype=torch.float32)
-        lam = torch.empty(k, device=A.device, dtype=torch.float64)
-        mat = dense(A) if mat is None else mat
+        U = torch.empty(n, k, device="cuda", dtype=torch.float32)
+        lam = torch.empty(k, device="cuda", dtype=torch.float64)
         flags = (SYNC if sync else 0) | (RENORM_ORTH if renorm == "orth" else 0)
         self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                           _ptr(U), U.stride(0), _ptr(lam)))
@@ -246,7 +290,7 @@ class Context:
         _need(S, torch.float64, 1, "S")
         if V is not None:
             _need(V, torch.float32, 2, "V")
-        mat = dense(A) if mat is None else mat
+        mat, _, _ = _as_mat(A, mat)
         out = ctypes.c_double()
         k = U.shape[1]
         self._check(self.lib.rpca_spectral_err(
@@ -288,10 +332,9 @@ class Context:
 
     def matmul(self, A, X, trans=False, center=False, mat=None):
         torch = self._torch
-        m, n = A.shape
+        mat, m, n = _as_mat(A, mat)
         l = X.shape[1]
-        Y = torch.empty(n if trans else m, l, device=A.device, dtype=torch.float32)
-        mat = dense(A) if mat is None else mat
+        Y = torch.empty(n if trans else m, l, device="cuda", dtype=torch.float32)
         self._check(self.lib.rpca_op_matmul(self.h, ctypes.byref(mat), 1 if trans else 0, l,
                                             _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
                                             CENTER if center else 0))

@@ -54,6 +54,16 @@ size_t quantize_work_bytes(int64_t m, int64_t n);
 void launch_quantize(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, int dtype,
                      void* out, int64_t ldo, float* scale, float* work);
 
+// ---- sparse A (sparse.hip) -----------------------------------------------------
+// Y[i][:lp] = sum over k in [ptr[i], ptr[i+1]) of val[k] X[idx[k]][:lp]
+// (CSR of A for A X, CSC of A = CSR of A^T for A^T X); dtype 0 float32, 1 bf16
+void launch_spmm(hipStream_t st, const int* ptr, const int* idx, const void* val, int dtype,
+                 int64_t nrows, int64_t nnz, int ncols, const float* X, int64_t ldx, float* Y,
+                 int64_t ldy, int lp);
+// the same with X, Y rows of 4 float64 (power-method blocks)
+void launch_spmm4_f64(hipStream_t st, const int* ptr, const int* idx, const void* val, int dtype,
+                      int64_t nrows, int64_t nnz, int ncols, const double* X, double* Y);
+
 // ---- tall-skinny helpers (tall.hip) -------------------------------------------
 // mu[c] = mean over rows of X[:, c] for c < cols (float64 accumulation).
 void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
@@ -124,9 +134,19 @@ void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int trans
 void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out);
 
 // ---- spectral-norm estimate (spectral.hip) -------------------------------------
+// a sparse A for the error estimate: CSR (ptr, idx, val) and CSC (ptr_t, ...)
+struct SpecSparse {
+  const int *ptr, *idx;
+  const void* val;
+  const int *ptr_t, *idx_t;
+  const void* val_t;
+  int dtype;
+  int64_t nnz;
+};
 void launch_spectral(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, bool center,
                      const float* U, int64_t ldu, const double* S, const float* V, int64_t ldv,
-                     int k, int iters, uint64_t seed, void* work, double* result);
+                     int k, int iters, uint64_t seed, void* work, double* result,
+                     const SpecSparse* sp);
 size_t spectral_work_bytes(int64_t m, int64_t n, int k);
 
 }  // namespace rpca

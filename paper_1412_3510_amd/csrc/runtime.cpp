@@ -196,10 +196,12 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.Z = ar.take<float>((size_t)round_up(n, 32) * lp);
   if (need_y2) w.Y2 = ar.take<float>((size_t)round_up(m, 32) * lp);
   w.Bk = ar.take<float>((size_t)round_up(rmax, 32) * lp);
-  w.Xp = ar.take<__bf16>(packed_bytes(pack_steps(rmax), w.nb) / sizeof(__bf16));
-  w.atx = plan_atx(m, n, w.nb, num_cus, dtype);
-  w.atx_rr = plan_atx(m, n, w.nb, num_cus, RPCA_F32);
-  w.P = ar.take<float>(std::max(w.atx.partial_bytes, w.atx_rr.partial_bytes) / sizeof(float));
+  if (dtype >= 0) {  // dense A: packed operand and split partials of A^T X
+    w.Xp = ar.take<__bf16>(packed_bytes(pack_steps(rmax), w.nb) / sizeof(__bf16));
+    w.atx = plan_atx(m, n, w.nb, num_cus, dtype);
+    w.atx_rr = plan_atx(m, n, w.nb, num_cus, RPCA_F32);
+    w.P = ar.take<float>(std::max(w.atx.partial_bytes, w.atx_rr.partial_bytes) / sizeof(float));
+  }
   w.mu = ar.take<float>(128);
   w.colpart = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
   w.colpart2 = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
@@ -235,11 +237,31 @@ rpca_status prepare(rpca_ctx ctx, Work& w, int64_t m, int64_t n, int l, bool nee
   return RPCA_OK;
 }
 
-rpca_status check_matrix(rpca_ctx ctx, const rpca_matrix* A) {
+bool is_sparse(const rpca_matrix* A) { return A->format == RPCA_SPARSE_CSR; }
+
+// layout argument: the dense copy's dtype, or -1 for a sparse A
+int layout_kind(const rpca_matrix* A) { return is_sparse(A) ? -1 : (int)A->dtype; }
+
+// need_t: the call applies A^T, so the CSC arrays must be there
+rpca_status check_sparse(rpca_ctx ctx, const rpca_matrix* A, bool need_t) {
+  if (A->dtype != RPCA_F32 && A->dtype != RPCA_BF16)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "sparse values must be float32 or bfloat16");
+  if (A->nnz < 0 || A->nnz > INT32_MAX) return fail(ctx, RPCA_ERR_INVALID_ARG, "nnz out of range");
+  if (A->m > INT32_MAX || A->n > INT32_MAX)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "sparse dimensions above 2^31 - 1");
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "CSR arrays missing");
+  if (need_t && (!A->col_ptr || (A->nnz > 0 && (!A->row_idx || !A->val_t))))
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "CSC arrays (A^T) missing");
+  return RPCA_OK;
+}
+
+rpca_status check_matrix(rpca_ctx ctx, const rpca_matrix* A, bool need_t = true) {
   if (!A) return fail(ctx, RPCA_ERR_INVALID_ARG, "A is null");
   if (A->m <= 0 || A->n <= 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "A must have m, n >= 1");
+  if (is_sparse(A)) return check_sparse(ctx, A, need_t);
   if (A->format != RPCA_DENSE_ROWMAJOR)
-    return fail(ctx, RPCA_ERR_UNSUPPORTED, "only dense row-major A is supported in this build");
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "unknown matrix format");
   if (!A->data) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->data is null");
   if (A->ld < A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "A->ld < n");
   if (A->dtype == RPCA_BF16 || A->dtype == RPCA_FP8_E4M3) {
@@ -357,6 +379,56 @@ void apply_at(rpca_ctx ctx, const AView& A, Work& w, float* Z) {
   launch_atx_reduce(ctx->stream, w.P, plan, w.nb, A.n, A.scale, Z, w.lp);
 }
 
+// Sparse passes: compulsory bytes are the index and value arrays, the
+// operand and the output once each.
+void run_spmm(rpca_ctx ctx, const rpca_matrix* A, bool trans, const Work& w, const float* X,
+              float* Y) {
+  TimedLaunch t;
+  const int64_t nrows = trans ? A->n : A->m, ncols = trans ? A->m : A->n;
+  const double vb = (A->dtype == RPCA_BF16) ? 2.0 : 4.0;
+  const double bytes = (double)(nrows + 1) * 4.0 + (double)A->nnz * (4.0 + vb) +
+                       (double)ncols * w.lp * 4.0 + (double)nrows * w.lp * 4.0;
+  begin_timed(ctx, t, trans ? 1 : 0, bytes);
+  if (trans)
+    launch_spmm(ctx->stream, A->col_ptr, A->row_idx, A->val_t, A->dtype, nrows, A->nnz,
+                (int)ncols, X, w.lp, Y, w.lp, w.lp);
+  else
+    launch_spmm(ctx->stream, A->row_ptr, A->col_idx, A->val, A->dtype, nrows, A->nnz, (int)ncols,
+                X, w.lp, Y, w.lp, w.lp);
+  end_timed(ctx, t);
+  ctx->stats.a_passes++;
+}
+
+// Y (m x lp) = A X for X (n x lp, float32, zero beyond column l)
+void apply_A(rpca_ctx ctx, const rpca_matrix* A, const AView& Av, Work& w, const float* X,
+             float* Y) {
+  if (is_sparse(A)) {
+    run_spmm(ctx, A, false, w, X, Y);
+    return;
+  }
+  pack_n_side(ctx, w, X, A->n, Av);
+  run_ax(ctx, Av, w, w.Xp, Y);
+}
+
+// Z (n x lp) = A^T Q, or A_c^T Q = A^T (Q - 1 mean(Q)) with centering
+void apply_At(rpca_ctx ctx, const rpca_matrix* A, const AView& Av, Work& w, const float* Q,
+              float* Z, bool center) {
+  if (is_sparse(A)) {
+    const float* src = Q;
+    if (center) {
+      launch_colmean(ctx->stream, Q, w.lp, A->m, w.l, w.colpart, 0, w.mu);
+      (void)hipMemcpyAsync(w.Bk, Q, (size_t)A->m * w.lp * sizeof(float), hipMemcpyDeviceToDevice,
+                           ctx->stream);
+      launch_sub_rowvec(ctx->stream, w.Bk, w.lp, A->m, w.l, w.mu);
+      src = w.Bk;
+    }
+    run_spmm(ctx, A, true, w, src, Z);
+    return;
+  }
+  pack_m_side(ctx, w, Q, A->m, center);
+  apply_at(ctx, Av, w, Z);
+}
+
 rpca_status check_kl(rpca_ctx ctx, int k, int& l, int64_t m, int64_t n) {
   if (l <= 0) l = k + 2;
   if (k < 1) return fail(ctx, RPCA_ERR_INVALID_ARG, "k must be >= 1");
@@ -449,7 +521,7 @@ rpca_status rpca_workspace_size(rpca_ctx ctx, const rpca_matrix* A, int k, int l
   if (s != RPCA_OK) return s;
   Work w;
   Arena probe;
-  layout(probe, w, A->m, A->n, l, ctx->num_cus, true, A->dtype);
+  layout(probe, w, A->m, A->n, l, ctx->num_cus, true, layout_kind(A));
   *bytes = probe.off + 256;
   return RPCA_OK;
 }
@@ -496,7 +568,7 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   const bool center = (flags & RPCA_CENTER) != 0;
   const bool orth_all = (flags & RPCA_RENORM_ORTH) != 0;
   Work w;
-  s = prepare(ctx, w, m, n, l, false, A->dtype);
+  s = prepare(ctx, w, m, n, l, false, layout_kind(A));
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
   ctx->stats.calls++;
@@ -511,27 +583,23 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   // Omega (n x l, zero padded to lp) -> packed right operand
   HIP_OK(hipMemsetAsync(w.Z, 0, (size_t)n * w.lp * sizeof(float), st));
   launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
-  pack_n_side(ctx, w, w.Z, n, Av);
   // Y = A Omega
-  run_ax(ctx, Av, w, w.Xp, w.Y);
+  apply_A(ctx, A, Av, w, w.Z, w.Y);
   if (center) center_rows(ctx, w, w.Y, m);
   if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
   else mid_renorm(w.Y, m);
   for (int it = 1; it <= its; ++it) {
     // Z = A^T Q, renormalized by LU
-    pack_m_side(ctx, w, w.Y, m, center);
-    apply_at(ctx, Av, w, w.Z);
+    apply_At(ctx, A, Av, w, w.Y, w.Z, center);
     mid_renorm(w.Z, n);
     // Y = A Q; LU except after the last application, which is orthonormalized
-    pack_n_side(ctx, w, w.Z, n, Av);
-    run_ax(ctx, Av, w, w.Xp, w.Y);
+    apply_A(ctx, A, Av, w, w.Z, w.Y);
     if (center) center_rows(ctx, w, w.Y, m);
     if (it < its) mid_renorm(w.Y, m);
     else orth_renorm(ctx, w, w.Y, m, false, seed);
   }
   // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
-  pack_m_side(ctx, w, w.Y, m, center);
-  apply_at(ctx, Ar, w, w.Z);
+  apply_At(ctx, A, Ar, w, w.Y, w.Z, center);
   orth_renorm(ctx, w, w.Z, n, true, seed + 1);
   launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
   // U = Q W, V = Q2 X, S = top k
@@ -547,7 +615,7 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
 rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
                          unsigned flags, float* U, int64_t ldu, double* lambda) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
-  rpca_status s = check_matrix(ctx, A);
+  rpca_status s = check_matrix(ctx, A, false);
   if (s != RPCA_OK) return s;
   if (A->m != A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "eig_psd needs a square matrix");
   s = check_kl(ctx, k, l, A->m, A->n);
@@ -558,7 +626,7 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   if (flags & RPCA_CENTER) return fail(ctx, RPCA_ERR_INVALID_ARG, "centering does not apply to eig_psd");
   const int64_t n = A->n;
   Work w;
-  s = prepare(ctx, w, n, n, l, true, A->dtype);
+  s = prepare(ctx, w, n, n, l, true, layout_kind(A));
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
   ctx->stats.calls++;
@@ -570,14 +638,13 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   launch_gaussian(st, seed, 0u, n, l, w.Y, w.lp, nullptr);
   if (its == 0) orth_renorm(ctx, w, w.Y, n, false, seed);
   for (int it = 1; it <= its; ++it) {
-    pack_n_side(ctx, w, w.Y, n, Av);
-    run_ax(ctx, Av, w, w.Xp, w.Y);
+    apply_A(ctx, A, Av, w, w.Y, w.Y2);
+    (void)hipMemcpyAsync(w.Y, w.Y2, (size_t)n * w.lp * sizeof(float), hipMemcpyDeviceToDevice, st);
     if (it < its && !(flags & RPCA_RENORM_ORTH)) lu_renorm(ctx, w, w.Y, n);
     else orth_renorm(ctx, w, w.Y, n, false, seed);
   }
   // B1 = A Q (start); B2 = Q* B1 (second), shifted; C = chol (Cholesky)
-  pack_n_side(ctx, w, w.Y, n, Ar);
-  run_ax(ctx, Ar, w, w.Xp, w.Y2);
+  apply_A(ctx, A, Ar, w, w.Y, w.Y2);
   launch_fro2_d(st, w.Y2, w.lp, n, l, w.colpart, w.colpart2, w.scal);
   launch_gram(st, w.Y, w.lp, n, w.lp, w.Y2, w.lp, w.gpart, w.G, nullptr);
   // unit roundoff of the copy of A that B1 was computed from
@@ -620,15 +687,17 @@ rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const f
   }
   const bool center = (flags & RPCA_CENTER) != 0;
   const AView Ar = rr_view(A);
-  if (Ar.dtype != RPCA_F32)
+  if (!is_sparse(A) && Ar.dtype != RPCA_F32)
     return fail(ctx, RPCA_ERR_UNSUPPORTED, "spectral_err reads float32 A (give data_f32)");
+  SpecSparse sp{A->row_ptr, A->col_idx, A->val, A->col_ptr, A->row_idx, A->val_t,
+                (int)A->dtype, A->nnz};
   const size_t wb = round_up(spectral_work_bytes(m, n, k), 256);
   s = ensure_ws(ctx, wb + 256);
   if (s != RPCA_OK) return s;
   double* result = reinterpret_cast<double*>(ctx->ws + wb);
   hipStream_t st = ctx->stream;
   launch_spectral(st, static_cast<const float*>(Ar.data), Ar.ld, m, n, center, U, ldu, S, V, ldv, k,
-                  iters, seed, ctx->ws, result);
+                  iters, seed, ctx->ws, result, is_sparse(A) ? &sp : nullptr);
   HIP_OK(hipGetLastError());
   double r = 0.0;
   HIP_OK(hipMemcpyAsync(&r, result, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -640,7 +709,7 @@ rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const f
 rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l, const float* X,
                            int64_t ldx, float* Y, int64_t ldy, unsigned flags) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
-  rpca_status s = check_matrix(ctx, A);
+  rpca_status s = check_matrix(ctx, A, trans != 0);
   if (s != RPCA_OK) return s;
   if (l < 1 || l > 128) return fail(ctx, RPCA_ERR_INVALID_ARG, "1 <= l <= 128");
   if (!X || !Y) return fail(ctx, RPCA_ERR_INVALID_ARG, "null operand");
@@ -649,7 +718,7 @@ rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l,
   if (ldx < l || ldy < l) return fail(ctx, RPCA_ERR_INVALID_ARG, "ld < l");
   const bool center = (flags & RPCA_CENTER) != 0;
   Work w;
-  s = prepare(ctx, w, m, n, l, false, A->dtype);
+  s = prepare(ctx, w, m, n, l, false, layout_kind(A));
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
   const AView Av = native_view(A);
@@ -660,11 +729,9 @@ rpca_status rpca_op_matmul(rpca_ctx ctx, const rpca_matrix* A, int trans, int l,
                           hipMemcpyDeviceToDevice, st));
   float* Yt = trans ? w.Z : w.Y;
   if (trans) {
-    pack_m_side(ctx, w, Xt, m, center);
-    apply_at(ctx, Av, w, Yt);
+    apply_At(ctx, A, Av, w, Xt, Yt, center);
   } else {
-    pack_n_side(ctx, w, Xt, n, Av);
-    run_ax(ctx, Av, w, w.Xp, Yt);
+    apply_A(ctx, A, Av, w, Xt, Yt);
     if (center) center_rows(ctx, w, Yt, m);
   }
   HIP_OK(hipMemcpy2DAsync(Y, ldy * sizeof(float), Yt, w.lp * sizeof(float), l * sizeof(float), yr,

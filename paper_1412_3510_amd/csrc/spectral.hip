@@ -56,13 +56,27 @@ __global__ void __launch_bounds__(256) spec_tn_partial_kernel(const float* __res
   const int64_t r1 = min(rows, r0 + kTnChunk);
   for (int o = threadIdx.x; o < nout; o += blockDim.x) {
     const int j = o / SB, q = o - j * SB;
-    double s = 0.0;
+    // four independent partial sums keep several loads in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t i = r0;
     if (j < k) {
-      for (int64_t i = r0; i < r1; ++i) s += (double)U[i * ldu + j] * T[i * SB + q];
+      for (; i + 4 <= r1; i += 4) {
+        s0 += (double)U[i * ldu + j] * T[i * SB + q];
+        s1 += (double)U[(i + 1) * ldu + j] * T[(i + 1) * SB + q];
+        s2 += (double)U[(i + 2) * ldu + j] * T[(i + 2) * SB + q];
+        s3 += (double)U[(i + 3) * ldu + j] * T[(i + 3) * SB + q];
+      }
+      for (; i < r1; ++i) s0 += (double)U[i * ldu + j] * T[i * SB + q];
     } else {
-      for (int64_t i = r0; i < r1; ++i) s += T[i * SB + q];
+      for (; i + 4 <= r1; i += 4) {
+        s0 += T[i * SB + q];
+        s1 += T[(i + 1) * SB + q];
+        s2 += T[(i + 2) * SB + q];
+        s3 += T[(i + 3) * SB + q];
+      }
+      for (; i < r1; ++i) s0 += T[i * SB + q];
     }
-    part[(int64_t)blockIdx.x * nout + o] = s;
+    part[(int64_t)blockIdx.x * nout + o] = (s0 + s1) + (s2 + s3);
   }
 }
 
@@ -272,6 +286,15 @@ __global__ void __launch_bounds__(256) spec_atx_reduce_kernel(const double* __re
 }
 
 // ---------------------------------------------------------------------------
+// Yc = Y - 1 mean(Y) (sparse A^T Y with centering); sums[q] = column sums
+__global__ void __launch_bounds__(256) spec_center_kernel(const double* __restrict__ Y, int64_t m,
+                                                          const double* __restrict__ sums,
+                                                          double* __restrict__ Yc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * SB) return;
+  Yc[e] = Y[e] - sums[e % SB] / (double)m;
+}
+
 // Cholesky QR of X (rows x SB, float64)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) spec_gram_partial_kernel(const double* __restrict__ X,
@@ -452,7 +475,7 @@ __global__ void __launch_bounds__(64) spec_final_kernel(const double* __restrict
 namespace {
 
 struct SpecLayout {
-  int64_t off_X, off_Y, off_Zp, off_part, off_vtx, off_uty, off_sum, off_rinv, total;
+  int64_t off_X, off_Y, off_Yc, off_Zp, off_part, off_vtx, off_uty, off_sum, off_rinv, total;
   int tiles, bands, parts;
   int64_t band_rows;
 };
@@ -473,6 +496,7 @@ SpecLayout spec_layout(int64_t m, int64_t n, int k) {
   };
   L.off_X = take(n * SB);
   L.off_Y = take(m * SB);
+  L.off_Yc = take(m * SB);
   L.off_Zp = take((int64_t)L.bands * n * SB);
   L.off_part = take((int64_t)L.parts * (k + 1) * SB);
   L.off_vtx = take((int64_t)(k + 1) * SB);
@@ -502,11 +526,13 @@ size_t spectral_work_bytes(int64_t m, int64_t n, int k) {
 
 void launch_spectral(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, bool center,
                      const float* U, int64_t ldu, const double* S, const float* V, int64_t ldv,
-                     int k, int iters, uint64_t seed, void* work, double* result) {
+                     int k, int iters, uint64_t seed, void* work, double* result,
+                     const SpecSparse* sp) {
   const SpecLayout L = spec_layout(m, n, k);
   double* base = static_cast<double*>(work);
   double* X = base + L.off_X;
   double* Y = base + L.off_Y;
+  double* Yc = base + L.off_Yc;
   double* Zp = base + L.off_Zp;
   double* part = base + L.off_part;
   double* vtx = base + L.off_vtx;
@@ -525,7 +551,9 @@ void launch_spectral(hipStream_t st, const float* A, int64_t lda, int64_t m, int
   // Y = E X
   auto apply_e = [&]() {
     tn_reduce(st, Vs, ldvs, k, X, n, part, vtx);
-    if (vec)
+    if (sp)
+      launch_spmm4_f64(st, sp->ptr, sp->idx, sp->val, sp->dtype, m, sp->nnz, (int)n, X, Y);
+    else if (vec)
       hipLaunchKernelGGL(spec_ax_kernel<true>, dim3(ax_grid), dim3(256), 0, st, A, lda, m, n, X, Y);
     else
       hipLaunchKernelGGL(spec_ax_kernel<false>, dim3(ax_grid), dim3(256), 0, st, A, lda, m, n, X,
@@ -538,6 +566,20 @@ void launch_spectral(hipStream_t st, const float* A, int64_t lda, int64_t m, int
     apply_e();
     // X = E^T Y, then orthonormalized
     tn_reduce(st, U, ldu, k, Y, m, part, uty);
+    if (sp) {
+      // A^T (Y - 1 mean(Y)) by the CSC gather, then the low-rank correction
+      const double* src = Y;
+      if (center) {
+        hipLaunchKernelGGL(spec_center_kernel, dim3((unsigned)ceil_div(m * SB, 256)), dim3(256), 0,
+                           st, Y, m, uty + k * SB, Yc);
+        src = Yc;
+      }
+      launch_spmm4_f64(st, sp->ptr_t, sp->idx_t, sp->val_t, sp->dtype, n, sp->nnz, (int)m, src, Zp);
+      hipLaunchKernelGGL(spec_atx_reduce_kernel, dim3((unsigned)ceil_div(n * SB, 256)), dim3(256),
+                         0, st, Zp, 1, n, Vs, ldvs, k, S, uty, X);
+      orth(st, X, n, part, Rinv);
+      continue;
+    }
     const dim3 grid((unsigned)L.tiles, (unsigned)L.bands);
     if (vec)
       hipLaunchKernelGGL(spec_atx_kernel<true>, grid, dim3(256), 0, st, A, lda, m, n, Y,

@@ -173,3 +173,22 @@ def test_range_matrix_enters_only_through_its_span():
     Ad = A.astype(np.float64)
     s_true = np.linalg.svd(Ad - Ad.mean(axis=0), compute_uv=False)
     assert np.all(S2 <= s_true[:10] * (1 + 1e-12))
+
+
+def test_sparse_input_equals_dense_definition():
+    import scipy.sparse as sps
+    from synth import sparse
+    m, n = 400, 250
+    rp, ci, va = sparse.random_rows(m, n, 8, seed=12)
+    A = sparse.to_scipy(m, n, rp, ci, va)
+    om = philox.omega(3, n, 16)
+    U0, S0, V0 = rsvd.rsvd(A.toarray(), 10, 16, 3, om)
+    U1, S1, V1 = rsvd.rsvd(A, 10, 16, 3, om)
+    np.testing.assert_allclose(S1, S0, rtol=1e-12)
+    np.testing.assert_allclose(U1, U0, atol=1e-9)
+    est0 = spectral.spectral_err_power(A.toarray(), U0, S0, V0, philox.omega(1, n, 4, stream=1), 5)
+    est1 = spectral.spectral_err_power(A, U1, S1, V1, philox.omega(1, n, 4, stream=1), 5)
+    assert est1 == pytest.approx(est0, rel=1e-10)
+    with pytest.raises(ValueError):
+        rsvd.rsvd(A, 10, 16, 3, om, center=True)
+    assert sps.issparse(A)

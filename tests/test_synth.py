@@ -55,3 +55,22 @@ def test_torch_construction_on_cpu():
     np.testing.assert_allclose(np.linalg.svd(A64, compute_uv=False), sig, atol=1e-6)
     want = np.linalg.svd(A64 - A64.mean(axis=0), compute_uv=False)
     np.testing.assert_allclose(cs, want, atol=1e-6)
+
+
+def test_sparse_rows_and_transpose():
+    import scipy.sparse as sp
+    from synth import sparse
+    m, n, r = 500, 300, 10
+    rp, ci, va = sparse.random_rows(m, n, r, seed=4)
+    assert rp.dtype == np.int32 and ci.dtype == np.int32 and va.dtype == np.float32
+    np.testing.assert_array_equal(rp, np.arange(m + 1) * r)
+    cols = ci.reshape(m, r)
+    assert np.all(np.diff(cols, axis=1) > 0)          # distinct, ascending
+    assert cols.min() >= 0 and cols.max() < n
+    A = sparse.to_scipy(m, n, rp, ci, va)
+    cp, ri, vt = sparse.transpose(m, n, rp, ci, va)
+    At = sp.csr_matrix((vt, ri, cp), shape=(n, m))
+    assert (At - A.T).nnz == 0 or np.abs((At - A.T).toarray()).max() == 0
+    # the row scale i^-1/2 on N(0,1) values: row norms shrink like sqrt(10 / i)
+    norms = np.sqrt(np.asarray(A.multiply(A).sum(axis=1)).ravel())
+    assert norms[:50].mean() > 3 * norms[-50:].mean()
