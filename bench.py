@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--no-precision", action="store_true",
                    help="skip the bfloat16 / E4M3 precision-form measurement")
     p.add_argument("--precision-steps", type=int, default=10)
+    p.add_argument("--no-sparse", action="store_true",
+                   help="skip the 10^6 x 10^6 sparse workload report")
     p.add_argument("--renorm", choices=("lu", "orth"), default="lu",
                    help="renormalization between applications: pivoted LU (the paper's) "
                         "or Cholesky QR")
@@ -135,12 +137,12 @@ def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
                       "NumPy/OpenBLAS), median %.2f s" % (nsolves, A.shape[0], n, med)}, rel
 
 
-def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="lu"):
+def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="lu", center=True):
     """Warm up, then time ``steps`` solves on the stream with events; returns
     (ms per solve, library stats over the timed solves)."""
     import torch
     for _ in range(warmup):
-        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat, renorm=renorm)
+        ctx.svd(A, k, l, its, seed, center=center, out=out, mat=mat, renorm=renorm)
     torch.cuda.synchronize()
     ctx.reset_stats()
     ctx.set_timing(True)
@@ -150,7 +152,7 @@ def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="lu"):
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        ctx.svd(A, k, l, its, seed, center=True, out=out, mat=mat, renorm=renorm)
+        ctx.svd(A, k, l, its, seed, center=center, out=out, mat=mat, renorm=renorm)
     e1.record(stream)
     torch.cuda.synchronize()
     ctx.set_timing(False)
@@ -191,6 +193,39 @@ def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps, renorm)
                      "passes_f32_rayleigh_ritz": pass_rates(st)}
         del q, sc, mat
     return res
+
+
+def sparse_workload(ctx, steps, renorm):
+    """The 10^6 x 10^6 sparse workload (10 entries per row, k = 20, l = 30,
+    its = 4): solves/s, compulsory GB/s per pass, err / sigma_{k+1}."""
+    import torch
+    import paper_1412_3510_amd as rp
+    from synth import sparse
+    m = n = 1000000
+    k, l, its, seed = 20, 30, 4, 2004
+    t0 = time.perf_counter()
+    rptr, ci, va = sparse.random_rows(m, n, 10, 1004)
+    cptr, ri, vt = sparse.transpose(m, n, rptr, ci, va)
+    dev = [torch.from_numpy(a).cuda() for a in (rptr, ci, va, cptr, ri, vt)]
+    S = rp.csr(m, n, *dev)
+    gen_s = time.perf_counter() - t0
+    U = torch.empty(m, k, device="cuda", dtype=torch.float32)
+    Sv = torch.empty(k, device="cuda", dtype=torch.float64)
+    V = torch.empty(n, k, device="cuda", dtype=torch.float32)
+    ms, st = time_solves(ctx, S, k, l, its, seed, (U, Sv, V), None, steps, 2, renorm,
+                         center=False)
+    try:
+        with open(os.path.join(HERE, "tests", "golden", "sparse_1e6_sigma.json")) as f:
+            sk1 = json.load(f)["sigma_k_plus_1"]
+    except (OSError, ValueError, KeyError):
+        sk1 = None
+    err = ctx.spectral_err(S, U, Sv, V, iters=20, seed=7)
+    return {"workload": "CSR %dx%d, 10 distinct uniform columns per row, N(0,1) i^-1/2 values; "
+                        "k=%d l=%d its=%d" % (m, n, k, l, its),
+            "solves_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 4),
+            "passes": pass_rates(st), "err_estimate": err,
+            "err_over_sigma_k1": round(err / sk1, 5) if sk1 else None,
+            "generation_s": round(gen_s, 1)}
 
 
 def main():
@@ -303,6 +338,8 @@ def main():
     }
     if prec is not None:
         out["precision_form"] = prec
+    if not args.no_sparse:
+        out["sparse"] = sparse_workload(ctx, args.precision_steps, args.renorm)
     if not args.no_cpu_baseline:
         cb, rel = cpu_baseline(A, k, l, its, args.seed, True, args.cpu_sample_solves, S_host)
         out["cpu_baseline"] = cb

@@ -126,6 +126,36 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
                          uint64_t seed, unsigned flags, float* U, int64_t ldu,
                          double* lambda);
 
+/* One problem of a batch (rpca_svd_batched).  kind 0: rpca_svd of A with
+ * outputs U, S, V; kind 1: rpca_eig_psd of A with outputs U and S (the
+ * eigenvalues), V unused.  ``flags`` takes RPCA_CENTER / RPCA_RENORM_ORTH.
+ * All pointers are device memory owned by the caller, except ``A`` (host). */
+typedef struct {
+  int32_t kind, k, l, its;
+  uint64_t seed;
+  uint32_t flags;
+  int32_t reserved; /* 0 */
+  const rpca_matrix* A;
+  float* U;
+  int64_t ldu;
+  double* S;
+  float* V;
+  int64_t ldv;
+} rpca_problem;
+
+/* Many independent solves in one call.  Every problem is checked before
+ * anything is launched.  The problems run concurrently on up to eight
+ * internal HIP streams (default priority) forked from and joined back into
+ * the context stream, so the call is ordered on that stream like a single
+ * solve and can be captured into a HIP graph there once an uncaptured call
+ * of the same batch has sized the per-stream workspaces (a capture that would
+ * need new workspace returns RPCA_ERR_UNSUPPORTED).  Each stream has its own
+ * workspace and pivot counters.  Unlike rpca_eig_psd, a PSD problem whose
+ * shifted Cholesky factor never exists is not reported (nothing is read back
+ * from the device); its eigenvalues are then not meaningful. */
+rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* problems,
+                             unsigned flags);
+
 /* Randomized power-method estimate of ||A - U diag(S) V^T||_2 (Section 4),
  * in float64: ``iters`` steps of X <- orth(E^T E X) from a Gaussian n x 4
  * start block (Philox stream 1), estimate = ||E X||_2 <= ||E||_2.

@@ -61,6 +61,24 @@ class Matrix(ctypes.Structure):
     ]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("l", ctypes.c_int32),
+        ("its", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+        ("A", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+        ("ldu", ctypes.c_int64),
+        ("S", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("ldv", ctypes.c_int64),
+    ]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("calls", ctypes.c_int64),
@@ -101,6 +119,7 @@ _SIGS = {
                           ctypes.c_uint, ctypes.POINTER(D)],
     "rpca_gaussian": [P, U64, U32, I64, I64, P, I64, P],
     "rpca_quantize": [P, P, I64, I64, I64, I32, P, I64, P],
+    "rpca_svd_batched": [P, I32, P, ctypes.c_uint],
     "rpca_op_matmul": [P, ctypes.POINTER(Matrix), I32, I32, P, I64, P, I64, ctypes.c_uint],
     "rpca_op_renorm": [P, I32, I64, I32, P, I64, P, P],
     "rpca_op_small_svd": [P, I32, P, P, P, P],
@@ -245,6 +264,11 @@ class Context:
         except Exception:
             pass
 
+    def set_stream(self, stream):
+        """Order later calls on ``stream`` (a torch CUDA stream); synchronizes the old one."""
+        self._check(self.lib.rpca_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def _check(self, st):
         if st != 0:
             msg = self.lib.rpca_last_error(self.h).decode() if getattr(self, "h", None) else ""
@@ -318,6 +342,42 @@ class Context:
         self._check(self.lib.rpca_quantize(self.h, _ptr(A), m, n, A.stride(0), code, _ptr(out),
                                            out.stride(0), _ptr(scale)))
         return out, scale
+
+    def svd_batched(self, problems, sync=False):
+        """Solve many independent problems in one call.
+
+        ``problems``: list of dicts with keys A (dense tensor or SparseMatrix),
+        k, and optionally l, its, seed, center, kind ("svd" or "psd"), renorm,
+        mat (a prepared rpca_matrix).  Returns a list of (U, S, V) for "svd"
+        and (U, lambda) for "psd"."""
+        torch = self._torch
+        arr = (Problem * len(problems))()
+        outs, mats = [], []
+        for i, pr in enumerate(problems):
+            mat, m, n = _as_mat(pr["A"], pr.get("mat"))
+            mats.append(mat)
+            k = int(pr["k"])
+            l = int(pr.get("l") or k + 2)
+            psd = pr.get("kind", "svd") == "psd"
+            U = torch.empty(m, k, device="cuda", dtype=torch.float32)
+            S = torch.empty(k, device="cuda", dtype=torch.float64)
+            V = None if psd else torch.empty(n, k, device="cuda", dtype=torch.float32)
+            q = arr[i]
+            q.kind = 1 if psd else 0
+            q.k, q.l, q.its = k, l, int(pr.get("its", 2))
+            q.seed = int(pr.get("seed", 0))
+            q.flags = (CENTER if pr.get("center") else 0) | \
+                (RENORM_ORTH if pr.get("renorm") == "orth" else 0)
+            q.A = ctypes.cast(ctypes.pointer(mat), ctypes.c_void_p)
+            q.U, q.ldu = U.data_ptr(), U.stride(0)
+            q.S = S.data_ptr()
+            if V is not None:
+                q.V, q.ldv = V.data_ptr(), V.stride(0)
+            outs.append((U, S) if psd else (U, S, V))
+        self._batch_keep = (arr, mats, problems)
+        self._check(self.lib.rpca_svd_batched(self.h, len(problems), ctypes.cast(arr, P),
+                                              SYNC if sync else 0))
+        return outs
 
     # ---- single steps --------------------------------------------------
     def gaussian(self, seed, n, l, stream=0, words=False):

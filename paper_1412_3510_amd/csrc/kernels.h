@@ -64,7 +64,11 @@ void launch_spmm(hipStream_t st, const int* ptr, const int* idx, const void* val
 void launch_spmm4_f64(hipStream_t st, const int* ptr, const int* idx, const void* val, int dtype,
                       int64_t nrows, int64_t nnz, int ncols, const double* X, double* Y);
 
-// ---- tall-skinny helpers (tall.hip) -------------------------------------------
+// ---- tall-skinny helpers (tall.hip)
+// p[0 .. count) = 0 and dst[0 .. count) = src[...]; count a multiple of 4,
+// pointers 16-byte aligned (kernel nodes only, for graph capture)
+void launch_fill_zero(hipStream_t st, float* p, int64_t count);
+void launch_copy(hipStream_t st, float* dst, const float* src, int64_t count);
 // mu[c] = mean over rows of X[:, c] for c < cols (float64 accumulation).
 void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
                     double* partial, int nblk_max, float* mu);

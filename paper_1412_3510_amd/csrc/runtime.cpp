@@ -26,6 +26,16 @@ struct TimedLaunch {
 
 }  // namespace
 
+// One stream of a batch: its own workspace and LU arrival counters.
+struct BatchSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned* counters = nullptr;
+  size_t counters_n = 0;
+};
+
 struct rpca_ctx_s {
   hipStream_t stream = nullptr;
   int device = 0;
@@ -41,6 +51,8 @@ struct rpca_ctx_s {
   std::vector<hipEvent_t> event_pool;
   rpca_stats stats{};
   int* host_state = nullptr;  // pinned
+  std::vector<BatchSlot> slots;
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -342,7 +354,7 @@ void lu_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
 void orth_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows, bool want_r, uint64_t seed) {
   hipStream_t st = ctx->stream;
   if (want_r)
-    (void)hipMemcpyAsync(w.Bk, Y, (size_t)rows * w.lp * sizeof(float), hipMemcpyDeviceToDevice, st);
+    launch_copy(st, w.Bk, Y, rows * w.lp);
   for (int pass = 1; pass <= 4; ++pass) {
     const int* skip = (pass >= 3) ? (w.state + 1) : nullptr;
     launch_gram(st, Y, w.lp, rows, w.lp, nullptr, 0, w.gpart, w.G, skip);
@@ -417,8 +429,7 @@ void apply_At(rpca_ctx ctx, const rpca_matrix* A, const AView& Av, Work& w, cons
     const float* src = Q;
     if (center) {
       launch_colmean(ctx->stream, Q, w.lp, A->m, w.l, w.colpart, 0, w.mu);
-      (void)hipMemcpyAsync(w.Bk, Q, (size_t)A->m * w.lp * sizeof(float), hipMemcpyDeviceToDevice,
-                           ctx->stream);
+      launch_copy(ctx->stream, w.Bk, Q, A->m * w.lp);
       launch_sub_rowvec(ctx->stream, w.Bk, w.lp, A->m, w.l, w.mu);
       src = w.Bk;
     }
@@ -494,6 +505,14 @@ rpca_status rpca_destroy(rpca_ctx ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->counters) (void)hipFree(ctx->counters);
   if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+  for (auto& b : ctx->slots) {
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+    if (b.ws) (void)hipFree(b.ws);
+    if (b.counters) (void)hipFree(b.counters);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+  }
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   delete ctx;
   return RPCA_OK;
 }
@@ -581,7 +600,7 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   };
 
   // Omega (n x l, zero padded to lp) -> packed right operand
-  HIP_OK(hipMemsetAsync(w.Z, 0, (size_t)n * w.lp * sizeof(float), st));
+  launch_fill_zero(st, w.Z, n * w.lp);
   launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
   // Y = A Omega
   apply_A(ctx, A, Av, w, w.Z, w.Y);
@@ -612,8 +631,14 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   return RPCA_OK;
 }
 
-rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
-                         unsigned flags, float* U, int64_t ldu, double* lambda) {
+}  // extern "C"
+
+namespace {
+// check_psd: read the Cholesky retry outcome back (synchronizes); the batched
+// path leaves it on the device.
+rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
+                         uint64_t seed, unsigned flags, float* U, int64_t ldu, double* lambda,
+                         bool check_psd) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
   rpca_status s = check_matrix(ctx, A, false);
   if (s != RPCA_OK) return s;
@@ -634,12 +659,12 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   const AView Ar = rr_view(A);      // B1 = A Q
 
   // Q = Omega; its times Q = A Q renormalized (LU, QR after the last).
-  HIP_OK(hipMemsetAsync(w.Y, 0, (size_t)n * w.lp * sizeof(float), st));
+  launch_fill_zero(st, w.Y, n * w.lp);
   launch_gaussian(st, seed, 0u, n, l, w.Y, w.lp, nullptr);
   if (its == 0) orth_renorm(ctx, w, w.Y, n, false, seed);
   for (int it = 1; it <= its; ++it) {
     apply_A(ctx, A, Av, w, w.Y, w.Y2);
-    (void)hipMemcpyAsync(w.Y, w.Y2, (size_t)n * w.lp * sizeof(float), hipMemcpyDeviceToDevice, st);
+    launch_copy(st, w.Y, w.Y2, n * w.lp);
     if (it < its && !(flags & RPCA_RENORM_ORTH)) lu_renorm(ctx, w, w.Y, n);
     else orth_renorm(ctx, w, w.Y, n, false, seed);
   }
@@ -659,6 +684,7 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   launch_finish_values(st, w.sv, k, w.scal + 1, lambda);
   launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
   HIP_OK(hipGetLastError());
+  if (!check_psd) return RPCA_OK;
   // the Cholesky retry outcome decides the status
   HIP_OK(hipMemcpyAsync(ctx->host_state, w.state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -666,6 +692,14 @@ rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   if (ctx->host_state[4])
     return fail(ctx, RPCA_ERR_NOT_PSD, "shifted B2 = Q*(A + nu I)Q not positive definite after retries");
   return RPCA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
+                         unsigned flags, float* U, int64_t ldu, double* lambda) {
+  return eig_psd_impl(ctx, A, k, l, its, seed, flags, U, ldu, lambda, true);
 }
 
 rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const float* U,
@@ -825,6 +859,136 @@ rpca_status rpca_reset_stats(rpca_ctx ctx) {
   rpca_status s = rpca_get_stats(ctx, &tmp);
   ctx->stats = rpca_stats{};
   return s;
+}
+
+
+rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* problems,
+                             unsigned flags) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (count < 0 || (count > 0 && !problems)) return fail(ctx, RPCA_ERR_INVALID_ARG, "bad batch");
+  if (count == 0) return RPCA_OK;
+  constexpr int kSlots = 8;
+  // check every problem and size its workspace
+  std::vector<size_t> ws_need(count), ctr_need(count);
+  std::vector<double> cost(count);
+  for (int p = 0; p < count; ++p) {
+    const rpca_problem& q = problems[p];
+    const std::string at = "problem " + std::to_string(p) + ": ";
+    if (q.kind != 0 && q.kind != 1) return fail(ctx, RPCA_ERR_INVALID_ARG, at + "kind must be 0 or 1");
+    rpca_status s = check_matrix(ctx, q.A, q.kind == 0);
+    if (s != RPCA_OK) return fail(ctx, s, at + ctx->err);
+    int l = q.l;
+    s = check_kl(ctx, q.k, l, q.A->m, q.A->n);
+    if (s != RPCA_OK) return fail(ctx, s, at + ctx->err);
+    if (q.its < 0) return fail(ctx, RPCA_ERR_INVALID_ARG, at + "its must be >= 0");
+    if (!q.U || !q.S || q.ldu < q.k) return fail(ctx, RPCA_ERR_INVALID_ARG, at + "bad U or S");
+    if (q.kind == 0 && (!q.V || q.ldv < q.k)) return fail(ctx, RPCA_ERR_INVALID_ARG, at + "bad V");
+    if (q.kind == 1 && (q.A->m != q.A->n || (q.flags & RPCA_CENTER)))
+      return fail(ctx, RPCA_ERR_INVALID_ARG, at + "PSD problems are square and not centered");
+    Work w;
+    Arena probe;
+    layout(probe, w, q.A->m, q.A->n, l, ctx->num_cus, q.kind == 1, layout_kind(q.A));
+    ws_need[p] = probe.off + 256;
+    ctr_need[p] = (size_t)std::max(w.lu_m.counter_total, w.lu_n.counter_total) + 16;
+    cost[p] = (double)q.A->m * q.A->n * (2.0 * q.its + 2.0) + 1e6;
+  }
+  const int ns = std::min(kSlots, count);
+  // largest problems first, each to the least loaded stream
+  std::vector<int> order(count), slot_of(count);
+  for (int p = 0; p < count; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<double> load(ns, 0.0);
+  std::vector<size_t> ws_max(ns, 0), ctr_max(ns, 0);
+  for (int p : order) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    slot_of[p] = b;
+    load[b] += cost[p];
+    ws_max[b] = std::max(ws_max[b], ws_need[p]);
+    ctr_max[b] = std::max(ctr_max[b], ctr_need[p]);
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_OK(hipStreamIsCapturing(ctx->stream, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if ((int)ctx->slots.size() < ns && capturing)
+    return fail(ctx, RPCA_ERR_UNSUPPORTED, "run the batch once before capturing it");
+  if (!ctx->fork) HIP_OK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  while ((int)ctx->slots.size() < ns) {
+    BatchSlot b;
+    HIP_OK(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+    ctx->slots.push_back(b);
+  }
+  for (int b = 0; b < ns; ++b) {
+    BatchSlot& sl = ctx->slots[b];
+    if (sl.ws_bytes < ws_max[b] || sl.counters_n < ctr_max[b]) {
+      if (capturing) return fail(ctx, RPCA_ERR_UNSUPPORTED, "run the batch once before capturing it");
+      if (ctx->ws_limit && ws_max[b] > ctx->ws_limit)
+        return fail(ctx, RPCA_ERR_NO_MEMORY, "batch workspace exceeds the limit");
+      HIP_OK(hipStreamSynchronize(sl.stream));
+      if (sl.ws_bytes < ws_max[b]) {
+        if (sl.ws) HIP_OK(hipFree(sl.ws));
+        sl.ws = nullptr;
+        sl.ws_bytes = 0;
+        void* p = nullptr;
+        if (hipMalloc(&p, ws_max[b]) != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(ctx, RPCA_ERR_NO_MEMORY, "batch workspace allocation failed");
+        }
+        sl.ws = static_cast<char*>(p);
+        sl.ws_bytes = ws_max[b];
+      }
+      if (sl.counters_n < ctr_max[b]) {
+        if (sl.counters) HIP_OK(hipFree(sl.counters));
+        sl.counters = nullptr;
+        sl.counters_n = 0;
+        void* p = nullptr;
+        if (hipMalloc(&p, ctr_max[b] * sizeof(unsigned)) != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(ctx, RPCA_ERR_NO_MEMORY, "batch counter allocation failed");
+        }
+        HIP_OK(hipMemset(p, 0, ctr_max[b] * sizeof(unsigned)));
+        sl.counters = static_cast<unsigned*>(p);
+        sl.counters_n = ctr_max[b];
+      }
+    }
+  }
+  // fork: every stream starts after the work already on the context stream
+  HIP_OK(hipEventRecord(ctx->fork, ctx->stream));
+  for (int b = 0; b < ns; ++b) HIP_OK(hipStreamWaitEvent(ctx->slots[b].stream, ctx->fork, 0));
+  // issue each problem on its stream with that stream's workspace
+  const hipStream_t st0 = ctx->stream;
+  char* const ws0 = ctx->ws;
+  const size_t wsb0 = ctx->ws_bytes;
+  unsigned* const ctr0 = ctx->counters;
+  const size_t ctrn0 = ctx->counters_n;
+  rpca_status res = RPCA_OK;
+  for (int p = 0; p < count && res == RPCA_OK; ++p) {
+    const rpca_problem& q = problems[p];
+    BatchSlot& sl = ctx->slots[slot_of[p]];
+    ctx->stream = sl.stream;
+    ctx->ws = sl.ws;
+    ctx->ws_bytes = sl.ws_bytes;
+    ctx->counters = sl.counters;
+    ctx->counters_n = sl.counters_n;
+    const unsigned f = q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH);
+    if (q.kind == 0)
+      res = rpca_svd(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, q.V, q.ldv);
+    else
+      res = eig_psd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, false);
+  }
+  ctx->stream = st0;
+  ctx->ws = ws0;
+  ctx->ws_bytes = wsb0;
+  ctx->counters = ctr0;
+  ctx->counters_n = ctrn0;
+  // join: the context stream continues after every stream's last solve
+  for (int b = 0; b < ns; ++b) {
+    HIP_OK(hipEventRecord(ctx->slots[b].done, ctx->slots[b].stream));
+    HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->slots[b].done, 0));
+  }
+  if (res != RPCA_OK) return res;
+  if (flags & RPCA_SYNC) HIP_OK(hipStreamSynchronize(ctx->stream));
+  return RPCA_OK;
 }
 
 }  // extern "C"

@@ -418,3 +418,34 @@ void launch_sign_fix(hipStream_t st, float* U, int64_t ldu, int64_t m, int k, fl
 }
 
 }  // namespace rpca
+
+namespace rpca {
+
+// Plain fills and copies as kernels (not hipMemsetAsync / hipMemcpyAsync), so
+// that a captured graph of a solve holds kernel nodes only.
+__global__ void __launch_bounds__(256) fill_zero_kernel(float4* __restrict__ p, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(256) copy_kernel(float4* __restrict__ d,
+                                                   const float4* __restrict__ s, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) d[i] = s[i];
+}
+
+void launch_fill_zero(hipStream_t st, float* p, int64_t count) {
+  const int64_t n4 = count / 4;  // callers pass multiples of 4 floats (16-byte aligned)
+  if (n4 <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)ceil_div(n4, 256)), dim3(256), 0, st,
+                     reinterpret_cast<float4*>(p), n4);
+}
+
+void launch_copy(hipStream_t st, float* dst, const float* src, int64_t count) {
+  const int64_t n4 = count / 4;
+  if (n4 <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)ceil_div(n4, 256)), dim3(256), 0, st,
+                     reinterpret_cast<float4*>(dst), reinterpret_cast<const float4*>(src), n4);
+}
+
+}  // namespace rpca

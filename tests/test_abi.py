@@ -25,6 +25,7 @@ def test_status_strings_and_struct_layout():
     # rpca_matrix: 2 int32 + 14 eight-byte fields
     assert ctypes.sizeof(rp.Matrix) == 8 + 14 * 8
     assert ctypes.sizeof(rp.Stats) == 16 * 8
+    assert ctypes.sizeof(rp.Problem) == 80
 
 
 def test_null_context_rejected():
