@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--no-precision", action="store_true",
                    help="skip the bfloat16 / E4M3 precision-form measurement")
     p.add_argument("--precision-steps", type=int, default=10)
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the 512-problem batched workload report")
     p.add_argument("--no-sparse", action="store_true",
                    help="skip the 10^6 x 10^6 sparse workload report")
     p.add_argument("--renorm", choices=("lu", "orth"), default="lu",
@@ -228,6 +230,72 @@ def sparse_workload(ctx, steps, renorm):
             "generation_s": round(gen_s, 1)}
 
 
+def batched_workload(ctx, steps):
+    """512 small problems (256 dense, 256 PSD) in one rpca_svd_batched call,
+    eager and replayed from a captured graph: problems/s and err / sigma_{k+1}."""
+    import torch
+    from synth import dense
+    t0 = time.perf_counter()
+    params = dense.batch_params()
+    probs = []
+    for q in params:
+        if q["kind"] == "svd":
+            r = min(q["m"], q["n"])
+            A, _, _ = dense.dense_torch(q["m"], q["n"], dense.spectrum_power(r), q["seed_A"], "cuda")
+            probs.append(dict(A=A, k=q["k"], l=q["l"], its=q["its"], seed=q["seed"]))
+        else:
+            A = dense.psd_torch(q["n"], dense.spectrum_exp(q["n"]), q["seed_A"], "cuda")
+            probs.append(dict(A=A, k=q["k"], l=q["l"], its=q["its"], seed=q["seed"], kind="psd"))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    s = torch.cuda.Stream()
+    ctx.set_stream(s)
+    try:
+        with torch.cuda.stream(s):
+            outs = ctx.svd_batched(probs)   # sizes the per-stream workspaces
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                outs = ctx.svd_batched(probs)
+            e1.record(s)
+            s.synchronize()
+            ms_eager = e0.elapsed_time(e1) / steps
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                gouts = ctx.svd_batched(probs)
+            g.replay()
+            s.synchronize()
+            e0.record(s)
+            for _ in range(steps):
+                g.replay()
+            e1.record(s)
+            s.synchronize()
+            ms_graph = e0.elapsed_time(e1) / steps
+    finally:
+        ctx.set_stream(torch.cuda.current_stream())
+    ratios = []
+    for q, pr, o in zip(params, probs, gouts):
+        if q["kind"] == "svd":
+            err = ctx.spectral_err(pr["A"], o[0], o[1], o[2], iters=20, seed=7)
+            sk1 = (q["k"] + 1) ** -1.5
+        else:
+            err = ctx.spectral_err(pr["A"], o[0], o[1], None, iters=20, seed=7)
+            sk1 = float(np.exp(-(q["k"] + 1) / 10.0))
+        ratios.append(err / sk1)
+    r = np.array(ratios)
+    return {"workload": "512 problems: 256 dense (m~logU[256,8192], n~logU[64,2048], "
+                        "sigma_j=j^-1.5) + 256 PSD Nystrom (n~logU[128,4096], lambda_j=e^-j/10); "
+                        "k~U{5..40}, l=k+5, its=2",
+            "ms_per_batch_eager": round(ms_eager, 3), "ms_per_batch_graph": round(ms_graph, 3),
+            "problems_per_s": round(512 * 1e3 / ms_graph, 1),
+            "err_over_sigma_k1": {"p50": round(float(np.median(r)), 4),
+                                  "p99": round(float(np.quantile(r, 0.99)), 4),
+                                  "max": round(float(r.max()), 4)},
+            "generation_s": round(gen_s, 1)}
+
+
 def main():
     args = parse()
     if args.traffic_from_pmc:
@@ -340,6 +408,8 @@ def main():
         out["precision_form"] = prec
     if not args.no_sparse:
         out["sparse"] = sparse_workload(ctx, args.precision_steps, args.renorm)
+    if not args.no_batched:
+        out["batched"] = batched_workload(ctx, 5)
     if not args.no_cpu_baseline:
         cb, rel = cpu_baseline(A, k, l, its, args.seed, True, args.cpu_sample_solves, S_host)
         out["cpu_baseline"] = cb

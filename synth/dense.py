@@ -180,3 +180,42 @@ def dense_torch(m, n, sigma, seed, device, center_spectrum=False):
         A[i:i + step] = (U[i:i + step] @ V.T).to(torch.float32)
     del U, V
     return A, np.asarray(sigma, dtype=np.float64), csig
+
+
+def psd_torch(n, lam, seed, device):
+    """Device construction of the symmetric PSD A = V diag(lam) V^T (Haar V: the
+    Householder QR of a square Gaussian in float64, columns signed so that
+    diag(R) > 0), returned as float32, exactly symmetric."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    G = torch.randn(n, n, generator=gen, device=device, dtype=torch.float64)
+    V, R = torch.linalg.qr(G)
+    d = torch.sign(torch.diagonal(R))
+    d[d == 0] = 1.0
+    V = V * d
+    lam = torch.as_tensor(np.asarray(lam, dtype=np.float64), device=device)
+    A = (V * lam) @ V.T
+    A = 0.5 * (A + A.T)
+    return A.to(torch.float32)
+
+
+def batch_params(count_dense=256, count_psd=256, seed=5000):
+    """Shapes and ranks of the batched workload: dense problems with
+    m ~ logU[256, 8192], n ~ logU[64, 2048], sigma_j = j^-1.5; PSD problems with
+    n ~ logU[128, 4096], lambda_j = exp(-j/10); k ~ U{5..40}, l = k + 5, its = 2.
+    Problem p is built with seed 10000 + p and solved with seed 20000 + p."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(count_dense + count_psd):
+        k = int(rng.integers(5, 41))
+        if p < count_dense:
+            m = int(np.exp(rng.uniform(np.log(256), np.log(8192))))
+            n = int(np.exp(rng.uniform(np.log(64), np.log(2048))))
+            out.append(dict(kind="svd", m=m, n=max(n, k + 5), k=k, l=k + 5, its=2,
+                            seed_A=10000 + p, seed=20000 + p))
+        else:
+            n = int(np.exp(rng.uniform(np.log(128), np.log(4096))))
+            out.append(dict(kind="psd", m=n, n=n, k=k, l=k + 5, its=2, seed_A=10000 + p,
+                            seed=20000 + p))
+    return out
