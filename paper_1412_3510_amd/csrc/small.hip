@@ -234,8 +234,8 @@ void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const d
 // Columns are stored contiguously in LDS (Mc[j*CS + i] = column j, row i,
 // CS = LP + 2 so columns of different pairs fall in different banks).
 // Column pairs follow the round-robin (circle) ordering, lp2/2 disjoint
-// pairs per round; each pair is handled by 8 lanes (one row block of
-// RPT = LP/8 consecutive rows each), whose partial inner products are
+// pairs per round; each pair is handled by G = 16 lanes (one row block of
+// RPT = LP/G consecutive rows each), whose partial inner products are
 // combined with DPP lane permutations.  With M Wacc = Xn diag(s):
 //   s    -- column norms, sorted descending
 //   Wacc -- accumulated rotations (orthogonal), columns in the same order
@@ -253,35 +253,40 @@ __device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
   } else if (ctrl_sel == 1) {
     lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
     hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
-  } else {
+  } else if (ctrl_sel == 2) {
     lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
     hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+  } else {  // row_mirror
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
   }
   return __hiloint2double(hi2, lo2);
 }
 
-// sum over the 8 aligned lanes of a group (all 8 get the sum)
-__device__ __forceinline__ double sum8(double v) {
+// sum over the G (8 or 16) aligned lanes of a group (all G get the sum)
+template <int G>
+__device__ __forceinline__ double sum_group(double v) {
   v += dpp_f64(v, 0);
   v += dpp_f64(v, 1);
   v += dpp_f64(v, 2);
+  if (G == 16) v += dpp_f64(v, 3);
   return v;
 }
 
-template <int LP, bool GLOBAL>
-__global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict__ M, int l,
+template <int LP, bool GLOBAL, int G>
+__global__ void __launch_bounds__(G * LP / 2) jacobi_kernel(const double* __restrict__ M, int l,
                                                      int transpose, double* __restrict__ s_out,
                                                      double* __restrict__ Wacc,
                                                      double* __restrict__ Xn,
                                                      double* __restrict__ gwork) {
   constexpr int CS = GLOBAL ? LP : LP + 2;
-  constexpr int RPT = LP / 8;  // rows per lane
-  constexpr int NT = 4 * LP;   // 8 lanes for each of the LP/2 pair slots
+  constexpr int RPT = LP / G;     // rows per lane
+  constexpr int NT = G * LP / 2;  // G lanes for each of the LP/2 pair slots
   __shared__ __attribute__((aligned(16))) double sM[GLOBAL ? 2 : LP * CS];
   __shared__ __attribute__((aligned(16))) double sV[GLOBAL ? 2 : LP * CS];
   __shared__ double sig[LP];
   __shared__ int perm[LP];
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_big;
   double* Mc = GLOBAL ? gwork : sM;
   double* Vc = GLOBAL ? gwork + LP * CS : sV;
   const int tid = threadIdx.x;
@@ -294,13 +299,20 @@ __global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict
   }
   const int lp2 = l + (l & 1);
   const int npairs = lp2 / 2;
-  const int k = tid >> 3, gl = tid & 7;  // pair slot, lane in the group of 8
+  const int k = tid / G, gl = tid % G;  // pair slot, lane in the group of G
   const bool active = (k < npairs);
   const int i0 = gl * RPT;  // this lane's first row
   const double tol = 1e-13;
+  // a sweep whose rotations all had |cos of the pair angle| <= 1e-9 leaves
+  // them near 1e-18 (cyclic Jacobi converges quadratically): the sweep that
+  // would only confirm convergence is skipped
+  const double quiet = 1e-9;
   for (int sweep = 0; sweep < 60; ++sweep) {
     __syncthreads();
-    if (tid == 0) s_rot = 0;
+    if (tid == 0) {
+      s_rot = 0;
+      s_big = 0;
+    }
     __syncthreads();
     for (int r = 0; r < lp2 - 1; ++r) {
       int p = 0, q = 0;
@@ -327,9 +339,11 @@ __global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict
           ga += mp[u] * mq[u];
         }
       }
-      al = sum8(al);
-      be = sum8(be);
-      ga = sum8(ga);
+      al = sum_group<G>(al);
+      be = sum_group<G>(be);
+      ga = sum_group<G>(ga);
+      if (go && al > 0.0 && be > 0.0 && ga * ga > (quiet * quiet) * (al * be) && gl == 0)
+        s_big = 1;
       if (go && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
         // Rutishauser's rotation; reciprocals and square roots from the
         // hardware approximations refined by Newton steps (rcp_nr, rsqrt_nr)
@@ -357,7 +371,7 @@ __global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict
       }
       __syncthreads();
     }
-    if (s_rot == 0) break;
+    if (s_rot == 0 || s_big == 0) break;
   }
   __syncthreads();
   if (tid < LP) {
@@ -391,9 +405,9 @@ __global__ void __launch_bounds__(4 * LP) jacobi_kernel(const double* __restrict
 void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
                        double* Wacc, double* Xn, double* work) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false>), dim3(1), dim3(128), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
-    case 64: hipLaunchKernelGGL((jacobi_kernel<64, false>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
-    case 128: hipLaunchKernelGGL((jacobi_kernel<128, true>), dim3(1), dim3(512), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
+    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false, 16>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
+    case 64: hipLaunchKernelGGL((jacobi_kernel<64, false, 16>), dim3(1), dim3(512), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
+    case 128: hipLaunchKernelGGL((jacobi_kernel<128, true, 16>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
     default: break;
   }
 }

@@ -11,7 +11,7 @@ namespace rpca {
 // ------------------------------------------------------------------------
 // column sums and sums of squares, float64 partials per row chunk
 // ------------------------------------------------------------------------
-static constexpr int kColChunk = 64;
+static constexpr int kColChunk = 128;
 
 int colmean_blocks(int64_t rows) { return (int)ceil_div(rows > 0 ? rows : 1, kColChunk); }
 
@@ -26,11 +26,23 @@ __global__ void __launch_bounds__(256) colstats_kernel(const float* __restrict__
   const int64_t r0 = (int64_t)blockIdx.x * kColChunk;
   double s = 0.0, q = 0.0;
   if (c < cols) {
-    for (int64_t r = r0 + p; r < r0 + kColChunk && r < rows; r += ph) {
+    const int64_t r1 = min(rows, r0 + kColChunk);
+    double s1 = 0.0, q1 = 0.0;
+    int64_t r = r0 + p;
+    for (; r + ph < r1; r += 2 * ph) {  // two rows in flight per thread
+      const double v = X[r * ldx + c], w = X[(r + ph) * ldx + c];
+      s += v;
+      q += v * v;
+      s1 += w;
+      q1 += w * w;
+    }
+    if (r < r1) {
       const double v = X[r * ldx + c];
       s += v;
       q += v * v;
     }
+    s += s1;
+    q += q1;
   }
   __shared__ double ss[256], sq[256];
   ss[threadIdx.x] = s;
@@ -47,35 +59,37 @@ __global__ void __launch_bounds__(256) colstats_kernel(const float* __restrict__
 }
 
 // out[e] = scale * sum_b part[b * stride + e] for e < E.  A workgroup owns 64
-// consecutive e; its four waves split the b range, then combine in LDS.
-__global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __restrict__ part,
-                                                              int nblk, int64_t stride, int E,
-                                                              double scale,
-                                                              double* __restrict__ out_d,
-                                                              float* __restrict__ out_f,
-                                                              const int* __restrict__ skip_flag) {
+// consecutive e; its sixteen waves split the b range (b = ph + 16 j, four
+// loads in flight), then combine in LDS in a fixed order.
+static constexpr int kRedWaves = 16;
+
+__global__ void __launch_bounds__(64 * kRedWaves) reduce_partials_kernel(
+    const double* __restrict__ part, int nblk, int64_t stride, int E, double scale,
+    double* __restrict__ out_d, float* __restrict__ out_f, const int* __restrict__ skip_flag) {
   if (skip_flag && *skip_flag == 0) return;
-  __shared__ double sh[4][64];
+  __shared__ double sh[kRedWaves][64];
   const int el = threadIdx.x & 63, ph = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
-  double acc[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (e < E) {
     int b = ph;
-    for (; b + 28 < nblk; b += 32) {
-      double v[8];
+    constexpr int W = kRedWaves;
+    for (; b + 3 * W < nblk; b += 4 * W) {
+      double v[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + 4 * u) * stride + e];
+      for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)(b + W * u) * stride + e];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += v[u];
+      for (int u = 0; u < 4; ++u) acc[u] += v[u];
     }
-    for (; b < nblk; b += 4) acc[0] += part[(int64_t)b * stride + e];
+    for (; b < nblk; b += W) acc[0] += part[(int64_t)b * stride + e];
   }
-  sh[ph][el] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  sh[ph][el] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (ph == 0 && e < E) {
-    const double s = scale * (((sh[0][el] + sh[1][el]) + sh[2][el]) + sh[3][el]);
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRedWaves; ++w) s += sh[w][el];
+    s *= scale;
     if (out_d) out_d[e] = s;
     if (out_f) out_f[e] = (float)s;
   }
@@ -83,8 +97,8 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __re
 
 static void launch_reduce(hipStream_t st, const double* part, int nblk, int64_t stride, int E,
                           double scale, double* out_d, float* out_f, const int* skip_flag) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(E, 64)), dim3(256), 0, st,
-                     part, nblk, stride, E, scale, out_d, out_f, skip_flag);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(E, 64)), dim3(64 * kRedWaves),
+                     0, st, part, nblk, stride, E, scale, out_d, out_f, skip_flag);
 }
 
 void launch_colmean(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols,
@@ -221,10 +235,15 @@ __global__ void __launch_bounds__(256) trsm_kernel(float* __restrict__ X, int64_
                                                    const float* __restrict__ nu,
                                                    const float* __restrict__ addX, int64_t ldadd) {
   if (skip_flag && *skip_flag == 0) return;
-  __shared__ float sU[LP * LP];
+  // column j of U stored contiguously (sUt[j][i] = U[i][j]) so the solve reads
+  // four entries per LDS access
+  __shared__ __attribute__((aligned(16))) float sU[LP * LP];
   __shared__ float sd[LP];
   __shared__ int sp[LP];
-  for (int e = threadIdx.x; e < LP * LP; e += 256) sU[e] = Ut[e];
+  for (int e = threadIdx.x; e < LP * LP; e += 256) {
+    const int i = e / LP, j = e % LP;
+    sU[j * LP + i] = Ut[e];
+  }
   if (threadIdx.x < LP) {
     const int j = threadIdx.x;
     const float d = (j < l) ? Ut[j * LP + j] : 0.f;
@@ -254,8 +273,9 @@ __global__ void __launch_bounds__(256) trsm_kernel(float* __restrict__ X, int64_
   for (int j = 0; j < LP; ++j) {
     if (j < l) {
       float s = x[j];
+      const float* col = sU + j * LP;
 #pragma unroll
-      for (int i = 0; i < j; ++i) s -= x[i] * sU[i * LP + j];
+      for (int i = 0; i < j; ++i) s -= x[i] * col[i];
       const float d = sd[j];
       x[j] = (d != 0.f) ? s * d : ((row == sp[j]) ? 1.f : 0.f);
     } else {
