@@ -5,14 +5,14 @@
 //
 // Tall Y (up to 10^6 rows) cannot be factored column by column with a
 // grid-wide argmax per column, so pivots are chosen by tournament (Grigori,
-// Demmel and Xiang's CALU): every block of NT rows (NT = 512 by default;
-// one row per thread) runs Gaussian elimination with
-// partial pivoting on its own rows and nominates its l pivot rows; the
-// nominated original rows of F = NT/lp blocks are merged by the same
-// elimination, level after level, until one set of l rows is left; its
-// elimination gives U.  The levels run inside one launch: the last
-// workgroup to finish a group (an atomic arrival counter) merges it, so no
-// grid-wide barrier is needed and every workgroup exits after its own block.
+// Demmel and Xiang's CALU): every block of R rows (R = 512 by default, 512
+// threads) runs Gaussian elimination with partial pivoting on its own rows
+// and nominates its l pivot rows; the nominated original rows of F = R/lp
+// blocks are merged by the same elimination, level after level, until one
+// set of l rows is left; its elimination gives U.  The levels run inside one
+// launch: the last workgroup to finish a group (an atomic arrival counter)
+// merges it, so no grid-wide barrier is needed and every workgroup exits
+// after its own block.
 // Counters are reset by the workgroup that consumed them.
 //
 // Zero pivots follow LAPACK's getrf: when the remaining column is exactly
@@ -33,60 +33,24 @@ struct LuLevels {
   int cnt_off[16];
 };
 
-template <int LP, int NT_>
+template <int LP, int R_, int NT_>
 struct LuCfg {
-  static constexpr int NT = NT_;       // threads = rows per block
-  static constexpr int NW = NT / 64;   // waves
-  static constexpr int F = NT / LP;    // candidate sets merged per block
+  static constexpr int R = R_;          // rows per block
+  static constexpr int NT = NT_;        // threads
+  static constexpr int NW = NT / 64;    // waves
+  static constexpr int RPL = R / 64;    // rows per lane
+  static constexpr int CPW = LP / NW;   // columns per wave (frame slots)
+  static constexpr int F = R / LP;      // candidate sets merged per block
+  static constexpr int KB = (R <= 255) ? 8 : (R <= 511 ? 9 : (R <= 1023 ? 10 : 11));
+  static constexpr unsigned KMASK = (1u << KB) - 1u;  // bits for R - local row
+  static constexpr int SROW = LP + 1;                 // staging row stride (floats)
+  static constexpr int STAGE = 2 * 64 * SROW;         // two 64-row staging buffers
+  static constexpr int SHARED = STAGE > LP * LP ? STAGE : LP * LP;  // staging, then U
+  static constexpr int PF = 64 * LP / 4 / NT;         // float4 loads per thread per chunk
+  static constexpr int PD = (LP >= 128) ? 2 : 3;      // chunks in flight
+  static_assert(RPL % 4 == 0 && CPW >= 2 && PF >= 1 && R % LP == 0, "LU block shape");
 };
 
-// row[c] <- row[c+1] - mult * prow[c+1] for c < W - 1 (the moving frame, see
-// gepp_block), prow streamed from LDS four values at a time.
-template <int W, int LP>
-__device__ __forceinline__ void shift_update(float (&row)[LP], float mult, const float* prow) {
-  static_assert(W <= LP && W % 4 == 0, "width");
-  float4 cur = *reinterpret_cast<const float4*>(prow);
-#pragma unroll
-  for (int c = 0; c < W; c += 4) {
-    const float4 nxt = (c + 4 < W) ? *reinterpret_cast<const float4*>(prow + c + 4)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
-    row[c] = row[c + 1] - mult * cur.y;
-    row[c + 1] = row[c + 2] - mult * cur.z;
-    row[c + 2] = row[c + 3] - mult * cur.w;
-    if (c + 4 < W) row[c + 3] = row[c + 4] - mult * nxt.x;
-    else row[c + 3] = 0.f;
-    cur = nxt;
-  }
-}
-
-template <int LP>
-__device__ __forceinline__ void shift_bucket(float (&row)[LP], float mult, const float* prow,
-                                             int live) {
-  if (LP >= 128 && live > 96) shift_update<(LP >= 128 ? 128 : 16), LP>(row, mult, prow);
-  else if (LP >= 128 && live > 64) shift_update<(LP >= 128 ? 96 : 16), LP>(row, mult, prow);
-  else if (LP >= 64 && live > 48) shift_update<(LP >= 64 ? 64 : 16), LP>(row, mult, prow);
-  else if (LP >= 64 && live > 32) shift_update<(LP >= 64 ? 48 : 16), LP>(row, mult, prow);
-  else if (live > 16) shift_update<(LP >= 32 ? 32 : 16), LP>(row, mult, prow);
-  else shift_update<16, LP>(row, mult, prow);
-}
-
-// Gaussian elimination with partial pivoting over the rows held by the NT
-// threads of a workgroup (one row per thread, in registers).  The row is kept
-// in a moving frame: before step p, register c holds column p + c, and the
-// elimination update writes the shifted row, so the current column is always
-// row[0] and no register is addressed by a run-time index.
-//
-// The pivot search works on one 32-bit key per row: the top bits of |row[0]|
-// (sign, exponent and 13 fraction bits) above NT - tid in the low KB bits,
-// 0 for rows that are no longer candidates.  The largest key is the largest
-// |value| up to 2^-13 relative (so |L| <= 1 + 2^-13), ties going to the lower
-// thread slot; |values| below 2^-100 count as zero; every key is distinct, so a wave maximum (six DPP max steps)
-// names its row.  Per step: the wave maximum, the wave winner's live row and
-// global index to LDS, one barrier, the maximum of the NW wave keys, the pivot
-// row streamed from LDS into the update of the live columns.  A key whose
-// value bits are all zero is a zero pivot (LAPACK getrf: nothing is
-// eliminated and U[p][p] = 0).  When ``U`` (LDS) is given the eliminated
-// pivot rows (row p of U = pivot row in frame p) are written to it.
 __device__ __forceinline__ unsigned dpp_max_u32(unsigned v, int sel) {
   unsigned o;
   switch (sel) {
@@ -106,112 +70,274 @@ __device__ __forceinline__ unsigned wave_max_key(unsigned k) {
   return (unsigned)__builtin_amdgcn_readlane((int)k, 63);
 }
 
-template <int LP, int NT>
-__device__ __forceinline__ void gepp_block(float (&row)[LP], bool cand, int gidx, int l,
-                                           int* s_piv, unsigned* s_wkey, int* s_widx,
-                                           float* s_wrow, float* U) {
-  constexpr int NW = LuCfg<LP, NT>::NW;
-  constexpr int KB = (NT <= 255) ? 8 : (NT <= 511 ? 9 : (NT <= 1023 ? 10 : 11));  // bits for NT - tid
-  constexpr unsigned KMASK = (1u << KB) - 1u;
-  static_assert(NT <= (int)KMASK, "slot bits");
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const unsigned slot = (unsigned)(NT - tid);  // 1 .. NT
-  for (int p = 0; p < l; ++p) {
-    const int buf = p & 1;
-    const int live = l - p;
-    // values below 2^-100 count as zero pivots (their reciprocal would overflow)
-    const float a0 = fabsf(row[0]);
-    const unsigned vbits = (a0 >= 7.8886091e-31f) ? (__float_as_uint(a0) & ~KMASK) : 0u;
-    const unsigned key = cand ? (vbits | slot) : 0u;
-    const unsigned wmax = wave_max_key(key);
-    if (wmax != 0u && key == wmax) {  // this wave's candidate for the pivot
-      s_wkey[buf * NW + wave] = wmax;
-      s_widx[buf * NW + wave] = gidx;
-      float4* dst = reinterpret_cast<float4*>(s_wrow + (buf * NW + wave) * LP);
-#pragma unroll
-      for (int c = 0; c < LP; c += 4)
-        if (c < live) dst[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
-    } else if (wmax == 0u && lane == 0) {
-      s_wkey[buf * NW + wave] = 0u;
-    }
-    __syncthreads();
-    unsigned gk = 0u;
-#pragma unroll
-    for (int w = 0; w < NW; w += 4) {
-      const uint4 k4 = *reinterpret_cast<const uint4*>(s_wkey + buf * NW + w);
-      gk = max(gk, max(max(k4.x, k4.y), max(k4.z, k4.w)));
-    }
-    const bool have = gk != 0u;  // some candidate row was left
-    const int wt = NT - (int)(gk & KMASK);  // thread slot of the pivot row
-    const int bw = have ? (wt >> 6) : 0;
-    const float* prow = s_wrow + (buf * NW + bw) * LP;
-    const bool nonzero = (gk & ~KMASK) != 0u;
-    if (tid == 0) s_piv[p] = have ? s_widx[buf * NW + bw] : -1;
-    if (U && tid < LP)  // LDS
-      U[p * LP + tid] = (have && tid >= p && tid < l && (nonzero || tid > p)) ? prow[tid - p] : 0.f;
-    const float inv = nonzero ? __builtin_amdgcn_rcpf(prow[0]) : 0.f;
-    float mult = 0.f;
-    if (cand && tid == wt) cand = false;
-    else if (cand) mult = row[0] * inv;
-    shift_bucket<LP>(row, mult, prow, live);
-  }
-  __syncthreads();
+__device__ __forceinline__ float lane_read(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <int LP, int NT_>
-__global__ void __launch_bounds__(NT_) lu_tree_kernel(const float* __restrict__ X, int64_t ldx,
-                                                      int64_t rows, int l, LuLevels lv,
-                                                      int* __restrict__ cand,
-                                                      unsigned* __restrict__ counters,
-                                                      float* __restrict__ U,
-                                                      int* __restrict__ piv) {
-  constexpr int NT = LuCfg<LP, NT_>::NT, NW = LuCfg<LP, NT_>::NW, F = LuCfg<LP, NT_>::F;
-  __shared__ int s_piv[LP];
-  __shared__ __attribute__((aligned(16))) unsigned s_wkey[2 * NW];
-  __shared__ __attribute__((aligned(16))) int s_widx[2 * NW];
-  __shared__ __attribute__((aligned(16))) float s_wrow[2 * NW * LP];
-  __shared__ float s_U[LP * LP];  // U of the root block (global stores stay out of the steps)
+// Gaussian elimination with partial pivoting over the R rows of a block,
+// distributed by columns: lane `lane` of every wave holds rows lane + 64 s
+// (s < RPL); wave w holds columns w + NW t in slots t < CPW.  The steps run in
+// CPW super-steps of NW steps; in super-step B the pivot column j = NW B + wp
+// is slot B of wave wp, and slots below B hold finished columns, so slot
+// indices are compile-time constants (template recursion over B) and no
+// register is addressed by a run-time index.
+//
+// A step: the wave that holds column j finds the pivot within the wave (one
+// 32-bit key per row, six DPP max steps), forms the multipliers of its rows
+// and writes them and the key to LDS (double buffered by step parity); after
+// one barrier every wave reads them, takes the pivot row's entries of its own
+// columns from the owning lane (readlane) and updates its columns.  Slots B
+// and B + 1 (one of which holds column j + 1) are updated first, then the
+// wave that holds column j + 1 publishes step j + 1, then the other slots are
+// updated.  The update has no branches (a slot that is not live gets a zero
+// pivot-row entry), so the row registers stay in place.
+//
+// Rows are never swapped.  A row leaves the candidate set (a bit per row) when
+// it becomes a pivot; it is still updated with the rest, but never read again.
+// Key: the top bits of |a| (exponent and 13 fraction bits) above R - local
+// row in the low KB bits, 0 for a non-candidate.  The largest key is the
+// largest |value| up to 2^-13 relative (|L| <= 1 + 2^-13 within a block), ties
+// going to the lower row.  A pivot below 2^-100 (including 0) is a zero
+// pivot, as in LAPACK getrf for an exactly zero column: nothing is eliminated
+// and U[j][j] = 0.
+template <int LP, int R, int NT>
+struct Gepp {
+  using C = LuCfg<LP, R, NT>;
+  static constexpr int RPL = C::RPL, CPW = C::CPW, NW = C::NW;
+  static constexpr unsigned KMASK = C::KMASK;
+  static constexpr unsigned VMASK = 0x7fffffffu & ~KMASK;  // |value| bits of a key
+  static constexpr unsigned TINY = 0x0d800000u;            // 2^-100
+
+  struct Ctx {
+    int lane, w, l;
+    unsigned live;  // slots whose column is < l
+    int* s_lr;
+    float* s_mult;
+    unsigned* s_key;
+    float* sU;
+  };
+
+  // a[.][T] -= m * (slot T live ? u[T] : 0)
+  template <int T>
+  static __device__ __forceinline__ void update(float (&a)[RPL][CPW], const float (&m)[RPL],
+                                                const float (&u)[CPW], unsigned lm) {
+    const float ut = ((lm >> T) & 1u) ? u[T] : 0.f;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) a[s][T] -= m[s] * ut;
+  }
+
+  // Pivot search on slot T (the owner wave); multipliers and key to LDS.
+  template <int T>
+  static __device__ __forceinline__ void publish(const float (&a)[RPL][CPW], unsigned cm,
+                                                 const Ctx& c, int j) {
+    unsigned best = 0u;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const unsigned key = (__float_as_uint(a[s][T]) & VMASK) | (unsigned)(R - 64 * s - c.lane);
+      best = max(best, ((cm >> s) & 1u) ? key : 0u);
+    }
+    const unsigned wmax = wave_max_key(best);
+    const bool nonzero = (wmax & ~KMASK) >= TINY;
+    const int lr = R - (int)(wmax & KMASK);  // local pivot row (R when there is none)
+    const int ls = lr & 63, ss = lr >> 6;
+    float pv = 0.f;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s)
+      if (s == ss) pv = lane_read(a[s][T], ls);
+    const float inv = nonzero ? __builtin_amdgcn_rcpf(pv) : 0.f;
+    float4* dst = reinterpret_cast<float4*>(c.s_mult + (j & 1) * R + c.lane * RPL);
+#pragma unroll
+    for (int s = 0; s < RPL; s += 4)
+      dst[s / 4] = make_float4(a[s][T] * inv, a[s + 1][T] * inv, a[s + 2][T] * inv,
+                               a[s + 3][T] * inv);
+    if (c.lane == 0) {
+      c.s_key[j & 1] = wmax;
+      if (wmax != 0u) {
+        c.s_lr[j] = lr;
+        if (c.sU) c.sU[j * LP + j] = nonzero ? pv : 0.f;
+      }
+    }
+  }
+
+  template <int T>
+  static __device__ __forceinline__ void update_from(float (&a)[RPL][CPW], const float (&m)[RPL],
+                                                     const float (&u)[CPW], unsigned lm) {
+    if constexpr (T < CPW) {
+      update<T>(a, m, u, lm);
+      update_from<T + 1>(a, m, u, lm);
+    }
+  }
+
+  // The NW steps of super-step B, then the next super-step.  Returns at the
+  // end or when no candidate row is left (the same for every wave).
+  template <int B>
+  static __device__ __forceinline__ void steps(float (&a)[RPL][CPW], unsigned& cm,
+                                               const Ctx& c) {
+    if constexpr (B < CPW) {
+      for (int wp = 0; wp < NW; ++wp) {
+        const int j = NW * B + wp;
+        if (j >= c.l) return;
+        __syncthreads();
+        float m[RPL];
+        const float4* src =
+            reinterpret_cast<const float4*>(c.s_mult + (j & 1) * R + c.lane * RPL);
+#pragma unroll
+        for (int s = 0; s < RPL; s += 4) {
+          const float4 v = src[s / 4];
+          m[s] = v.x; m[s + 1] = v.y; m[s + 2] = v.z; m[s + 3] = v.w;
+        }
+        const unsigned key = (unsigned)__builtin_amdgcn_readfirstlane((int)c.s_key[j & 1]);
+        if (key == 0u) return;
+        const bool nz = (key & ~KMASK) >= TINY;
+        const int lr = R - (int)(key & KMASK), ls = lr & 63, ss = lr >> 6;
+        float u[CPW];
+#pragma unroll
+        for (int t = 0; t < CPW; ++t) u[t] = 0.f;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s)
+          if (s == ss) {
+#pragma unroll
+            for (int t = B; t < CPW; ++t) u[t] = lane_read(a[s][t], ls);
+          }
+        if (c.lane == ls) cm &= ~(1u << ss);
+        // live slots: column w + NW t is right of j and left of l
+        unsigned lm = c.live;
+        if (c.w <= wp) lm &= ~(1u << B);
+        if (c.sU && c.lane == 0) {
+#pragma unroll
+          for (int t = B; t < CPW; ++t)
+            if ((lm >> t) & 1u) c.sU[j * LP + c.w + NW * t] = u[t];
+        }
+        if (!nz) lm = 0u;
+        update<B>(a, m, u, lm);
+        if constexpr (B + 1 < CPW) update<B + 1>(a, m, u, lm);
+        const int jn = j + 1;
+        if (jn < c.l && c.w == (wp + 1) % NW) {
+          // column j + 1: slot B, or slot B + 1 when it starts the next super-step
+          if (wp != NW - 1) {
+            publish<B>(a, cm, c, jn);
+          } else {
+            if constexpr (B + 1 < CPW) publish<B + 1>(a, cm, c, jn);
+          }
+        }
+        update_from<B + 2>(a, m, u, lm);
+      }
+      steps<B + 1>(a, cm, c);
+    }
+  }
+
+  // a: the block's rows (see above, zero where a row does not exist); valid:
+  // bit s = row lane + 64 s exists.  Writes s_lr[j] (local pivot row, left as
+  // is when no candidate remains) and, when sU is given, U (LDS, zeroed by
+  // the caller).
+  static __device__ __forceinline__ void run(float (&a)[RPL][CPW], unsigned valid, int l,
+                                             int* s_lr, float* s_mult, unsigned* s_key,
+                                             float* sU) {
+    Ctx c;
+    c.lane = threadIdx.x & 63;
+    c.w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    c.l = l;
+    const int left = l - c.w;
+    const int t1 = left <= 0 ? 0 : min(CPW, (left + NW - 1) / NW);
+    c.live = (t1 >= 32) ? ~0u : ((1u << t1) - 1u);
+    c.s_lr = s_lr;
+    c.s_mult = s_mult;
+    c.s_key = s_key;
+    c.sU = sU;
+    unsigned cm = valid;  // candidate rows (bit s: row lane + 64 s)
+    if (c.w == 0 && l > 0) publish<0>(a, cm, c, 0);
+    steps<0>(a, cm, c);
+    __syncthreads();
+  }
+};
+
+template <int LP, int R, int NT>
+__global__ void __launch_bounds__(NT) lu_tree_kernel(const float* __restrict__ X, int64_t ldx,
+                                                     int64_t rows, int l, LuLevels lv,
+                                                     int* __restrict__ cand,
+                                                     unsigned* __restrict__ counters,
+                                                     float* __restrict__ U,
+                                                     int* __restrict__ piv) {
+  using C = LuCfg<LP, R, NT>;
+  constexpr int NW = C::NW, RPL = C::RPL, CPW = C::CPW, F = C::F, SROW = C::SROW, PF = C::PF,
+                PD = C::PD;
+  __shared__ int s_lr[LP];  // local pivot rows
+  __shared__ int s_gidx[R];
+  __shared__ __attribute__((aligned(16))) float s_mult[2 * R];
+  __shared__ unsigned s_key[2];
+  __shared__ __attribute__((aligned(16))) float s_big[C::SHARED];  // staging, then U of the root
   __shared__ int s_last;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   int level = 0, blk = blockIdx.x;
   while (true) {
-    float row[LP];
-    bool valid = false;
-    int gidx = 0x7fffffff;
-    if (level == 0) {
-      const int64_t r = (int64_t)blk * NT + tid;
-      valid = r < rows;
-      gidx = (int)r;
-    } else {
-      const int child = blk * F + tid / LP, p = tid % LP;
-      if (child < lv.nblk[level - 1] && p < l) {
-        const int ci = __hip_atomic_load(&cand[lv.cand_off[level - 1] + child * LP + p],
-                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ci >= 0) {
-          valid = true;
-          gidx = ci;
+    // global row of each local row (-1: none)
+    for (int i = tid; i < R; i += NT) {
+      int g = -1;
+      if (level == 0) {
+        const int64_t r = (int64_t)blk * R + i;
+        if (r < rows) g = (int)r;
+      } else {
+        const int child = blk * F + i / LP, p = i % LP;
+        if (child < lv.nblk[level - 1] && p < l) {
+          const int ci = __hip_atomic_load(&cand[lv.cand_off[level - 1] + child * LP + p],
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (ci >= 0) g = ci;
         }
       }
+      s_gidx[i] = g;
     }
-    if (valid) {
-      const float* src = X + (int64_t)gidx * ldx;
+    if (tid < LP) s_lr[tid] = -1;
+    __syncthreads();
+    unsigned valid = 0u;
 #pragma unroll
-      for (int c = 0; c < LP; c += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(src + c);
-        row[c] = v.x; row[c + 1] = v.y; row[c + 2] = v.z; row[c + 3] = v.w;
+    for (int s = 0; s < RPL; ++s)
+      if (s_gidx[64 * s + lane] >= 0) valid |= 1u << s;
+    // rows to registers through LDS, 64 rows at a time (coalesced float4 loads
+    // PD chunks ahead, two staging buffers, one barrier per chunk)
+    float a[RPL][CPW];
+    float4 pre[RPL][PF];
+    auto load = [&](int s) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int e = tid + NT * q, rr = e / (LP / 4), c4 = e % (LP / 4);
+        const int g = s_gidx[64 * s + rr];
+        pre[s][q] = (g >= 0) ? *reinterpret_cast<const float4*>(X + (int64_t)g * ldx + 4 * c4)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-    } else {
+    };
 #pragma unroll
-      for (int c = 0; c < LP; ++c) row[c] = 0.f;
+    for (int s = 0; s < PD && s < RPL; ++s) load(s);
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      float* st = s_big + (s & 1) * 64 * SROW;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int e = tid + NT * q, rr = e / (LP / 4), c = 4 * (e % (LP / 4));
+        st[rr * SROW + c] = pre[s][q].x;
+        st[rr * SROW + c + 1] = pre[s][q].y;
+        st[rr * SROW + c + 2] = pre[s][q].z;
+        st[rr * SROW + c + 3] = pre[s][q].w;
+      }
+      if (s + PD < RPL) load(s + PD);
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < CPW; ++t) a[s][t] = st[lane * SROW + w + NW * t];
     }
     const bool root = (lv.nblk[level] == 1);
-    gepp_block<LP, NT>(row, valid, gidx, l, s_piv, s_wkey, s_widx, s_wrow, root ? s_U : nullptr);
+    __syncthreads();  // staging reads are done before U overwrites it
+    if (root)
+      for (int e = tid; e < LP * LP; e += NT) s_big[e] = 0.f;
+    __syncthreads();
+    Gepp<LP, R, NT>::run(a, valid, l, s_lr, s_mult, s_key, root ? s_big : nullptr);
+    int pg = -1;  // global index of pivot tid
+    if (tid < l && s_lr[tid] >= 0) pg = s_gidx[s_lr[tid]];
     if (root) {
-      if (tid < LP) piv[tid] = (tid < l) ? s_piv[tid] : -1;
-      for (int e = tid; e < LP * LP; e += NT) U[e] = (e < l * LP) ? s_U[e] : 0.f;
+      if (tid < LP) piv[tid] = pg;
+      for (int e = tid; e < LP * LP; e += NT) U[e] = s_big[e];
       return;
     }
-    if (tid < LP) cand[lv.cand_off[level] + blk * LP + tid] = (tid < l) ? s_piv[tid] : -1;
+    if (tid < LP) cand[lv.cand_off[level] + blk * LP + tid] = pg;
     __threadfence();
     __syncthreads();
     const int parent = blk / F;
@@ -231,11 +357,11 @@ __global__ void __launch_bounds__(NT_) lu_tree_kernel(const float* __restrict__ 
   }
 }
 
-// rows per block (= threads); RPCA_LU_NT overrides for tuning
+// rows per block (512 threads each); RPCA_LU_ROWS overrides for tuning
 static int lu_block_rows(int lp) {
   static int env = -1;
   if (env < 0) {
-    const char* e = getenv("RPCA_LU_NT");
+    const char* e = getenv("RPCA_LU_ROWS");
     env = e ? atoi(e) : 0;
   }
   int nt = 512;
@@ -280,20 +406,21 @@ void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, i
     if (i >= 1) acc += plan.nblk[i];
   }
   const dim3 grid((unsigned)plan.nblk[0]);
-  const int nt = lu_block_rows(plan.lp);
-#define LU_LAUNCH(LP_, NT_)                                                                  \
-  hipLaunchKernelGGL((lu_tree_kernel<LP_, NT_>), grid, dim3(NT_), 0, st, X, ldx, rows, l, lv, \
-                     cand, counters, U, piv)
+  const int r = lu_block_rows(plan.lp);
+#define LU_LAUNCH(LP_, R_)                                                                    \
+  hipLaunchKernelGGL((lu_tree_kernel<LP_, R_, 512>), grid, dim3(512), 0, st, X, ldx, rows, l, \
+                     lv, cand, counters, U, piv)
   if (plan.lp == 32) {
-    if (nt == 1024) LU_LAUNCH(32, 1024);
-    else if (nt == 512) LU_LAUNCH(32, 512);
+    if (r == 1024) LU_LAUNCH(32, 1024);
+    else if (r == 512) LU_LAUNCH(32, 512);
     else LU_LAUNCH(32, 256);
   } else if (plan.lp == 64) {
-    if (nt == 1024) LU_LAUNCH(64, 1024);
-    else if (nt == 512) LU_LAUNCH(64, 512);
+    if (r == 1024) LU_LAUNCH(64, 1024);
+    else if (r == 512) LU_LAUNCH(64, 512);
     else LU_LAUNCH(64, 256);
   } else if (plan.lp == 128) {
-    LU_LAUNCH(128, 512);
+    if (r == 256) LU_LAUNCH(128, 256);
+    else LU_LAUNCH(128, 512);
   }
 #undef LU_LAUNCH
 }
