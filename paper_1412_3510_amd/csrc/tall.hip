@@ -151,45 +151,84 @@ void launch_fro2_d(hipStream_t st, const float* X, int64_t ldx, int64_t rows, in
 }
 
 // ------------------------------------------------------------------------
-// Gram matrix G = X^T X2 in float64 (X2 = X when null).  Each workgroup
-// accumulates a 256-row block; a 16 x 16 grid of threads owns T x T tiles of
-// the lp x lp result (T = lp / 16).  Rows are staged in LDS 32 at a time.
+// Gram matrix G = X^T X2 in float64 (X2 = X when null).  The rows are split
+// into at most kGramMaxBlocks equal contiguous ranges, one workgroup each
+// (about one per CU).  A workgroup has NG groups of 256 threads (NG = 4 for
+// tall inputs, so that four slices of loads are in flight per CU, else 1);
+// within a group a 16 x 16 grid of threads owns T x T tiles of the lp x lp
+// result (T = lp / 16).  The range is walked in slices of 32 rows, slice s
+// going to group s % NG; a slice is widened to float64 once in LDS, and the
+// next one is loaded into registers while the current one is used.  At the
+// end the groups' sums are added in LDS in group order.  Products of float32
+// values are exact in float64.
 // ------------------------------------------------------------------------
-static constexpr int kGramRows = 256;
+static constexpr int kGramMaxBlocks = 256;
+static constexpr int kGramSlice = 32;
+static constexpr int64_t kGramTall = (int64_t)kGramMaxBlocks * kGramSlice * 4;  // NG = 4 from here
 
-int gram_blocks(int64_t rows) { return (int)ceil_div(rows > 0 ? rows : 1, kGramRows); }
+template <int LP, int NG>
+struct GramCfg {
+  static constexpr int STAGE = 2 * kGramSlice * LP;  // doubles per group (X and X2 slices)
+  static constexpr int COMB = (NG - 1) * LP * LP;    // doubles for the combination
+  static constexpr int SHARED = NG * STAGE > COMB ? NG * STAGE : COMB;
+};
 
-template <int LP>
-__global__ void __launch_bounds__(256) gram_kernel(const float* __restrict__ X, int64_t ldx,
-                                                   const float* __restrict__ X2, int64_t ldx2,
-                                                   int64_t rows, double* __restrict__ partial,
-                                                   const int* __restrict__ skip_flag) {
+static int gram_grid(int64_t rows, int ng) {
+  const int64_t b = ceil_div(rows > 0 ? rows : 1, (int64_t)kGramSlice * ng);
+  return (int)(b < kGramMaxBlocks ? b : kGramMaxBlocks);
+}
+
+int gram_blocks(int64_t rows) { return gram_grid(rows, 1); }  // an upper bound for any lp
+
+template <int LP, int NG>
+__global__ void __launch_bounds__(256 * NG) gram_kernel(const float* __restrict__ X, int64_t ldx,
+                                                        const float* __restrict__ X2,
+                                                        int64_t ldx2, int64_t rows,
+                                                        double* __restrict__ partial,
+                                                        const int* __restrict__ skip_flag) {
   if (skip_flag && *skip_flag == 0) return;
   constexpr int T = LP / 16;
-  __shared__ float sa[32][LP];
-  __shared__ float sb[32][LP];
-  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+  constexpr int PER = kGramSlice * LP / 256;  // values per thread per slice
+  __shared__ __attribute__((aligned(16))) double sh[GramCfg<LP, NG>::SHARED];
+  const int g = threadIdx.x >> 8, tid = threadIdx.x & 255, ti = tid >> 4, tj = tid & 15;
+  const bool same = (X2 == nullptr);
+  double* sa = sh + g * GramCfg<LP, NG>::STAGE;
+  double* sb = same ? sa : sa + kGramSlice * LP;
+  const int64_t r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
   double acc[T][T];
 #pragma unroll
   for (int a = 0; a < T; ++a)
 #pragma unroll
     for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
-  const bool same = (X2 == nullptr);
-  for (int64_t rc = r0; rc < r0 + kGramRows && rc < rows; rc += 32) {
-    for (int e = tid; e < 32 * LP; e += 256) {
-      const int rr = e / LP, c = e % LP;
+  float pa[PER], pb[PER];
+  auto load = [&](int64_t rc) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, rr = e / LP, c = e % LP;
       const int64_t r = rc + rr;
-      sa[rr][c] = (r < rows) ? X[r * ldx + c] : 0.f;
-      if (!same) sb[rr][c] = (r < rows) ? X2[r * ldx2 + c] : 0.f;
+      pa[q] = (r < r1) ? X[r * ldx + c] : 0.f;
+      if (!same) pb[q] = (r < r1) ? X2[r * ldx2 + c] : 0.f;
+    }
+  };
+  constexpr int64_t kStep = (int64_t)kGramSlice * NG;
+  load(r0 + g * kGramSlice);
+  for (int64_t rb = r0; rb < r1; rb += kStep) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, rr = e / LP, c = e % LP;
+      sa[rr * LP + c] = (double)pa[q];
+      if (!same) sb[rr * LP + c] = (double)pb[q];
     }
     __syncthreads();
-    for (int rr = 0; rr < 32; ++rr) {
+    if (rb + kStep < r1) load(rb + kStep + g * kGramSlice);
+    for (int rr = 0; rr < kGramSlice; ++rr) {
       double a[T], b[T];
 #pragma unroll
-      for (int u = 0; u < T; ++u) {
-        a[u] = sa[rr][ti * T + u];
-        b[u] = same ? sa[rr][tj * T + u] : sb[rr][tj * T + u];
+      for (int u = 0; u < T; u += 2) {
+        const double2 va = *reinterpret_cast<const double2*>(&sa[rr * LP + ti * T + u]);
+        const double2 vb = *reinterpret_cast<const double2*>(&sb[rr * LP + tj * T + u]);
+        a[u] = va.x; a[u + 1] = va.y;
+        b[u] = vb.x; b[u + 1] = vb.y;
       }
 #pragma unroll
       for (int u = 0; u < T; ++u)
@@ -197,6 +236,23 @@ __global__ void __launch_bounds__(256) gram_kernel(const float* __restrict__ X, 
         for (int v = 0; v < T; ++v) acc[u][v] += a[u] * b[v];
     }
     __syncthreads();
+  }
+  if constexpr (NG > 1) {
+    if (g > 0) {
+      double* cb = sh + (g - 1) * LP * LP;
+#pragma unroll
+      for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) cb[(ti * T + u) * LP + tj * T + v] = acc[u][v];
+    }
+    __syncthreads();
+    if (g > 0) return;
+#pragma unroll
+    for (int h = 0; h < NG - 1; ++h)
+#pragma unroll
+      for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) acc[u][v] += sh[h * LP * LP + (ti * T + u) * LP + tj * T + v];
   }
   double* out = partial + (int64_t)blockIdx.x * LP * LP;
 #pragma unroll
@@ -208,13 +264,19 @@ __global__ void __launch_bounds__(256) gram_kernel(const float* __restrict__ X, 
 void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int lp,
                  const float* X2, int64_t ldx2, double* partial, double* G,
                  const int* skip_flag) {
-  const int nblk = gram_blocks(rows);
+  // four row groups for tall inputs (lp <= 64; lp = 128 has no LDS for them)
+  const int ng = (rows >= kGramTall && lp <= 64) ? 4 : 1;
+  const int nblk = gram_grid(rows, ng);
+#define GRAM_GO(LP_, NG_)                                                                      \
+  hipLaunchKernelGGL((gram_kernel<LP_, NG_>), dim3(nblk), dim3(256 * NG_), 0, st, X, ldx, X2,   \
+                     ldx2, rows, partial, skip_flag)
   switch (lp) {
-    case 32: hipLaunchKernelGGL(gram_kernel<32>, dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2, rows, partial, skip_flag); break;
-    case 64: hipLaunchKernelGGL(gram_kernel<64>, dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2, rows, partial, skip_flag); break;
-    case 128: hipLaunchKernelGGL(gram_kernel<128>, dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2, rows, partial, skip_flag); break;
+    case 32: if (ng == 4) GRAM_GO(32, 4); else GRAM_GO(32, 1); break;
+    case 64: if (ng == 4) GRAM_GO(64, 4); else GRAM_GO(64, 1); break;
+    case 128: GRAM_GO(128, 1); break;
     default: return;
   }
+#undef GRAM_GO
   const int lp2 = lp * lp;
   launch_reduce(st, partial, nblk, lp2, lp2, 1.0, G, nullptr, skip_flag);
 }
