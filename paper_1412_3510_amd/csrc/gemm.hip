@@ -210,19 +210,24 @@ __global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A
 // multiplied by zero rows of packed X or never stored.
 // ========================================================================
 // ---------------- Y = A X --------------------------------------------------
-// Stage: 32 columns of a 128-row tile (16 KB of A, rows 8b..8b+7 per 1 KB DMA
-// block b; the 16-byte chunk c of row R sits at position c ^ ((R >> 1) & 7))
-// plus the matching 2 x NB packed X fragments.
-template <int NB, int S>
-__global__ void __launch_bounds__(256) ax_dma_kernel(const float* __restrict__ A, int64_t lda,
-                                                     int64_t m, int64_t n,
-                                                     const __bf16* __restrict__ Xp,
-                                                     float* __restrict__ Y, int64_t ldy,
-                                                     int64_t rows_per_wg) {
+// NW waves on a 32 NW-row tile.  Stage: 32 columns of the tile (4 NW KB of A,
+// rows 8b..8b+7 per 1 KB DMA block b; the 16-byte chunk c of row R sits at
+// position c ^ ((R >> 1) & 7)) plus the matching 4 NB packed X fragments, XW
+// per wave.  With NW = 8 one workgroup holds a CU's whole LDS, so a deeper
+// ring keeps more bytes of A in flight per CU.
+template <int NB, int S, int NW>
+__global__ void __launch_bounds__(64 * NW) ax_dma_kernel(const float* __restrict__ A,
+                                                         int64_t lda, int64_t m, int64_t n,
+                                                         const __bf16* __restrict__ Xp,
+                                                         float* __restrict__ Y, int64_t ldy,
+                                                         int64_t rows_per_wg) {
   constexpr int KC = 32;
-  constexpr int ABYTES = 16384;
+  constexpr int TR = 32 * NW;             // tile rows
+  constexpr int ABYTES = TR * 128;
   constexpr int STAGE = ABYTES + NB * 4096;
-  constexpr int PER = 4 + NB;  // DMA instructions per wave per stage
+  constexpr int XW = 4 * NB / NW;         // X fragments per wave per stage
+  static_assert(XW * NW == 4 * NB, "X fragments per wave");
+  constexpr int PER = 4 + XW;  // DMA instructions per wave per stage
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -235,7 +240,7 @@ __global__ void __launch_bounds__(256) ax_dma_kernel(const float* __restrict__ A
   const int lrow = lane >> 3;  // row within the 8-row block
   const int g = lane >> 5;
 
-  for (int64_t row0 = rbeg; row0 < rend; row0 += 128) {
+  for (int64_t row0 = rbeg; row0 < rend; row0 += TR) {
     const float* rowp[4];
     int cofs[4];
 #pragma unroll
@@ -253,8 +258,8 @@ __global__ void __launch_bounds__(256) ax_dma_kernel(const float* __restrict__ A
       const int64_t col_ = stg_ * KC + cofs[i];                                           \
       dma16(rowp[i] + (col_ < n ? col_ : 0), slot_ + (4 * wave + i) * 1024);              \
     }                                                                                     \
-    _Pragma("unroll") for (int i = 0; i < NB; ++i) {                                      \
-      const int blk_ = wave + 4 * i;                                                      \
+    _Pragma("unroll") for (int i = 0; i < XW; ++i) {                                      \
+      const int blk_ = wave + NW * i;                                                     \
       dma16(xg + (stg_ * (NB * 4) + blk_) * 1024 + 16 * lane, slot_ + ABYTES + blk_ * 1024); \
     }                                                                                     \
   } while (0)
@@ -315,38 +320,47 @@ __global__ void __launch_bounds__(256) ax_dma_kernel(const float* __restrict__ A
 }
 
 // ---------------- Z = A^T X (split-K partials) ------------------------------
-// Stage: 32 rows of a 128-column tile (16 KB; rows 2b, 2b+1 per DMA block b;
+// NW waves on a 32 NW-column tile (wave w: columns 32w..32w+31 of it).
+// Stage: 32 rows of the tile (4 NW KB; RPB = 2 or 1 rows per 1 KB DMA block;
 // the 16-byte chunk c of row r sits at position c ^ (8 ((r >> 3) & 1))) plus
-// the matching packed X fragments.
-template <int NB, int S>
-__global__ void __launch_bounds__(256) atx_dma_kernel(const float* __restrict__ A, int64_t lda,
-                                                      int64_t m, int64_t n,
-                                                      const __bf16* __restrict__ Xp,
-                                                      float* __restrict__ P, int ntiles,
-                                                      int64_t rows_per) {
+// the matching 4 NB packed X fragments, XW per wave.  The workgroup index
+// gives (split, tile) over gtiles tiles per split; partials are laid out by
+// 32-column block, ntiles * 4 blocks per split (ntiles = ceil(n / 128)),
+// whatever the tile width.
+template <int NB, int S, int NW>
+__global__ void __launch_bounds__(64 * NW) atx_dma_kernel(const float* __restrict__ A,
+                                                          int64_t lda, int64_t m, int64_t n,
+                                                          const __bf16* __restrict__ Xp,
+                                                          float* __restrict__ P, int gtiles,
+                                                          int ntiles, int64_t rows_per) {
   constexpr int KC = 32;
-  constexpr int ABYTES = 16384;
+  constexpr int TC = 32 * NW;           // tile columns
+  constexpr int ABYTES = KC * TC * 4;
   constexpr int STAGE = ABYTES + NB * 4096;
-  constexpr int PER = 4 + NB;
+  constexpr int RPB = 1024 / (TC * 4);  // rows per DMA block
+  constexpr int LPR = 64 / RPB;         // lanes per row
+  constexpr int XW = 4 * NB / NW;       // X fragments per wave per stage
+  static_assert(RPB >= 1 && XW * NW == 4 * NB, "tile shape");
+  constexpr int PER = 4 + XW;
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int split = t / ntiles, tile = t % ntiles;
-  const int64_t col0 = (int64_t)tile * 128;
+  const int split = t / gtiles, tile = t % gtiles;
+  const int64_t col0 = (int64_t)tile * TC;
   const int64_t rbeg = (int64_t)split * rows_per;
   const int64_t rend = (rbeg + rows_per < m) ? rbeg + rows_per : m;
   const int64_t nstage = (rend > rbeg) ? ceil_div(rend - rbeg, KC) : 0;
   const char* xg = reinterpret_cast<const char*>(Xp) + (rbeg / 16) * NB * 2 * 1024;
 
-  // DMA: block b = 4 * wave + i covers stage rows 2b + (lane >> 5)
+  // DMA: block b = 4 * wave + i covers stage rows RPB b + lane / LPR
   int64_t colc[4];
   int rr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int b = 4 * wave + i;
-    rr[i] = 2 * b + (lane >> 5);
-    const int chunk = (lane & 31) ^ (8 * ((rr[i] >> 3) & 1));
+    rr[i] = RPB * b + lane / LPR;
+    const int chunk = (lane % LPR) ^ (8 * ((rr[i] >> 3) & 1));
     int64_t c = col0 + 4 * chunk;
     colc[i] = (c + 4 <= n) ? c : 0;
   }
@@ -358,8 +372,8 @@ __global__ void __launch_bounds__(256) atx_dma_kernel(const float* __restrict__ 
       const int64_t grow_ = min(rbeg + stg_ * KC + rr[i], rend - 1);                      \
       dma16(A + grow_ * lda + colc[i], slot_ + (4 * wave + i) * 1024);                    \
     }                                                                                     \
-    _Pragma("unroll") for (int i = 0; i < NB; ++i) {                                      \
-      const int blk_ = wave + 4 * i;                                                      \
+    _Pragma("unroll") for (int i = 0; i < XW; ++i) {                                      \
+      const int blk_ = wave + NW * i;                                                     \
       dma16(xg + (stg_ * (NB * 4) + blk_) * 1024 + 16 * lane, slot_ + ABYTES + blk_ * 1024); \
     }                                                                                     \
   } while (0)
@@ -389,7 +403,7 @@ __global__ void __launch_bounds__(256) atx_dma_kernel(const float* __restrict__ 
       bf16x8 bh, bl;
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        const float x = Af[(16 * s + 8 * g + jj) * 128 + word];
+        const float x = Af[(16 * s + 8 * g + jj) * TC + word];
         __bf16 th, tl;
         split_bf16(x, th, tl);
         bh[jj] = th;
@@ -404,7 +418,9 @@ __global__ void __launch_bounds__(256) atx_dma_kernel(const float* __restrict__ 
     }
     barrier_mem();
   }
-  float* out = P + ((int64_t)(split * ntiles + tile) * 4 + wave) * NB * 1024;
+  const int blk32 = tile * NW + wave;  // 32-column block of this wave
+  if (blk32 >= ntiles * 4) return;      // columns past the partial layout (beyond n)
+  float* out = P + ((int64_t)split * ntiles * 4 + blk32) * NB * 1024;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
@@ -433,20 +449,40 @@ static bool dma_ok(const float* A, int64_t lda, int64_t n) {
   return !env && (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (n % 4) == 0;
 }
 
+// waves per workgroup of the Y = A X kernel: 8 (one workgroup per CU, a
+// four-stage ring) for nb = 2 on tall A, else 4; RPCA_AX_WAVES=4 overrides
+static int ax_waves(int nb, int64_t m, int num_cus) {
+  static int env = -1;
+  if (env < 0) {
+    const char* e = getenv("RPCA_AX_WAVES");
+    env = e ? atoi(e) : 0;
+  }
+  if (env == 4) return 4;
+  return (nb == 2 && m >= (int64_t)num_cus * 256) ? 8 : 4;
+}
+
 template <int NB>
 static void launch_ax_dma(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n,
                           const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
-  const int S = ring_depth(NB);
-  const int per_cu = std::max(1, (160 * 1024) / (S * dma_stage_bytes(NB)));
+  const int nw = ax_waves(NB, m, num_cus);
+  const int S = nw == 8 ? 4 : ring_depth(NB);
+  const int stage = 32 * nw * 128 + NB * 4096;
+  const int per_cu = std::max(1, (160 * 1024) / (S * stage));
   int64_t G = (int64_t)num_cus * per_cu;
   G = std::min<int64_t>(G, ceil_div(m, 32));
   const int64_t rows_per = ceil_div(m, G);
   G = ceil_div(m, rows_per);
   const dim3 grid((unsigned)G);
+  if constexpr (NB == 2) {
+    if (nw == 8) {
+      hipLaunchKernelGGL((ax_dma_kernel<2, 4, 8>), grid, dim3(512), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per);
+      return;
+    }
+  }
   switch (S) {
-    case 2: hipLaunchKernelGGL((ax_dma_kernel<NB, 2>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
-    case 4: hipLaunchKernelGGL((ax_dma_kernel<NB, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
-    default: hipLaunchKernelGGL((ax_dma_kernel<NB, 3>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
+    case 2: hipLaunchKernelGGL((ax_dma_kernel<NB, 2, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
+    case 4: hipLaunchKernelGGL((ax_dma_kernel<NB, 4, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
+    default: hipLaunchKernelGGL((ax_dma_kernel<NB, 3, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
   }
 }
 
@@ -570,15 +606,32 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
     for (int r = 0; r < 16; ++r) out[(cb * 16 + r) * 64 + lane] = acc[cb][r];
 }
 
+// waves per workgroup of the float32 A^T X DMA kernel: 8 (256-column tiles,
+// one workgroup per CU, a four-stage ring) for nb = 2 on wide, tall A, else 4;
+// RPCA_ATX_WAVES=4 overrides
+static int atx_waves(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
+  static int env = -1;
+  if (env < 0) {
+    const char* e = getenv("RPCA_ATX_WAVES");
+    env = e ? atoi(e) : 0;
+  }
+  if (env == 4) return 4;
+  return (dtype == 0 && nb == 2 && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4;
+}
+
 AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
   AtxPlan p;
   p.ntiles = (int)ceil_div(n, 128);
+  p.waves = atx_waves(m, n, nb, num_cus, dtype);
+  p.gtiles = (int)ceil_div(n, 32 * p.waves);
   const int rs = dtype == 0 ? 32 : lp_rows_per_stage(dtype);  // rows per stage
   const int64_t stages = ceil_div(m, rs);
   // workgroups resident per CU for the LDS ring of the DMA kernel
-  const int per_cu = dtype == 0 ? std::max(1, (160 * 1024) / (ring_depth(nb) * dma_stage_bytes(nb)))
+  const int per_cu = dtype == 0 ? (p.waves == 8 ? 1
+                                                : std::max(1, (160 * 1024) / (ring_depth(nb) *
+                                                                              dma_stage_bytes(nb))))
                                 : lp_per_cu(nb, dtype);
-  int64_t want = (int64_t)per_cu * num_cus / p.ntiles;
+  int64_t want = (int64_t)per_cu * num_cus / p.gtiles;
   if (want < 1) want = 1;
   int64_t maxs = stages / 4;
   if (maxs < 1) maxs = 1;
@@ -597,11 +650,17 @@ void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m
   const dim3 grid((unsigned)(plan.ntiles * plan.nsplit));
   if (dma_ok(Af, lda, n)) {
     const int S = ring_depth(nb);
+    if (plan.waves == 8 && nb == 2) {
+      hipLaunchKernelGGL((atx_dma_kernel<2, 4, 8>), dim3((unsigned)(plan.gtiles * plan.nsplit)),
+                         dim3(512), 0, st, Af, lda, m, n, Xp, P, plan.gtiles, plan.ntiles,
+                         plan.rows_per);
+      return;
+    }
 #define ATX_DMA(NB_)                                                                                 \
   switch (S) {                                                                                       \
-    case 2: hipLaunchKernelGGL((atx_dma_kernel<NB_, 2>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per); break; \
-    case 4: hipLaunchKernelGGL((atx_dma_kernel<NB_, 4>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per); break; \
-    default: hipLaunchKernelGGL((atx_dma_kernel<NB_, 3>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.rows_per); break; \
+    case 2: hipLaunchKernelGGL((atx_dma_kernel<NB_, 2, 4>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.ntiles, plan.rows_per); break; \
+    case 4: hipLaunchKernelGGL((atx_dma_kernel<NB_, 4, 4>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.ntiles, plan.rows_per); break; \
+    default: hipLaunchKernelGGL((atx_dma_kernel<NB_, 3, 4>), grid, dim3(256), 0, st, Af, lda, m, n, Xp, P, plan.ntiles, plan.ntiles, plan.rows_per); break; \
   }
     switch (nb) {
       case 1: ATX_DMA(1); return;

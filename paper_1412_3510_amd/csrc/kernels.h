@@ -25,7 +25,9 @@ void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m,
 
 // Split-K partial products of A^T X (X packed on the m side).
 struct AtxPlan {
-  int ntiles;        // ceil(n / 128)
+  int ntiles;        // ceil(n / 128): the partials hold 4 * ntiles 32-column blocks per split
+  int waves;         // waves per workgroup of the float32 DMA kernel (4 or 8)
+  int gtiles;        // column tiles of that kernel, ceil(n / (32 * waves))
   int nsplit;        // number of row splits
   int64_t rows_per;  // rows per split (multiple of 32)
   size_t partial_bytes;
