@@ -345,14 +345,25 @@ __global__ void __launch_bounds__(G * LP / 2) jacobi_kernel(const double* __rest
       if (go && al > 0.0 && be > 0.0 && ga * ga > (quiet * quiet) * (al * be) && gl == 0)
         s_big = 1;
       if (go && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
-        // Rutishauser's rotation; reciprocals and square roots from the
-        // hardware approximations refined by Newton steps (rcp_nr, rsqrt_nr)
-        const double zeta = (be - al) * (0.5 * rcp_nr(ga));
-        const double w = fma(zeta, zeta, 1.0);
-        // beyond |zeta| = 1e150, w would overflow; there t = 1 / (2 zeta) to
-        // working precision
-        const double t = (fabs(zeta) < 1e150) ? copysign(rcp_nr(fabs(zeta) + w * rsqrt_nr(w)), zeta)
-                                               : 0.5 * rcp_nr(zeta);
+        // Rutishauser's rotation, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+        // with zeta = (be - al) / (2 ga), evaluated as
+        // t = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (one
+        // reciprocal fewer on the critical path); reciprocals and square
+        // roots from the hardware approximations refined by Newton steps
+        // (rcp_nr, rsqrt_nr)
+        const double d = be - al;
+        double t;
+        if (fabs(d) < 1e150 && fabs(ga) < 1e150) {
+          const double h2 = fma(d, d, 4.0 * ga * ga);
+          const double h = h2 * rsqrt_nr(h2);
+          // sign(zeta) = sign(d) sign(ga), with d = +0 counting as positive
+          t = copysign(2.0 * fabs(ga) * rcp_nr(fabs(d) + h), d >= 0.0 ? ga : -ga);
+        } else {  // huge entries: the zeta form, which cannot overflow in h2
+          const double zeta = d * (0.5 * rcp_nr(ga));
+          t = (fabs(zeta) < 1e150)
+                  ? copysign(rcp_nr(fabs(zeta) + fma(zeta, zeta, 1.0) * rsqrt_nr(fma(zeta, zeta, 1.0))), zeta)
+                  : 0.5 * rcp_nr(zeta);
+        }
         const double c = rsqrt_nr(fma(t, t, 1.0)), s = c * t;
 #pragma unroll
         for (int u = 0; u < RPT; u += 2) {
