@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--precision-steps", type=int, default=10)
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 512-problem batched workload report")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the autotuner (built-in tile configurations)")
     p.add_argument("--no-sparse", action="store_true",
                    help="skip the 10^6 x 10^6 sparse workload report")
     p.add_argument("--renorm", choices=("lu", "orth"), default="lu",
@@ -182,6 +184,7 @@ def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps, renorm)
     for kind in ("bf16", "fp8"):
         q, sc = ctx.quantize(A, kind)
         mat = rp.dense(q, col_scale=sc, A_f32=A)
+        ctx.tune(q, l, reps=2, mat=mat)   # the tournament of this class
         U = torch.empty(m, k, device=A.device, dtype=torch.float32)
         S = torch.empty(k, device=A.device, dtype=torch.float64)
         V = torch.empty(n, k, device=A.device, dtype=torch.float32)
@@ -248,6 +251,16 @@ def batched_workload(ctx, steps):
             probs.append(dict(A=A, k=q["k"], l=q["l"], its=q["its"], seed=q["seed"], kind="psd"))
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
+    # the autotuner: one problem of each shape class (log2 m, log2 n, padded l)
+    t1 = time.perf_counter()
+    classes = {}
+    for pr in probs:
+        m_, n_ = pr["A"].shape
+        key = ((m_ - 1).bit_length(), (n_ - 1).bit_length(), 32 if pr["l"] <= 32 else 64)
+        classes.setdefault(key, pr)
+    for pr in classes.values():
+        ctx.tune(pr["A"], pr["l"], reps=2)
+    tune_s = time.perf_counter() - t1
     s = torch.cuda.Stream()
     ctx.set_stream(s)
     try:
@@ -289,6 +302,7 @@ def batched_workload(ctx, steps):
                         "sigma_j=j^-1.5) + 256 PSD Nystrom (n~logU[128,4096], lambda_j=e^-j/10); "
                         "k~U{5..40}, l=k+5, its=2",
             "ms_per_batch_eager": round(ms_eager, 3), "ms_per_batch_graph": round(ms_graph, 3),
+            "autotuned_classes": len(classes), "autotune_s": round(tune_s, 1),
             "problems_per_s": round(512 * 1e3 / ms_graph, 1),
             "err_over_sigma_k1": {"p50": round(float(np.median(r)), 4),
                                   "p99": round(float(np.quantile(r, 0.99)), 4),
@@ -324,6 +338,11 @@ def main():
     S = torch.empty(k, device=dev, dtype=torch.float64)
     V = torch.empty(n, k, device=dev, dtype=torch.float32)
     mat = rp.dense(A)
+    tuned = None
+    if not args.no_tune:
+        # the autotuner picks the tile configurations of this shape class
+        tuned = ctx.tune(A, l, reps=3, mat=mat)
+        print("autotune: %s" % tuned, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ctx.svd(A, k, l, its, args.seed, center=True, out=(U, S, V), mat=mat, renorm=args.renorm)
     torch.cuda.synchronize()
@@ -400,6 +419,8 @@ def main():
                                "1e-3*exp(-(j-51)/200); k=%d l=%d its=%d" % (m, n, k, l, its),
                    "m": m, "n": n, "k": k, "l": l, "its": its, "center": True, "renorm": args.renorm},
         "passes": passes,
+        "autotune": ({kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in tuned.items()}
+                     if tuned else None),
         "roofline": roofline,
         "sigma_k_plus_1": sk1,
         "err_over_sigma_k1": round(err_f32 / sk1, 5),

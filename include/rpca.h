@@ -233,6 +233,41 @@ rpca_status rpca_set_timing(rpca_ctx ctx, int enable);
 rpca_status rpca_get_stats(rpca_ctx ctx, rpca_stats* out);
 rpca_status rpca_reset_stats(rpca_ctx ctx);
 
+/* ---- autotuner -----------------------------------------------------------
+ * The float32 A-pass kernels and the LU pivot tournament have tile
+ * configurations whose best choice depends on the shape: waves per workgroup
+ * and LDS ring depth of Y = A X and of A^T X, and rows per tournament block.
+ * rpca_tune times every candidate on the caller's dense A with l sketch
+ * columns (one warm-up and ``reps`` timed launches each, reps < 1 means 3),
+ * using the context's stream and workspace (A is only read; the call
+ * synchronizes the stream), and keeps the fastest in the context's table
+ * under the shape class of A: (ceil log2 m, ceil log2 n, l padded to
+ * 32/64/128, dtype).  Later rpca_svd, rpca_eig_psd and rpca_svd_batched
+ * calls on matrices of that class use it.  Only a float32 A has A-pass
+ * alternatives; for a low-precision copy the tournament alone is tuned.
+ * ``out`` (nullable) receives the choice and the average launch time of each
+ * chosen configuration.  Sparse A: RPCA_ERR_UNSUPPORTED. */
+typedef struct {
+  int32_t ax_waves, ax_ring;    /* Y = A X: waves per workgroup, ring stages */
+  int32_t atx_waves, atx_ring;  /* A^T X                                     */
+  int32_t lu_rows;              /* rows per tournament block                 */
+  int32_t candidates;           /* configurations timed                      */
+  double ms_ax, ms_atx;         /* ms per launch (A^T X with its reduction)  */
+  double ms_lu;                 /* ms per tournament, m side plus n side     */
+} rpca_tune_result;
+rpca_status rpca_tune(rpca_ctx ctx, const rpca_matrix* A, int32_t l, int32_t reps,
+                      rpca_tune_result* out);
+/* The table as text, one shape class a line:
+ *   log2m log2n lp dtype ax_waves ax_ring atx_waves atx_ring lu_rows
+ * (lines starting with '#' are comments).  Loading adds to the table and
+ * replaces entries of the same class; a malformed line fails with
+ * RPCA_ERR_INVALID_ARG and leaves the table as it was. */
+rpca_status rpca_tune_save(rpca_ctx ctx, const char* path);
+rpca_status rpca_tune_load(rpca_ctx ctx, const char* path);
+rpca_status rpca_tune_clear(rpca_ctx ctx);
+/* Number of shape classes in the table. */
+rpca_status rpca_tune_count(rpca_ctx ctx, int32_t* count);
+
 const char* rpca_status_str(rpca_status s);
 const char* rpca_last_error(rpca_ctx ctx);
 

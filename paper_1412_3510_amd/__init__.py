@@ -103,6 +103,23 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("ax_waves", ctypes.c_int32),
+        ("ax_ring", ctypes.c_int32),
+        ("atx_waves", ctypes.c_int32),
+        ("atx_ring", ctypes.c_int32),
+        ("lu_rows", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("ms_ax", ctypes.c_double),
+        ("ms_atx", ctypes.c_double),
+        ("ms_lu", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 P, I32, I64, U32, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                             ctypes.c_uint64, ctypes.c_double)
@@ -126,6 +143,11 @@ _SIGS = {
     "rpca_set_timing": [P, I32],
     "rpca_get_stats": [P, ctypes.POINTER(Stats)],
     "rpca_reset_stats": [P],
+    "rpca_tune": [P, ctypes.POINTER(Matrix), I32, I32, ctypes.POINTER(TuneResult)],
+    "rpca_tune_save": [P, ctypes.c_char_p],
+    "rpca_tune_load": [P, ctypes.c_char_p],
+    "rpca_tune_clear": [P],
+    "rpca_tune_count": [P, ctypes.POINTER(I32)],
 }
 
 
@@ -421,6 +443,29 @@ class Context:
         X = torch.empty(l, l, device=M.device, dtype=torch.float64)
         self._check(self.lib.rpca_op_small_svd(self.h, l, _ptr(M), _ptr(s), _ptr(W), _ptr(X)))
         return W, s, X
+
+    # ---- autotuner ----------------------------------------------------
+    def tune(self, A, l, reps=3, mat=None):
+        """Time the tile configurations on dense A with l sketch columns and keep the
+        fastest for A's shape class; returns the choice and its times (ms per launch)."""
+        mat, _, _ = _as_mat(A, mat)
+        res = TuneResult()
+        self._check(self.lib.rpca_tune(self.h, ctypes.byref(mat), l, reps, ctypes.byref(res)))
+        return res.as_dict()
+
+    def tune_save(self, path):
+        self._check(self.lib.rpca_tune_save(self.h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        self._check(self.lib.rpca_tune_load(self.h, os.fsencode(path)))
+
+    def tune_clear(self):
+        self._check(self.lib.rpca_tune_clear(self.h))
+
+    def tune_count(self):
+        c = I32()
+        self._check(self.lib.rpca_tune_count(self.h, ctypes.byref(c)))
+        return c.value
 
     # ---- diagnostics ---------------------------------------------------
     def set_timing(self, on=True):

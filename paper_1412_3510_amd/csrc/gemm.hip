@@ -428,15 +428,8 @@ __global__ void __launch_bounds__(64 * NW) atx_dma_kernel(const float* __restric
 #undef ATX_ISSUE
 }
 
-static int ring_depth(int nb) {
-  static int env = -1;
-  if (env < 0) {
-    const char* e = getenv("RPCA_RING");
-    env = e ? atoi(e) : 0;
-  }
-  if (env >= 2 && env <= 4) return env;
-  return nb >= 4 ? 2 : 3;
-}
+// built-in LDS ring depth of the 4-wave float32 kernels
+static int ring_depth(int nb) { return nb >= 4 ? 2 : 3; }
 
 static int dma_stage_bytes(int nb) { return 16384 + nb * 4096; }
 
@@ -449,37 +442,50 @@ static bool dma_ok(const float* A, int64_t lda, int64_t n) {
   return !env && (lda % 4) == 0 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (n % 4) == 0;
 }
 
-// waves per workgroup of the Y = A X kernel: 8 (one workgroup per CU, a
-// four-stage ring) for nb = 2 on tall A, else 4; RPCA_AX_WAVES=4 overrides
-static int ax_waves(int nb, int64_t m, int num_cus) {
-  static int env = -1;
-  if (env < 0) {
-    const char* e = getenv("RPCA_AX_WAVES");
-    env = e ? atoi(e) : 0;
-  }
-  if (env == 4) return 4;
-  return (nb == 2 && m >= (int64_t)num_cus * 256) ? 8 : 4;
+bool dma_ok_shape(const void* A, int64_t lda, int64_t n) {
+  return dma_ok(static_cast<const float*>(A), lda, n);
+}
+
+// (waves, ring stages) of the float32 Y = A X kernel: the configuration when
+// the kernel has it, else the built-in choice: 8 waves with a four-stage ring
+// (one workgroup per CU) for nb = 2 on tall A, 4 waves otherwise.
+struct PassChoice {
+  int nw, S;
+};
+static PassChoice ax_choice(int nb, int64_t m, int num_cus, const TuneCfg* cfg) {
+  PassChoice c{(nb == 2 && m >= (int64_t)num_cus * 256) ? 8 : 4, 0};
+  if (cfg && cfg->ax_waves == 8 && nb == 2) c.nw = 8;
+  if (cfg && cfg->ax_waves == 4) c.nw = 4;
+  c.S = c.nw == 8 ? 4 : ((cfg && cfg->ax_ring >= 2 && cfg->ax_ring <= 4) ? cfg->ax_ring : ring_depth(nb));
+  return c;
+}
+
+int ax_candidates(int nb, int (*out)[2]) {
+  int k = 0;
+  if (nb == 2) { out[k][0] = 8; out[k][1] = 4; ++k; }
+  for (int S = 2; S <= 4; ++S) { out[k][0] = 4; out[k][1] = S; ++k; }
+  return k;
 }
 
 template <int NB>
 static void launch_ax_dma(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n,
-                          const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
-  const int nw = ax_waves(NB, m, num_cus);
-  const int S = nw == 8 ? 4 : ring_depth(NB);
-  const int stage = 32 * nw * 128 + NB * 4096;
-  const int per_cu = std::max(1, (160 * 1024) / (S * stage));
+                          const __bf16* Xp, float* Y, int64_t ldy, int num_cus,
+                          const TuneCfg* cfg) {
+  const PassChoice c = ax_choice(NB, m, num_cus, cfg);
+  const int stage = 32 * c.nw * 128 + NB * 4096;
+  const int per_cu = std::max(1, (160 * 1024) / (c.S * stage));
   int64_t G = (int64_t)num_cus * per_cu;
   G = std::min<int64_t>(G, ceil_div(m, 32));
   const int64_t rows_per = ceil_div(m, G);
   G = ceil_div(m, rows_per);
   const dim3 grid((unsigned)G);
   if constexpr (NB == 2) {
-    if (nw == 8) {
+    if (c.nw == 8) {
       hipLaunchKernelGGL((ax_dma_kernel<2, 4, 8>), grid, dim3(512), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per);
       return;
     }
   }
-  switch (S) {
+  switch (c.S) {
     case 2: hipLaunchKernelGGL((ax_dma_kernel<NB, 2, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
     case 4: hipLaunchKernelGGL((ax_dma_kernel<NB, 4, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
     default: hipLaunchKernelGGL((ax_dma_kernel<NB, 3, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per); break;
@@ -487,14 +493,15 @@ static void launch_ax_dma(hipStream_t st, const float* A, int64_t lda, int64_t m
 }
 
 void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
-               const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus) {
+               const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus,
+               const TuneCfg* cfg) {
   (void)dtype;
   const float* Af = static_cast<const float*>(A);
   if (dma_ok(Af, lda, n)) {
     switch (nb) {
-      case 1: launch_ax_dma<1>(st, Af, lda, m, n, Xp, Y, ldy, num_cus); return;
-      case 2: launch_ax_dma<2>(st, Af, lda, m, n, Xp, Y, ldy, num_cus); return;
-      case 4: launch_ax_dma<4>(st, Af, lda, m, n, Xp, Y, ldy, num_cus); return;
+      case 1: launch_ax_dma<1>(st, Af, lda, m, n, Xp, Y, ldy, num_cus, cfg); return;
+      case 2: launch_ax_dma<2>(st, Af, lda, m, n, Xp, Y, ldy, num_cus, cfg); return;
+      case 4: launch_ax_dma<4>(st, Af, lda, m, n, Xp, Y, ldy, num_cus, cfg); return;
       default: return;
     }
   }
@@ -606,30 +613,30 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
     for (int r = 0; r < 16; ++r) out[(cb * 16 + r) * 64 + lane] = acc[cb][r];
 }
 
-// waves per workgroup of the float32 A^T X DMA kernel: 8 (256-column tiles,
-// one workgroup per CU, a four-stage ring) for nb = 2 on wide, tall A, else 4;
-// RPCA_ATX_WAVES=4 overrides
-static int atx_waves(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
-  static int env = -1;
-  if (env < 0) {
-    const char* e = getenv("RPCA_ATX_WAVES");
-    env = e ? atoi(e) : 0;
-  }
-  if (env == 4) return 4;
-  return (dtype == 0 && nb == 2 && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4;
+// (waves, ring stages) of the float32 A^T X DMA kernel, as for Y = A X: 8
+// waves (256-column tiles, one workgroup per CU, a four-stage ring) for nb = 2
+// on wide, tall A, else 4; the low-precision kernels have one configuration.
+static PassChoice atx_choice(int64_t m, int64_t n, int nb, int num_cus, int dtype,
+                             const TuneCfg* cfg) {
+  if (dtype != 0) return PassChoice{4, 0};
+  PassChoice c{(nb == 2 && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4, 0};
+  if (cfg && cfg->atx_waves == 8 && nb == 2) c.nw = 8;
+  if (cfg && cfg->atx_waves == 4) c.nw = 4;
+  c.S = c.nw == 8 ? 4 : ((cfg && cfg->atx_ring >= 2 && cfg->atx_ring <= 4) ? cfg->atx_ring : ring_depth(nb));
+  return c;
 }
 
-AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
+AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype, const TuneCfg* cfg) {
   AtxPlan p;
+  const PassChoice c = atx_choice(m, n, nb, num_cus, dtype, cfg);
   p.ntiles = (int)ceil_div(n, 128);
-  p.waves = atx_waves(m, n, nb, num_cus, dtype);
+  p.waves = c.nw;
+  p.ring = c.S;
   p.gtiles = (int)ceil_div(n, 32 * p.waves);
   const int rs = dtype == 0 ? 32 : lp_rows_per_stage(dtype);  // rows per stage
   const int64_t stages = ceil_div(m, rs);
   // workgroups resident per CU for the LDS ring of the DMA kernel
-  const int per_cu = dtype == 0 ? (p.waves == 8 ? 1
-                                                : std::max(1, (160 * 1024) / (ring_depth(nb) *
-                                                                              dma_stage_bytes(nb))))
+  const int per_cu = dtype == 0 ? (p.waves == 8 ? 1 : std::max(1, (160 * 1024) / (p.ring * dma_stage_bytes(nb))))
                                 : lp_per_cu(nb, dtype);
   int64_t want = (int64_t)per_cu * num_cus / p.gtiles;
   if (want < 1) want = 1;
@@ -643,13 +650,27 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
   return p;
 }
 
+size_t atx_partial_bytes_max(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
+  size_t b = plan_atx(m, n, nb, num_cus, dtype, nullptr).partial_bytes;
+  if (dtype != 0) return b;
+  int cand[8][2];
+  const int k = ax_candidates(nb, cand);
+  for (int i = 0; i < k; ++i) {
+    TuneCfg c;
+    c.atx_waves = cand[i][0];
+    c.atx_ring = cand[i][1];
+    b = std::max(b, plan_atx(m, n, nb, num_cus, dtype, &c).partial_bytes);
+  }
+  return b;
+}
+
 void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                 const __bf16* Xp, float* P, const AtxPlan& plan, int nb) {
   (void)dtype;
   const float* Af = static_cast<const float*>(A);
   const dim3 grid((unsigned)(plan.ntiles * plan.nsplit));
   if (dma_ok(Af, lda, n)) {
-    const int S = ring_depth(nb);
+    const int S = plan.ring;
     if (plan.waves == 8 && nb == 2) {
       hipLaunchKernelGGL((atx_dma_kernel<2, 4, 8>), dim3((unsigned)(plan.gtiles * plan.nsplit)),
                          dim3(512), 0, st, Af, lda, m, n, Xp, P, plan.gtiles, plan.ntiles,

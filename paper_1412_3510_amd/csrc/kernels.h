@@ -19,21 +19,43 @@ size_t packed_bytes(int64_t nsteps, int nb);
 void launch_pack(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int cols, int nb,
                  const float* mu, const float* rscale, __bf16* out, int64_t nsteps);
 
+// Tile configuration of the float32 A-pass kernels and of the LU tournament
+// (0: the built-in choice).  The autotuner (rpca_tune) picks it per shape
+// class; the launchers fall back to the built-in choice for values they do
+// not support.
+struct TuneCfg {
+  int ax_waves = 0;   // waves per workgroup of Y = A X: 4 or 8 (8: lp = 64 only)
+  int ax_ring = 0;    // LDS ring stages of the 4-wave form: 2, 3 or 4
+  int atx_waves = 0;  // the same for A^T X
+  int atx_ring = 0;
+  int lu_rows = 0;    // rows per tournament block: 256, 512 or 1024 (lp <= 64)
+};
+
 // Y (m x 32*nb) = A (m x n) X, X packed with >= 2*ceil(n/32) steps.
 void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
-               const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus);
+               const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus,
+               const TuneCfg* cfg = nullptr);
+// the (waves, ring) pairs launch_ax can run for nb (the autotuner's candidates)
+int ax_candidates(int nb, int (*out)[2]);
+// whether float32 A in this layout takes the LDS-DMA kernels (which have the
+// configurations above)
+bool dma_ok_shape(const void* A, int64_t lda, int64_t n);
 
 // Split-K partial products of A^T X (X packed on the m side).
 struct AtxPlan {
   int ntiles;        // ceil(n / 128): the partials hold 4 * ntiles 32-column blocks per split
   int waves;         // waves per workgroup of the float32 DMA kernel (4 or 8)
+  int ring;          // its LDS ring stages
   int gtiles;        // column tiles of that kernel, ceil(n / (32 * waves))
   int nsplit;        // number of row splits
   int64_t rows_per;  // rows per split (multiple of 32)
   size_t partial_bytes;
 };
 // dtype: 0 float32, 1 bfloat16, 2 E4M3 (the copy of A the pass reads)
-AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype);
+AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype,
+                 const TuneCfg* cfg = nullptr);
+// largest partial buffer over every configuration plan_atx can choose
+size_t atx_partial_bytes_max(int64_t m, int64_t n, int nb, int num_cus, int dtype);
 void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                 const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
 // Z (n x 32*nb) = sum of the partials (fixed order); ``cscale`` (nullable,
@@ -104,13 +126,15 @@ void launch_sign_fix(hipStream_t st, float* U, int64_t ldu, int64_t m, int k, fl
 // ---- pivoted LU by tournament (lu.hip) ---------------------------------------
 struct LuPlan {
   int lp;
+  int rows;            // rows per tournament block
   int levels;
   int nblk[16];        // blocks at each level (level 0 = leaves)
   int64_t cand_off[16];
   int64_t cand_total;  // ints
   int64_t counter_total;
 };
-LuPlan plan_lu(int64_t rows, int lp);
+// block_rows: 256, 512 or 1024 (lp <= 64); anything else takes 512
+LuPlan plan_lu(int64_t rows, int lp, int block_rows = 0);
 // Tournament pivoting over rows of X; writes the root's U (lp x lp float32,
 // row-major), the pivot rows piv[l] and zero-pivot markers (U[j][j] == 0).
 void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,

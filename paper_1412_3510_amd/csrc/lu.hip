@@ -357,23 +357,20 @@ __global__ void __launch_bounds__(NT) lu_tree_kernel(const float* __restrict__ X
   }
 }
 
-// rows per block (512 threads each); RPCA_LU_ROWS overrides for tuning
-static int lu_block_rows(int lp) {
-  static int env = -1;
-  if (env < 0) {
-    const char* e = getenv("RPCA_LU_ROWS");
-    env = e ? atoi(e) : 0;
-  }
-  int nt = 512;
-  if (env == 256 || env == 512 || (env == 1024 && lp <= 64)) nt = env;
-  if (nt < 2 * lp) nt = 2 * lp;
-  return nt;
+// rows per block (512 threads each): the requested count when the kernel
+// has that instantiation, else 512; at least 2 lp
+static int lu_block_rows(int lp, int want) {
+  int r = 512;
+  if (want == 256 || want == 512 || (want == 1024 && lp <= 64)) r = want;
+  if (r < 2 * lp) r = 2 * lp;
+  return r;
 }
 
-LuPlan plan_lu(int64_t rows, int lp) {
+LuPlan plan_lu(int64_t rows, int lp, int block_rows) {
   LuPlan p{};
   p.lp = lp;
-  const int NT = lu_block_rows(lp);
+  const int NT = lu_block_rows(lp, block_rows);
+  p.rows = NT;
   const int F = NT / lp;
   int nb = (int)ceil_div(rows, NT);
   int64_t coff = 0, koff = 0;
@@ -406,7 +403,7 @@ void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, i
     if (i >= 1) acc += plan.nblk[i];
   }
   const dim3 grid((unsigned)plan.nblk[0]);
-  const int r = lu_block_rows(plan.lp);
+  const int r = plan.rows;
 #define LU_LAUNCH(LP_, R_)                                                                    \
   hipLaunchKernelGGL((lu_tree_kernel<LP_, R_, 512>), grid, dim3(512), 0, st, X, ldx, rows, l, \
                      lv, cand, counters, U, piv)

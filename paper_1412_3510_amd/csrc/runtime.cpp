@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -53,6 +55,8 @@ struct rpca_ctx_s {
   int* host_state = nullptr;  // pinned
   std::vector<BatchSlot> slots;
   hipEvent_t fork = nullptr;
+  // autotuned configurations by shape class (ceil log2 m, ceil log2 n, lp, dtype)
+  std::map<std::array<int, 4>, TuneCfg> tune;
 };
 
 namespace {
@@ -164,6 +168,8 @@ struct Work {
   int* signwork = nullptr;
   double* scal = nullptr;  // [0] fro2, [1] nu
   float* nu_f = nullptr;
+  TuneCfg cfg{};     // tile configuration of this shape class
+  int64_t lu_ctr = 0;  // LU arrival counters the largest tournament plan needs
   AtxPlan atx{};     // plan for the copy of A the range finder reads
   AtxPlan atx_rr{};  // plan for the float32 copy of the Rayleigh-Ritz pass
   LuPlan lu_m{}, lu_n{};
@@ -196,8 +202,11 @@ int elem_bytes(int dtype) { return dtype == RPCA_F32 ? 4 : (dtype == RPCA_BF16 ?
 // stages of every pass kernel (8 steps = 128 rows)
 int64_t pack_steps(int64_t rows) { return round_up(ceil_div(rows, 16), 8); }
 
+// Buffer sizes do not depend on the tile configuration: the partials and the
+// tournament buffers are sized for every configuration the autotuner tries.
 void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool need_y2,
-            int dtype) {
+            int dtype, const TuneCfg* cfg = nullptr) {
+  w.cfg = cfg ? *cfg : TuneCfg{};
   w.l = l;
   w.lp = lp_of(l);
   w.nb = w.lp / 32;
@@ -210,9 +219,11 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.Bk = ar.take<float>((size_t)round_up(rmax, 32) * lp);
   if (dtype >= 0) {  // dense A: packed operand and split partials of A^T X
     w.Xp = ar.take<__bf16>(packed_bytes(pack_steps(rmax), w.nb) / sizeof(__bf16));
-    w.atx = plan_atx(m, n, w.nb, num_cus, dtype);
-    w.atx_rr = plan_atx(m, n, w.nb, num_cus, RPCA_F32);
-    w.P = ar.take<float>(std::max(w.atx.partial_bytes, w.atx_rr.partial_bytes) / sizeof(float));
+    w.atx = plan_atx(m, n, w.nb, num_cus, dtype, &w.cfg);
+    w.atx_rr = plan_atx(m, n, w.nb, num_cus, RPCA_F32, &w.cfg);
+    w.P = ar.take<float>(std::max(atx_partial_bytes_max(m, n, w.nb, num_cus, dtype),
+                                  atx_partial_bytes_max(m, n, w.nb, num_cus, RPCA_F32)) /
+                         sizeof(float));
   }
   w.mu = ar.take<float>(128);
   w.colpart = ar.take<double>((size_t)colmean_blocks(rmax) * 128);
@@ -220,9 +231,16 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.gpart = ar.take<double>((size_t)gram_blocks(rmax) * lp * lp);
   w.G = ar.take<double>((size_t)lp * lp);
   w.Rf = ar.take<float>((size_t)lp * lp);
-  w.lu_m = plan_lu(m, lp);
-  w.lu_n = plan_lu(n, lp);
-  w.cand = ar.take<int>((size_t)std::max(w.lu_m.cand_total, w.lu_n.cand_total));
+  w.lu_m = plan_lu(m, lp, w.cfg.lu_rows);
+  w.lu_n = plan_lu(n, lp, w.cfg.lu_rows);
+  int64_t cand = 0;
+  w.lu_ctr = 0;
+  for (int r : {256, 512, 1024}) {
+    const LuPlan a = plan_lu(m, lp, r), b = plan_lu(n, lp, r);
+    cand = std::max({cand, a.cand_total, b.cand_total});
+    w.lu_ctr = std::max({w.lu_ctr, a.counter_total, b.counter_total});
+  }
+  w.cand = ar.take<int>((size_t)cand);
   w.piv = ar.take<int>(128);
   w.Ulu = ar.take<float>((size_t)lp * lp);
   w.state = ar.take<int>(16);
@@ -235,17 +253,33 @@ void layout(Arena& ar, Work& w, int64_t m, int64_t n, int l, int num_cus, bool n
   w.nu_f = ar.take<float>(4);
 }
 
+int ceil_log2(int64_t v) {
+  int b = 0;
+  while (((int64_t)1 << b) < v) ++b;
+  return b;
+}
+
+std::array<int, 4> tune_key(int64_t m, int64_t n, int lp, int dtype) {
+  return {ceil_log2(m), ceil_log2(n), lp, dtype};
+}
+
+const TuneCfg* tune_lookup(rpca_ctx ctx, int64_t m, int64_t n, int l, int dtype) {
+  auto it = ctx->tune.find(tune_key(m, n, lp_of(l), dtype));
+  return it == ctx->tune.end() ? nullptr : &it->second;
+}
+
 rpca_status prepare(rpca_ctx ctx, Work& w, int64_t m, int64_t n, int l, bool need_y2,
-                    int dtype = RPCA_F32) {
+                    int dtype = RPCA_F32, const TuneCfg* force = nullptr) {
+  const TuneCfg* cfg = force ? force : tune_lookup(ctx, m, n, l, dtype);
   Arena probe;
-  layout(probe, w, m, n, l, ctx->num_cus, need_y2, dtype);
+  layout(probe, w, m, n, l, ctx->num_cus, need_y2, dtype, cfg);
   rpca_status s = ensure_ws(ctx, probe.off + 256);
   if (s != RPCA_OK) return s;
-  s = ensure_counters(ctx, (size_t)std::max(w.lu_m.counter_total, w.lu_n.counter_total) + 16);
+  s = ensure_counters(ctx, (size_t)w.lu_ctr + 16);
   if (s != RPCA_OK) return s;
   Arena real;
   real.base = ctx->ws;
-  layout(real, w, m, n, l, ctx->num_cus, need_y2, dtype);
+  layout(real, w, m, n, l, ctx->num_cus, need_y2, dtype, cfg);
   return RPCA_OK;
 }
 
@@ -317,7 +351,8 @@ void run_ax(rpca_ctx ctx, const AView& A, const Work& w, const __bf16* Xp, float
                        (double)A.m * w.lp * 4.0;
   begin_timed(ctx, t, A.dtype == RPCA_F32 ? 0 : 2, bytes);
   if (A.dtype == RPCA_F32)
-    launch_ax(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus);
+    launch_ax(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus,
+              &w.cfg);
   else
     launch_ax_lp(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus);
   end_timed(ctx, t);
@@ -341,7 +376,7 @@ void run_atx(rpca_ctx ctx, const AView& A, const Work& w, const __bf16* Qp) {
 
 // Y (rows x lp) <- P L with Y = P L U (tournament-pivoted LU), in place.
 void lu_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
-  const LuPlan plan = plan_lu(rows, w.lp);
+  const LuPlan plan = plan_lu(rows, w.lp, w.cfg.lu_rows);
   launch_lu_tree(ctx->stream, Y, w.lp, rows, w.l, plan, w.cand, ctx->counters, w.Ulu, w.piv);
   launch_trsm(ctx->stream, Y, w.lp, rows, w.l, w.lp, w.Ulu, w.piv, nullptr, nullptr, nullptr, 0);
 }
@@ -889,7 +924,7 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     Arena probe;
     layout(probe, w, q.A->m, q.A->n, l, ctx->num_cus, q.kind == 1, layout_kind(q.A));
     ws_need[p] = probe.off + 256;
-    ctr_need[p] = (size_t)std::max(w.lu_m.counter_total, w.lu_n.counter_total) + 16;
+    ctr_need[p] = (size_t)w.lu_ctr + 16;
     cost[p] = (double)q.A->m * q.A->n * (2.0 * q.its + 2.0) + 1e6;
   }
   const int ns = std::min(kSlots, count);
@@ -988,6 +1023,181 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
   }
   if (res != RPCA_OK) return res;
   if (flags & RPCA_SYNC) HIP_OK(hipStreamSynchronize(ctx->stream));
+  return RPCA_OK;
+}
+
+rpca_status rpca_tune(rpca_ctx ctx, const rpca_matrix* A, int32_t l, int32_t reps,
+                      rpca_tune_result* out) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  if (is_sparse(A)) return fail(ctx, RPCA_ERR_UNSUPPORTED, "tune: dense A only");
+  s = check_kl(ctx, 1, l, A->m, A->n);
+  if (s != RPCA_OK) return s;
+  if (reps < 1) reps = 3;
+  const int64_t m = A->m, n = A->n;
+  const AView Av = native_view(A);
+  const bool f32 = Av.dtype == RPCA_F32;
+  Work w;
+  const TuneCfg base{};
+  s = prepare(ctx, w, m, n, l, false, Av.dtype, &base);
+  if (s != RPCA_OK) return s;
+  hipStream_t st = ctx->stream;
+  hipEvent_t ea = take_event(ctx), eb = take_event(ctx);
+  if (!ea || !eb) return fail(ctx, RPCA_ERR_HIP, "tune: no events");
+  // average device time of one launch sequence over reps runs after a warm-up
+  auto timed = [&](auto&& run, double* ms) -> rpca_status {
+    run();
+    HIP_OK(hipEventRecord(ea, st));
+    for (int r = 0; r < reps; ++r) run();
+    HIP_OK(hipEventRecord(eb, st));
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventSynchronize(eb));
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, ea, eb));
+    *ms = (double)t / reps;
+    return RPCA_OK;
+  };
+  rpca_tune_result res{};
+  TuneCfg best{};
+  // operands: a Gaussian X (n x l), Y = A X, Q = Y for A^T Q, Z = A^T Q
+  launch_fill_zero(st, w.Z, n * w.lp);
+  launch_gaussian(st, 0x7475ull, 0u, n, l, w.Z, w.lp, nullptr);
+  pack_n_side(ctx, w, w.Z, n, Av);
+  int cand[8][2];
+  const int nc = ax_candidates(w.nb, cand);
+  if (f32 && dma_ok_shape(Av.data, Av.ld, n)) {
+    double bms = 1e30;
+    for (int i = 0; i < nc; ++i) {
+      TuneCfg c{};
+      c.ax_waves = cand[i][0];
+      c.ax_ring = cand[i][1];
+      double ms = 0;
+      s = timed([&] { launch_ax(st, Av.data, Av.dtype, Av.ld, m, n, w.Xp, w.Y, w.lp, w.nb,
+                                ctx->num_cus, &c); }, &ms);
+      if (s != RPCA_OK) break;
+      ++res.candidates;
+      if (ms < bms) { bms = ms; best.ax_waves = c.ax_waves; best.ax_ring = c.ax_ring; }
+    }
+    res.ms_ax = bms;
+  }
+  if (s == RPCA_OK) {
+    // Y = A X with the chosen configuration (the tournament's input)
+    w.cfg = best;
+    run_ax(ctx, Av, w, w.Xp, w.Y);
+    pack_m_side(ctx, w, w.Y, m, false);
+  }
+  if (s == RPCA_OK && f32 && dma_ok_shape(Av.data, Av.ld, n)) {
+    double bms = 1e30;
+    for (int i = 0; i < nc && s == RPCA_OK; ++i) {
+      TuneCfg c{};
+      c.atx_waves = cand[i][0];
+      c.atx_ring = cand[i][1];
+      const AtxPlan plan = plan_atx(m, n, w.nb, ctx->num_cus, RPCA_F32, &c);
+      double ms = 0;
+      s = timed([&] {
+        launch_atx(st, Av.data, Av.dtype, Av.ld, m, n, w.Xp, w.P, plan, w.nb);
+        launch_atx_reduce(st, w.P, plan, w.nb, n, nullptr, w.Z, w.lp);
+      }, &ms);
+      ++res.candidates;
+      if (ms < bms) { bms = ms; best.atx_waves = c.atx_waves; best.atx_ring = c.atx_ring; }
+    }
+    res.ms_atx = bms;
+  } else if (s == RPCA_OK) {
+    apply_at(ctx, Av, w, w.Z);
+  }
+  if (s == RPCA_OK) {
+    // the tournament on both sides, for each block height
+    double bms = 1e30;
+    for (int r : {256, 512, 1024}) {
+      if (r == 1024 && w.lp > 64) continue;
+      const LuPlan pm = plan_lu(m, w.lp, r), pn = plan_lu(n, w.lp, r);
+      double ms = 0;
+      s = timed([&] {
+        launch_lu_tree(st, w.Y, w.lp, m, w.l, pm, w.cand, ctx->counters, w.Ulu, w.piv);
+        launch_lu_tree(st, w.Z, w.lp, n, w.l, pn, w.cand, ctx->counters, w.Ulu, w.piv);
+      }, &ms);
+      if (s != RPCA_OK) break;
+      ++res.candidates;
+      if (ms < bms) { bms = ms; best.lu_rows = r; }
+    }
+    res.ms_lu = bms;
+  }
+  ctx->event_pool.push_back(ea);
+  ctx->event_pool.push_back(eb);
+  if (s != RPCA_OK) return s;
+  ctx->tune[tune_key(m, n, w.lp, Av.dtype)] = best;
+  res.ax_waves = best.ax_waves;
+  res.ax_ring = best.ax_ring;
+  res.atx_waves = best.atx_waves;
+  res.atx_ring = best.atx_ring;
+  res.lu_rows = best.lu_rows;
+  if (out) *out = res;
+  return RPCA_OK;
+}
+
+rpca_status rpca_tune_save(rpca_ctx ctx, const char* path) {
+  if (!ctx || !path) return RPCA_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(ctx, RPCA_ERR_INVALID_ARG, std::string("tune: cannot write ") + path);
+  std::fprintf(f, "# log2m log2n lp dtype ax_waves ax_ring atx_waves atx_ring lu_rows\n");
+  for (const auto& kv : ctx->tune) {
+    const TuneCfg& c = kv.second;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d\n", kv.first[0], kv.first[1], kv.first[2],
+                 kv.first[3], c.ax_waves, c.ax_ring, c.atx_waves, c.atx_ring, c.lu_rows);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok ? RPCA_OK : fail(ctx, RPCA_ERR_INVALID_ARG, std::string("tune: write failed: ") + path);
+}
+
+rpca_status rpca_tune_load(rpca_ctx ctx, const char* path) {
+  if (!ctx || !path) return RPCA_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(ctx, RPCA_ERR_INVALID_ARG, std::string("tune: cannot read ") + path);
+  std::map<std::array<int, 4>, TuneCfg> add;
+  char line[512];
+  int lineno = 0;
+  bool bad = false;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    const char* p = line;
+    while (*p == ' ' || *p == '\t') ++p;
+    if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0) continue;
+    int v[9];
+    char tail[8];
+    const int got = std::sscanf(p, "%d %d %d %d %d %d %d %d %d %7s", &v[0], &v[1], &v[2], &v[3],
+                                &v[4], &v[5], &v[6], &v[7], &v[8], tail);
+    const bool lp_ok = v[2] == 32 || v[2] == 64 || v[2] == 128;
+    if (got != 9 || !lp_ok || v[0] < 0 || v[0] > 62 || v[1] < 0 || v[1] > 62 || v[3] < 0 ||
+        v[3] > 2 || v[4] < 0 || v[5] < 0 || v[6] < 0 || v[7] < 0 || v[8] < 0) {
+      bad = true;
+      break;
+    }
+    TuneCfg c;
+    c.ax_waves = v[4];
+    c.ax_ring = v[5];
+    c.atx_waves = v[6];
+    c.atx_ring = v[7];
+    c.lu_rows = v[8];
+    add[{v[0], v[1], v[2], v[3]}] = c;
+  }
+  std::fclose(f);
+  if (bad)
+    return fail(ctx, RPCA_ERR_INVALID_ARG,
+                std::string("tune: malformed line ") + std::to_string(lineno) + " of " + path);
+  for (const auto& kv : add) ctx->tune[kv.first] = kv.second;
+  return RPCA_OK;
+}
+
+rpca_status rpca_tune_clear(rpca_ctx ctx) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  ctx->tune.clear();
+  return RPCA_OK;
+}
+
+rpca_status rpca_tune_count(rpca_ctx ctx, int32_t* count) {
+  if (!ctx || !count) return RPCA_ERR_INVALID_ARG;
+  *count = (int32_t)ctx->tune.size();
   return RPCA_OK;
 }
 

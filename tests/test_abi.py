@@ -26,6 +26,7 @@ def test_status_strings_and_struct_layout():
     assert ctypes.sizeof(rp.Matrix) == 8 + 14 * 8
     assert ctypes.sizeof(rp.Stats) == 16 * 8
     assert ctypes.sizeof(rp.Problem) == 80
+    assert ctypes.sizeof(rp.TuneResult) == 6 * 4 + 3 * 8
 
 
 def test_null_context_rejected():
