@@ -214,7 +214,10 @@ __global__ void __launch_bounds__(256) ax_f32_kernel(const float* __restrict__ A
 // rows 8b..8b+7 per 1 KB DMA block b; the 16-byte chunk c of row R sits at
 // position c ^ ((R >> 1) & 7)) plus the matching 4 NB packed X fragments, XW
 // per wave.  With NW = 8 one workgroup holds a CU's whole LDS, so a deeper
-// ring keeps more bytes of A in flight per CU.
+// ring keeps more bytes of A in flight per CU.  Each wave loads (and reads)
+// only its own 32 rows of A, so in a short last tile a wave whose rows are
+// all past the end issues only its X fragments (and waits for those alone)
+// and skips its products: the tile then costs what its rows cost.
 template <int NB, int S, int NW>
 __global__ void __launch_bounds__(64 * NW) ax_dma_kernel(const float* __restrict__ A,
                                                          int64_t lda, int64_t m, int64_t n,
@@ -250,13 +253,16 @@ __global__ void __launch_bounds__(64 * NW) ax_dma_kernel(const float* __restrict
       rowp[i] = A + grow * lda;
       cofs[i] = 4 * ((lane & 7) ^ ((R >> 1) & 7));
     }
+    const bool live = row0 + 32 * wave < rend;  // this wave has rows in the tile
 #define AX_ISSUE(STG)                                                                     \
   do {                                                                                    \
     const int64_t stg_ = (STG);                                                           \
     char* slot_ = ring + (int)(stg_ % S) * STAGE;                                         \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
-      const int64_t col_ = stg_ * KC + cofs[i];                                           \
-      dma16(rowp[i] + (col_ < n ? col_ : 0), slot_ + (4 * wave + i) * 1024);              \
+    if (live) {                                                                           \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                     \
+        const int64_t col_ = stg_ * KC + cofs[i];                                         \
+        dma16(rowp[i] + (col_ < n ? col_ : 0), slot_ + (4 * wave + i) * 1024);            \
+      }                                                                                   \
     }                                                                                     \
     _Pragma("unroll") for (int i = 0; i < XW; ++i) {                                      \
       const int blk_ = wave + NW * i;                                                     \
@@ -278,29 +284,34 @@ __global__ void __launch_bounds__(64 * NW) ax_dma_kernel(const float* __restrict
     for (int64_t stg = 0; stg < nstage; ++stg) {
       if (stg + S - 1 < nstage) AX_ISSUE(stg + S - 1);
       const int64_t last = min(nstage - 1, stg + S - 1);
-      wait_ahead<PER, S>((int)(last - stg));
+      // (both waits end in the workgroup barrier; a wave without rows
+      // still takes every barrier of the stage)
+      if (live) wait_ahead<PER, S>((int)(last - stg));
+      else wait_ahead<XW, S>((int)(last - stg));
       const char* As = ring + (int)(stg % S) * STAGE;
       const char* Xs = As + ABYTES;
+      if (live) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int c0 = 4 * s + 2 * g;
-        const float4 a0 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * (c0 ^ sw));
-        const float4 a1 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * ((c0 + 1) ^ sw));
-        bf16x8 ah, al;
-        __bf16 th, tl;
-        split_bf16(a0.x, th, tl); ah[0] = th; al[0] = tl;
-        split_bf16(a0.y, th, tl); ah[1] = th; al[1] = tl;
-        split_bf16(a0.z, th, tl); ah[2] = th; al[2] = tl;
-        split_bf16(a0.w, th, tl); ah[3] = th; al[3] = tl;
-        split_bf16(a1.x, th, tl); ah[4] = th; al[4] = tl;
-        split_bf16(a1.y, th, tl); ah[5] = th; al[5] = tl;
-        split_bf16(a1.z, th, tl); ah[6] = th; al[6] = tl;
-        split_bf16(a1.w, th, tl); ah[7] = th; al[7] = tl;
+        for (int s = 0; s < 2; ++s) {
+          const int c0 = 4 * s + 2 * g;
+          const float4 a0 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * (c0 ^ sw));
+          const float4 a1 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * ((c0 + 1) ^ sw));
+          bf16x8 ah, al;
+          __bf16 th, tl;
+          split_bf16(a0.x, th, tl); ah[0] = th; al[0] = tl;
+          split_bf16(a0.y, th, tl); ah[1] = th; al[1] = tl;
+          split_bf16(a0.z, th, tl); ah[2] = th; al[2] = tl;
+          split_bf16(a0.w, th, tl); ah[3] = th; al[3] = tl;
+          split_bf16(a1.x, th, tl); ah[4] = th; al[4] = tl;
+          split_bf16(a1.y, th, tl); ah[5] = th; al[5] = tl;
+          split_bf16(a1.z, th, tl); ah[6] = th; al[6] = tl;
+          split_bf16(a1.w, th, tl); ah[7] = th; al[7] = tl;
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) {
-          const bf16x8 xh = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
-          const bf16x8 xl = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
-          acc[cb] = mfma3(ah, al, xh, xl, acc[cb]);
+          for (int cb = 0; cb < NB; ++cb) {
+            const bf16x8 xh = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
+            const bf16x8 xl = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
+            acc[cb] = mfma3(ah, al, xh, xl, acc[cb]);
+          }
         }
       }
       barrier_mem();
