@@ -144,13 +144,33 @@ typedef struct {
 } rpca_problem;
 
 /* Many independent solves in one call.  Every problem is checked before
- * anything is launched.  The problems run concurrently on up to eight
- * internal HIP streams (default priority) forked from and joined back into
- * the context stream, so the call is ordered on that stream like a single
- * solve and can be captured into a HIP graph there once an uncaptured call
- * of the same batch has sized the per-stream workspaces (a capture that would
- * need new workspace returns RPCA_ERR_UNSUPPORTED).  Each stream has its own
- * workspace and pivot counters.  Unlike rpca_eig_psd, a PSD problem whose
+ * anything is launched.
+ *
+ * Problems with a dense float32 A, m, n <= 8192 and l <= 64 are solved by one
+ * persistent launch on the context stream: each workgroup of 512 threads
+ * solves a whole problem (Sections 2, 3 and 5 with the same steps as the
+ * single calls) and then takes the next one from a device counter, largest
+ * problems first.  Its results equal the single calls' up to rounding (the
+ * renormalizations pick other, equivalent bases).  Each call writes its
+ * problem table to device memory on the stream (kernel arguments carry it, so
+ * a captured graph replays its own table); the table, the work counter and
+ * the working memory (one slot per workgroup, sized by the largest m or n)
+ * belong to the context and are sized by uncaptured calls, which only grow
+ * them (memory a larger buffer replaces is kept until rpca_destroy, for the
+ * graphs that use it).  Calls that overlap on several streams share these
+ * buffers and must not run at the same time.
+ *
+ * The other problems (sparse, bfloat16/E4M3 storage, larger sizes), and every
+ * problem after rpca_set_batch_mode(ctx, 1), run the single-problem kernels
+ * concurrently on up to rpca_set_batch_streams internal HIP streams (default
+ * priority) forked from and joined back into the context stream; the results
+ * then equal the single calls' bit for bit.  Each stream has its own
+ * workspace and pivot counters.
+ *
+ * The call is ordered on the context stream like a single solve and can be
+ * captured into a HIP graph there once an uncaptured call of the same batch
+ * has sized the tables and workspaces (a capture that would need new ones
+ * returns RPCA_ERR_UNSUPPORTED).  Unlike rpca_eig_psd, a PSD problem whose
  * shifted Cholesky factor never exists is not reported (nothing is read back
  * from the device); its eigenvalues are then not meaningful. */
 rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* problems,
@@ -232,6 +252,15 @@ rpca_status rpca_set_timing(rpca_ctx ctx, int enable);
 /* Synchronizes the stream, folds the recorded events into the totals. */
 rpca_status rpca_get_stats(rpca_ctx ctx, rpca_stats* out);
 rpca_status rpca_reset_stats(rpca_ctx ctx);
+
+/* Batched mode: 0 (default) solves the problems the persistent launch takes
+ * there and the others on streams; 1 runs every problem on streams. */
+rpca_status rpca_set_batch_mode(rpca_ctx ctx, int32_t mode);
+
+/* Number of HIP streams rpca_svd_batched spreads a batch over (1..64,
+ * default 8; each has its own workspace).  How many of them run at once is
+ * bounded by the hardware queues HIP gives the process (GPU_MAX_HW_QUEUES). */
+rpca_status rpca_set_batch_streams(rpca_ctx ctx, int32_t streams);
 
 /* ---- autotuner -----------------------------------------------------------
  * The float32 A-pass kernels and the LU pivot tournament have tile

@@ -143,6 +143,8 @@ _SIGS = {
     "rpca_set_timing": [P, I32],
     "rpca_get_stats": [P, ctypes.POINTER(Stats)],
     "rpca_reset_stats": [P],
+    "rpca_set_batch_streams": [P, I32],
+    "rpca_set_batch_mode": [P, I32],
     "rpca_tune": [P, ctypes.POINTER(Matrix), I32, I32, ctypes.POINTER(TuneResult)],
     "rpca_tune_save": [P, ctypes.c_char_p],
     "rpca_tune_load": [P, ctypes.c_char_p],
@@ -443,6 +445,14 @@ class Context:
         X = torch.empty(l, l, device=M.device, dtype=torch.float64)
         self._check(self.lib.rpca_op_small_svd(self.h, l, _ptr(M), _ptr(s), _ptr(W), _ptr(X)))
         return W, s, X
+
+    def set_batch_mode(self, mode):
+        """0: persistent launch for the problems it takes (default); 1: streams only."""
+        self._check(self.lib.rpca_set_batch_mode(self.h, mode))
+
+    def set_batch_streams(self, n):
+        """Streams svd_batched spreads a batch over (default 8)."""
+        self._check(self.lib.rpca_set_batch_streams(self.h, n))
 
     # ---- autotuner ----------------------------------------------------
     def tune(self, A, l, reps=3, mat=None):

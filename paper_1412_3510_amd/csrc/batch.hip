@@ -1,0 +1,1076 @@
+// Persistent batched solver: many small problems in one launch.
+//
+// A workgroup of 512 threads (8 waves) solves one whole problem at a time --
+// the randomized SVD of Section 2 with the renormalized power iteration of
+// Section 5 (optionally on the column-centered A), or the shifted Nystrom
+// method of Section 3 for a PSD A -- with the workgroup-collective routines
+// below, and then takes the next problem from a device counter until the
+// list is exhausted.  The host orders the list by decreasing cost, so the
+// largest problems start first and the small ones fill in behind them.  No
+// workgroup ever waits for another, so the launch always drains.
+//
+// Per problem the steps are the ones of the multi-kernel path, restated for
+// one workgroup:
+//   * Omega from Philox4x32-10 (the same values as the single solve);
+//   * Y = A X and Z = A^T X on MFMA (v_mfma_f32_32x32x16_bf16, float32
+//     operands split into bfloat16 pairs, three products per tile): each wave
+//     owns 32 rows of the output tile (32 columns of A for A^T X) and loads
+//     its A values straight from memory; the packed small operand is staged
+//     through a two-buffer LDS ring shared by the 8 waves;
+//   * centering (Section 2: A_c = A - 1 mu): Y minus its column means after
+//     A X; the m-side operand minus its column means before A^T X;
+//   * LU renormalization (Section 5): a right-looking partial-pivoting LU,
+//     blocked by 4 columns, without physical row swaps.  Every thread keeps
+//     16 rows of the 4-column panel in registers; a step finds the pivot with
+//     one wave reduction and one barrier (the winning lane of each wave
+//     publishes its row), scales the multipliers and updates the panel; the
+//     trailing columns get one rank-4 update per panel.  The result P L
+//     (rows in the original order) overwrites Y; a zero pivot leaves the
+//     unit vector of its pivot row as that column of L;
+//   * orthonormalization: Cholesky QR twice with a float64 Gram matrix (up to
+//     four passes with a shifted factorization and completion of dependent
+//     columns, exactly as in the multi-kernel path);
+//   * the Rayleigh-Ritz step: B^T = A_c^T Q = Q2 R, the one-sided Jacobi SVD
+//     of R (shared with the single-problem kernel), U = Q W, V = Q2 X;
+//   * Nystrom: B1 = A Q, nu = sqrt(n) 2^-24 ||B1||_F, Cholesky of
+//     Q^T B1 + nu I (nu times 10 while it fails), F = (B1 + nu Q) C^-1, its
+//     SVD through Cholesky QR and Jacobi, lambda = max(s^2 - nu, 0);
+//   * the sign convention: the largest-magnitude entry of each column of U
+//     positive (ties to the smaller row), V's column follows.
+// Results agree with the single solve up to rounding (the renormalizations
+// choose other but equivalent bases; the final factors do not depend on
+// them in exact arithmetic).
+//
+// Limits (checked by the host): float32 A, row-major, lda >= n; m, n <=
+// 8192; l <= 64.  Working memory: one slot per workgroup (see pers_slot_floats).
+#include "common.h"
+#include "kernels.h"
+#include "philox.h"
+#include "small_core.h"
+
+namespace rpca {
+
+namespace {
+
+// Pointers passed into the (non-inlined) routines are generic; the routines
+// re-qualify them as global so that their accesses are global_* rather than
+// flat_* instructions (flat accesses also count against the LDS wait
+// counter, which would serialize the LDS reads with the A loads in flight).
+#define GAS __attribute__((address_space(1)))
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ GAS T* as_global(T* p) { return (GAS T*)p; }
+
+// Arguments of the routines are the same in every lane; reading them from the
+// first lane puts them in scalar registers (uniform branches and addresses).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint64_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ uint64_t uni(uint64_t v) { return (uint64_t)uni((int64_t)v); }
+template <class T>
+__device__ __forceinline__ T* uni(T* p) { return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p); }
+
+constexpr int NT = 512;                  // threads per workgroup
+constexpr int NWAVE = NT / 64;           // waves per workgroup
+constexpr int RPT = kPersMaxDim / NT;    // rows per thread in the LU (16)
+constexpr int PB = 4;                    // LU panel width
+
+// LDS of one workgroup.  The union holds the buffers of one step at a time.
+struct PLds {
+  union {
+    u32x4 xs[2][4 * 2 * 2 * 64];  // A-pass operand ring: 2 x (4 steps x 2 blocks x hi/lo x 64 lanes)
+    double gr[4096];              // Gram: row slices, then the group partials
+    struct {
+      double M[64 * 66];
+      double V[64 * 66];
+      double sig[64];
+      int perm[64];
+      int rot, big;
+    } jac;
+    struct {
+      unsigned long long key[2][NWAVE];
+      float row[2][NWAVE][PB];
+      float U12[PB][64];
+      int piv[64];
+    } lu;
+    struct {
+      float R[64 * 64];   // float32 factor (row-major), written by the Cholesky
+      float Rt[64 * 64];  // its transpose (column j contiguous)
+      float rd[64];       // reciprocals of the diagonal (0 for a zero pivot)
+    } tri;
+    double red[16 * 64];
+    unsigned long long kred[NWAVE * 64];
+    float W[64 * 64];
+  } u;
+  double ubuf[2 * 64];
+  double diag[64];
+  double zero[64];
+  float mu[64];
+  float sgn[64];
+  int state[16];
+  int idx;
+};
+
+__shared__ PLds g_S;
+
+// Working memory of one problem, carved from the workgroup's slot.
+struct Buf {
+  float* Y;     // R x 64
+  float* Z;     // R x 64
+  float* T;     // R x 64
+  __bf16* P;    // packed operand, R x 64 x 2 bf16
+  double* G;    // 64 x 64
+  double* Wacc; // 64 x 64
+  double* Xn;   // 64 x 64
+  double* sv;   // 64
+};
+
+__device__ __forceinline__ Buf carve(float* slot, int64_t R) {
+  Buf b;
+  b.Y = slot;
+  b.Z = slot + R * 64;
+  b.T = slot + 2 * R * 64;
+  b.P = reinterpret_cast<__bf16*>(slot + 3 * R * 64);
+  double* d = reinterpret_cast<double*>(slot + 4 * R * 64);
+  b.G = d;
+  b.Wacc = d + 4096;
+  b.Xn = d + 2 * 4096;
+  b.sv = d + 3 * 4096;
+  return b;
+}
+
+__device__ __forceinline__ f32x16 mfma3s(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                         const bf16x8& bl, f32x16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ __forceinline__ void split8(const float (&a)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    __bf16 h, l;
+    split_bf16(a[j], h, l);
+    hi[j] = h;
+    lo[j] = l;
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, o, 64);
+    const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), o, 64);
+    const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+    v = (w > v) ? w : v;
+  }
+  return v;
+}
+
+// |v| in the high word (larger wins), the complement of the index in the low
+// word (ties go to the smaller index); never 0 for a valid index.
+__device__ __forceinline__ unsigned long long abs_key(float v, int i) {
+  return ((unsigned long long)(__float_as_uint(v) & 0x7fffffffu) << 32) | (unsigned)(~(unsigned)i);
+}
+
+// ---- Omega: X (n x LP), X[i][c] = Omega[i][c] for c < l, 0 beyond ------------
+template <int LP>
+__device__ __attribute__((noinline)) void p_omega(uint64_t seed, int n, int l, float* X_) {
+  seed = uni(seed);
+  n = uni(n);
+  l = uni(l);
+  auto X = as_global(uni(X_));
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * LP; e += NT)
+    if ((e % LP) >= l) X[e] = 0.f;
+  // element e = 4 t + q of the stream is Omega[e % n][e / n]
+  const int64_t total = (int64_t)n * l, nb = (total + 3) / 4;
+  for (int64_t t = tid; t < nb; t += NT) {
+    uint32_t c[4] = {(uint32_t)t, (uint32_t)((uint64_t)t >> 32), 0u, 0u};
+    philox_block(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    float z[4];
+    box_muller(c[0], c[1], z[0], z[1]);
+    box_muller(c[2], c[3], z[2], z[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t e = 4 * t + q;
+      if (e < total) {
+        const int64_t j = e / n, i = e - j * n;
+        X[i * LP + j] = z[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ---- packed operand: src (rows x LP) minus mu -> bfloat16 (hi, lo) fragments,
+// rows padded with zeros to a multiple of 64.  Fragment (s, cb, h) holds, for
+// lane L = c + 32 g, the entries (16 s + 8 g + j, 32 cb + c), j = 0..7.
+template <int LP>
+__device__ __attribute__((noinline)) void p_pack(const float* src_, int rows, int l, bool use_mu, __bf16* out_) {
+  rows = uni(rows);
+  l = uni(l);
+  auto src = as_global(uni(src_));
+  auto out = as_global(uni(out_));
+  constexpr int NB = LP / 32;
+  const int nsteps = ((rows + 63) / 64) * 4;
+  const int total = nsteps * NB * 64;
+  GAS bf16x8* o = reinterpret_cast<GAS bf16x8*>(out);
+  for (int t = threadIdx.x; t < total; t += NT) {
+    const int L = t & 63, rest = t >> 6;
+    const int cb = rest % NB, s = rest / NB;
+    const int c = 32 * cb + (L & 31), g = L >> 5;
+    const float m = (use_mu && c < l) ? g_S.mu[c] : 0.f;
+    float a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int r = 16 * s + 8 * g + j;
+      a[j] = (r < rows && c < l) ? src[(int64_t)r * LP + c] - m : 0.f;
+    }
+    bf16x8 hi, lo;
+    split8(a, hi, lo);
+    o[((s * NB + cb) * 2) * 64 + L] = hi;
+    o[((s * NB + cb) * 2 + 1) * 64 + L] = lo;
+  }
+  __syncthreads();
+}
+
+// stage chunk ch (4 steps) of the packed operand into ring buffer buf
+template <int LP>
+__device__ __forceinline__ void stage_chunk(const GAS __bf16* Pk, int ch, int buf) {
+  PLds& S = g_S;
+  constexpr int CH = 4 * (LP / 32) * 2 * 64;  // uint4 per chunk
+  const GAS u32x4* src = reinterpret_cast<const GAS u32x4*>(Pk) + (int64_t)ch * CH;
+  for (int e = threadIdx.x; e < CH; e += NT) S.u.xs[buf][e] = src[e];
+}
+
+// ---- Y (m x LP) = A X, X packed (n side, >= ceil(n/64)*4 steps) -----------
+template <int LP>
+__device__ __attribute__((noinline)) void p_ax(const float* __restrict__ A_, int64_t lda, int m, int n, const __bf16* Xp_,
+                     float* Y_) {
+  lda = uni(lda);
+  m = uni(m);
+  n = uni(n);
+  auto A = as_global(uni(A_));
+  auto Xp = as_global(uni(Xp_));
+  auto Y = as_global(uni(Y_));
+  PLds& S = g_S;
+  constexpr int NB = LP / 32;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c = lane & 31, g = lane >> 5;
+  const int nchunk = (n + 63) / 64;
+  const bool vec = ((lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  for (int r0 = 0; r0 < m; r0 += 32 * NWAVE) {
+    const int rbase = r0 + 32 * wave;
+    const bool live = rbase < m;
+    const int row = rbase + c;
+    const bool rok = row < m;
+    const GAS float* arow = A + (int64_t)(rok ? row : 0) * lda;
+    f32x16 acc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+    float a[4][8];
+    auto load_a = [&](int ch) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k0 = 64 * ch + 16 * s + 8 * g;
+        if (vec && k0 + 8 <= n) {
+          const f32x4 v0 = *reinterpret_cast<const GAS f32x4*>(arow + k0);
+          const f32x4 v1 = *reinterpret_cast<const GAS f32x4*>(arow + k0 + 4);
+          a[s][0] = v0.x; a[s][1] = v0.y; a[s][2] = v0.z; a[s][3] = v0.w;
+          a[s][4] = v1.x; a[s][5] = v1.y; a[s][6] = v1.z; a[s][7] = v1.w;
+        } else {  // the tail (or an unaligned A): clamped loads, zero past n
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float v = arow[min(k0 + j, n - 1)];
+            a[s][j] = (k0 + j < n) ? v : 0.f;
+          }
+        }
+        if (!rok)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) a[s][j] = 0.f;
+      }
+    };
+    stage_chunk<LP>(Xp, 0, 0);
+    if (live) load_a(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nchunk) stage_chunk<LP>(Xp, ch + 1, buf ^ 1);
+      if (live) {
+        bf16x8 ah[4], al[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) split8(a[s], ah[s], al[s]);
+        if (ch + 1 < nchunk) load_a(ch + 1);
+        const bf16x8* xs = reinterpret_cast<const bf16x8*>(S.u.xs[buf]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) {
+            const bf16x8 xh = xs[((s * NB + cb) * 2) * 64 + lane];
+            const bf16x8 xl = xs[((s * NB + cb) * 2 + 1) * 64 + lane];
+            acc[cb] = mfma3s(ah[s], al[s], xh, xl, acc[cb]);
+          }
+      }
+      __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int ro = rbase + (r & 3) + 4 * g + 8 * (r >> 2);
+          if (ro < m) Y[(int64_t)ro * LP + 32 * cb + c] = acc[cb][r];
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// ---- Z (n x LP) = A^T Q, Q packed (m side, >= ceil(m/64)*4 steps) ---------
+template <int LP>
+__device__ __attribute__((noinline)) void p_atx(const float* __restrict__ A_, int64_t lda, int m, int n, const __bf16* Qp_,
+                      float* Z_) {
+  lda = uni(lda);
+  m = uni(m);
+  n = uni(n);
+  auto A = as_global(uni(A_));
+  auto Qp = as_global(uni(Qp_));
+  auto Z = as_global(uni(Z_));
+  PLds& S = g_S;
+  constexpr int NB = LP / 32;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c = lane & 31, g = lane >> 5;
+  const int nchunk = (m + 63) / 64;
+  for (int j0 = 0; j0 < n; j0 += 32 * NWAVE) {
+    const int cbase = j0 + 32 * wave;
+    const bool live = cbase < n;
+    const int col = cbase + c;
+    const bool cok = col < n;
+    const GAS float* acol = A + (cok ? col : 0);
+    f32x16 acc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+    float a[4][8];
+    auto load_a = [&](int ch) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k0 = 64 * ch + 16 * s + 8 * g;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {  // clamped row, zero past m
+          const float v = acol[(int64_t)min(k0 + j, m - 1) * lda];
+          a[s][j] = (cok && k0 + j < m) ? v : 0.f;
+        }
+      }
+    };
+    stage_chunk<LP>(Qp, 0, 0);
+    if (live) load_a(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nchunk) stage_chunk<LP>(Qp, ch + 1, buf ^ 1);
+      if (live) {
+        bf16x8 ah[4], al[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) split8(a[s], ah[s], al[s]);
+        if (ch + 1 < nchunk) load_a(ch + 1);
+        const bf16x8* xs = reinterpret_cast<const bf16x8*>(S.u.xs[buf]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) {
+            const bf16x8 xh = xs[((s * NB + cb) * 2) * 64 + lane];
+            const bf16x8 xl = xs[((s * NB + cb) * 2 + 1) * 64 + lane];
+            acc[cb] = mfma3s(ah[s], al[s], xh, xl, acc[cb]);
+          }
+      }
+      __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int jo = cbase + (r & 3) + 4 * g + 8 * (r >> 2);
+          if (jo < n) Z[(int64_t)jo * LP + 32 * cb + c] = acc[cb][r];
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// ---- column means of X (rows x LP) in float64 -> S.mu (0 beyond l) --------
+template <int LP>
+__device__ __attribute__((noinline)) void p_colmean(const float* X_, int rows, int l) {
+  rows = uni(rows);
+  l = uni(l);
+  auto X = as_global(uni(X_));
+  PLds& S = g_S;
+  constexpr int NG = NT / LP;
+  const int tid = threadIdx.x, c = tid % LP, gi = tid / LP;
+  double s = 0.0;
+  if (c < l)
+    for (int r = gi; r < rows; r += NG) s += (double)X[(int64_t)r * LP + c];
+  S.u.red[gi * LP + c] = s;
+  __syncthreads();
+  if (tid < LP) {
+    double t = 0.0;
+    for (int h = 0; h < NG; ++h) t += S.u.red[h * LP + tid];
+    S.mu[tid] = (tid < l && rows > 0) ? (float)(t / rows) : 0.f;
+  }
+  __syncthreads();
+}
+
+template <int LP>
+__device__ __attribute__((noinline)) void p_sub_mu(float* X_, int rows, int l) {
+  rows = uni(rows);
+  l = uni(l);
+  auto X = as_global(uni(X_));
+  PLds& S = g_S;
+  for (int e = threadIdx.x; e < rows * LP; e += NT) {
+    const int c = e % LP;
+    if (c < l) X[e] -= S.mu[c];
+  }
+  __syncthreads();
+}
+
+// ---- LU renormalization: Y (rows x LP) <- P L in place (rows <= 8192) -----
+template <int LP>
+__device__ __attribute__((noinline)) void p_lu(float* Y_, int rows, int l) {
+  rows = uni(rows);
+  l = uni(l);
+  auto Y = as_global(uni(Y_));
+  PLds& S = g_S;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  unsigned done = 0u;  // bit r: row tid + NT r is a pivot row
+  int ph = 0;
+  for (int c0 = 0; c0 < l; c0 += PB) {
+    const int pw = min(PB, l - c0);
+    const unsigned done0 = done;
+    float pan[RPT][PB];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + NT * r;
+      const bool own = i < rows && !((done >> r) & 1u);
+#pragma unroll
+      for (int q = 0; q < PB; ++q)
+        pan[r][q] = (own && q < pw) ? Y[(int64_t)i * LP + c0 + q] : 0.f;
+    }
+#pragma unroll
+    for (int jj = 0; jj < PB; ++jj) {
+      if (jj < pw) {
+        const int j = c0 + jj;
+        unsigned long long best = 0ull;
+        float bv[PB];
+#pragma unroll
+        for (int q = 0; q < PB; ++q) bv[q] = 0.f;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + NT * r;
+          if (i < rows && !((done >> r) & 1u)) {
+            const unsigned long long key = abs_key(pan[r][jj], i);
+            if (key > best) {
+              best = key;
+#pragma unroll
+              for (int q = 0; q < PB; ++q) bv[q] = pan[r][q];
+            }
+          }
+        }
+        const unsigned long long wbest = wave_max_u64(best);
+        if (best == wbest && best != 0ull) {
+          S.u.lu.key[ph][wave] = best;
+#pragma unroll
+          for (int q = 0; q < PB; ++q) S.u.lu.row[ph][wave][q] = bv[q];
+        }
+        if (lane == 0 && wbest == 0ull) S.u.lu.key[ph][wave] = 0ull;
+        __syncthreads();
+        unsigned long long kb = 0ull;
+        int wb = 0;
+#pragma unroll
+        for (int w = 0; w < NWAVE; ++w) {
+          const unsigned long long k = S.u.lu.key[ph][w];
+          if (k > kb) {
+            kb = k;
+            wb = w;
+          }
+        }
+        const int p = (int)(~(unsigned)kb);
+        float pr[PB];
+#pragma unroll
+        for (int q = 0; q < PB; ++q) pr[q] = S.u.lu.row[ph][wb][q];
+        const float pv = pr[jj];
+        const float rp = (pv != 0.f) ? 1.0f / pv : 0.f;  // a zero pivot: multipliers 0
+        if (tid == 0) S.u.lu.piv[j] = p;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (tid + NT * r == p) done |= 1u << r;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + NT * r;
+          if (i < rows && !((done >> r) & 1u)) {
+            const float f = pan[r][jj] * rp;
+            pan[r][jj] = f;
+#pragma unroll
+            for (int q = jj + 1; q < PB; ++q) pan[r][q] = fmaf(-f, pr[q], pan[r][q]);
+          }
+        }
+        ph ^= 1;
+      }
+    }
+    // multipliers (and the U part of this panel's pivot rows) back to Y
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + NT * r;
+      if (i < rows && !((done0 >> r) & 1u))
+#pragma unroll
+        for (int q = 0; q < PB; ++q)
+          if (q < pw) Y[(int64_t)i * LP + c0 + q] = pan[r][q];
+    }
+    __syncthreads();
+    const int cs = c0 + pw;  // first trailing column
+    if (cs < l) {
+      // U12: the pivot rows' trailing entries after this panel's eliminations
+      if (tid < l - cs) {
+        const int col = cs + tid;
+        float u[PB];
+#pragma unroll
+        for (int t = 0; t < PB; ++t) {
+          if (t < pw) {
+            const int pt = S.u.lu.piv[c0 + t];
+            float v = Y[(int64_t)pt * LP + col];
+#pragma unroll
+            for (int s2 = 0; s2 < t; ++s2) v = fmaf(-Y[(int64_t)pt * LP + c0 + s2], u[s2], v);
+            u[t] = v;
+            Y[(int64_t)pt * LP + col] = v;
+            S.u.lu.U12[t][col] = v;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = tid + NT * r;
+        if (i < rows && !((done >> r) & 1u)) {
+          auto yr = Y + (int64_t)i * LP;
+          for (int col = cs; col < l; ++col) {
+            float v = yr[col];
+#pragma unroll
+            for (int t = 0; t < PB; ++t)
+              if (t < pw) v = fmaf(-pan[r][t], S.u.lu.U12[t][col], v);
+            yr[col] = v;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // pivot rows of L: 1 at their own step, 0 after it
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + NT * r;
+    if (i < rows && ((done >> r) & 1u)) {
+      int st = 0;
+      for (int j = 0; j < l; ++j)
+        if (S.u.lu.piv[j] == i) st = j;
+      auto yr = Y + (int64_t)i * LP;
+      yr[st] = 1.f;
+      for (int c = st + 1; c < l; ++c) yr[c] = 0.f;
+    }
+  }
+  __syncthreads();
+}
+
+// ---- G (LP x LP, float64) = X^T X2 (X2 = X when null) ---------------------
+template <int LP>
+__device__ __attribute__((noinline)) void p_gram(const float* X_, const float* X2_, int rows, double* G_) {
+  rows = uni(rows);
+  auto X = as_global(uni(X_));
+  auto X2 = as_global(uni(X2_));
+  auto G = as_global(uni(G_));
+  PLds& S = g_S;
+  constexpr int T = LP / 16, SL = 16;
+  const int tid = threadIdx.x, grp = tid >> 8, t = tid & 255, ti = t >> 4, tj = t & 15;
+  const bool same = (X2 == nullptr);
+  double* sa = S.u.gr + grp * 2 * SL * 64;
+  double* sb = same ? sa : sa + SL * 64;
+  double acc[T][T];
+#pragma unroll
+  for (int u = 0; u < T; ++u)
+#pragma unroll
+    for (int v = 0; v < T; ++v) acc[u][v] = 0.0;
+  for (int r0 = 0; r0 < rows; r0 += 2 * SL) {
+    const int rs = r0 + grp * SL;
+    for (int e = t; e < SL * LP; e += 256) {
+      const int rr = e / LP, c = e % LP, r = rs + rr;
+      sa[e] = (r < rows) ? (double)X[(int64_t)r * LP + c] : 0.0;
+      if (!same) sb[e] = (r < rows) ? (double)X2[(int64_t)r * LP + c] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < SL; ++rr) {
+      double a[T], b[T];
+#pragma unroll
+      for (int u = 0; u < T; ++u) {
+        a[u] = sa[rr * LP + ti * T + u];
+        b[u] = sb[rr * LP + tj * T + u];
+      }
+#pragma unroll
+      for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
+  }
+  if (grp == 1)
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+      for (int v = 0; v < T; ++v) S.u.gr[(ti * T + u) * LP + tj * T + v] = acc[u][v];
+  __syncthreads();
+  if (grp == 0)
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+      for (int v = 0; v < T; ++v) {
+        const int e = (ti * T + u) * LP + tj * T + v;
+        G[e] = acc[u][v] + S.u.gr[e];
+      }
+  __syncthreads();
+}
+
+// transpose and reciprocal diagonal of the float32 factor in S.u.tri.R (rows < l)
+template <int LP>
+__device__ __attribute__((noinline)) void p_tri_finish(int l) {
+  PLds& S = g_S;
+  for (int e = threadIdx.x; e < LP * LP; e += NT) {
+    const int i = e / LP, j = e % LP;
+    S.u.tri.Rt[j * LP + i] = (i < l && j < l) ? S.u.tri.R[e] : 0.f;
+  }
+  if (threadIdx.x < LP) {
+    const int j = threadIdx.x;
+    const float d = (j < l) ? S.u.tri.R[j * LP + j] : 0.f;
+    S.u.tri.rd[j] = (d != 0.f) ? 1.0f / d : 0.f;
+  }
+  __syncthreads();
+}
+
+// One Cholesky-QR pass on the Gram matrix G: the factor (shifted when G is
+// numerically singular) in S.u.tri, the pass bookkeeping in S.state (the
+// layout of the multi-kernel path).
+template <int LP>
+__device__ __attribute__((noinline)) void p_chol_qr(const double* G_, int l, int pass) {
+  l = uni(l);
+  pass = uni(pass);
+  auto G = as_global(uni(G_));
+  PLds& S = g_S;
+  const int tid = threadIdx.x;
+  if (pass == 1 && tid < 12) S.state[tid] = 0;
+  if (tid < LP) S.diag[tid] = (tid < l) ? G[tid * LP + tid] : 0.0;
+  __syncthreads();
+  double maxd = 0.0;
+  for (int j = 0; j < l; ++j) maxd = fmax(maxd, S.diag[j]);
+  bool shifted = false;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    __syncthreads();
+    const double srel = attempt ? kShiftRel : 0.0;
+    const double sabs = attempt ? (1e-30 * maxd + 1e-300) : 0.0;
+    const bool ok = chol_par<LP, NT>(G_, false, l, srel, sabs, S.diag, attempt ? 0.0 : kTauRel,
+                                     S.u.tri.R, S.ubuf);
+    if (ok) break;
+    if (attempt == 1 && tid == 0) S.state[5] = 1;
+    shifted = true;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (shifted) S.state[0] = 1;
+    if (pass == 2) {
+      unsigned mask[4] = {0u, 0u, 0u, 0u};
+      int any = 0;
+      if (S.state[0]) {
+        for (int j = 0; j < l; ++j)
+          if (!(S.diag[j] >= kJunkNorm2)) {
+            mask[j >> 5] |= 1u << (j & 31);
+            any = 1;
+          }
+      }
+      for (int w = 0; w < 4; ++w) S.state[8 + w] = (int)mask[w];
+      S.state[2] = any;
+      S.state[1] = S.state[0] | any;
+    }
+  }
+  p_tri_finish<LP>(l);
+}
+
+// X (rows x LP) <- (X + nu addX) R^-1 with the factor in S.u.tri
+template <int LP>
+__device__ __attribute__((noinline)) void p_trsm(float* X_, int rows, int l, const float* addX_, float nu) {
+  rows = uni(rows);
+  l = uni(l);
+  auto X = as_global(uni(X_));
+  auto addX = as_global(uni(addX_));
+  PLds& S = g_S;
+  for (int row = threadIdx.x; row < rows; row += NT) {
+    asm volatile("" ::: "memory");  // read the factor from LDS inside the loop
+    float x[LP];
+    auto src = X + (int64_t)row * LP;
+#pragma unroll
+    for (int c = 0; c < LP; c += 4) {
+      const f32x4 v = *reinterpret_cast<const GAS f32x4*>(src + c);
+      x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
+    }
+    if (addX) {
+      auto a = addX + (int64_t)row * LP;
+#pragma unroll
+      for (int c = 0; c < LP; c += 4) {
+        const f32x4 v = *reinterpret_cast<const GAS f32x4*>(a + c);
+        x[c] += nu * v.x; x[c + 1] += nu * v.y; x[c + 2] += nu * v.z; x[c + 3] += nu * v.w;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < LP; ++j) {
+      if (j < l) {
+        float s = x[j];
+        const float* col = S.u.tri.Rt + j * LP;
+#pragma unroll
+        for (int i = 0; i < j; ++i) s -= x[i] * col[i];
+        x[j] = s * S.u.tri.rd[j];
+      } else {
+        x[j] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < LP; c += 4)
+      *reinterpret_cast<GAS f32x4*>(src + c) = f32x4{x[c], x[c + 1], x[c + 2], x[c + 3]};
+  }
+  __syncthreads();
+}
+
+// Q (rows x LP): dependent columns (S.state mask) replaced by Gaussian ones
+template <int LP>
+__device__ __attribute__((noinline)) void p_complete(float* Q_, int rows, int l, uint64_t seed) {
+  rows = uni(rows);
+  l = uni(l);
+  seed = uni(seed);
+  auto Q = as_global(uni(Q_));
+  PLds& S = g_S;
+  if (S.state[2] == 0) return;
+  for (int e = threadIdx.x; e < rows * l; e += NT) {
+    const int r = e / l, j = e % l;
+    if ((((unsigned)S.state[8 + (j >> 5)]) >> (j & 31)) & 1u)
+      Q[(int64_t)r * LP + j] = philox_normal(seed, 3u, (uint64_t)r * 128u + (uint64_t)j);
+  }
+  __syncthreads();
+}
+
+// Cholesky QR, twice (and twice more when a pass was shifted or columns were
+// completed); with want_r, G = Q^T X_in afterwards (X_in kept in Bk).
+template <int LP>
+__device__ __attribute__((noinline)) void p_orth(float* X, int rows, int l, bool want_r, float* Bk, double* G,
+                       uint64_t seed) {
+  rows = uni(rows);
+  l = uni(l);
+  seed = uni(seed);
+  X = uni(X);
+  Bk = uni(Bk);
+  G = uni(G);
+  want_r = uni((int)want_r) != 0;
+  PLds& S = g_S;
+  if (want_r) {
+    auto src = as_global(X);
+    auto dst = as_global(Bk);
+    for (int e = threadIdx.x; e < rows * LP; e += NT) dst[e] = src[e];
+    __syncthreads();
+  }
+  for (int pass = 1; pass <= 4; ++pass) {
+    if (pass >= 3 && S.state[1] == 0) break;
+    p_gram<LP>(X, nullptr, rows, G);
+    p_chol_qr<LP>(G, l, pass);
+    p_trsm<LP>(X, rows, l, nullptr, 0.f);
+    if (pass == 2) p_complete<LP>(X, rows, l, seed ^ 0x5bd1e995u);
+  }
+  if (want_r) p_gram<LP>(X, Bk, rows, G);
+}
+
+// out (rows x k, ld ldo) = X (rows x l) W (l x k), W float64 (stride LP) rounded to float32
+template <int LP>
+__device__ __attribute__((noinline)) void p_small_gemm(const float* X_, int rows, int l, const double* W_, int k, float* out_,
+                             int64_t ldo) {
+  rows = uni(rows);
+  l = uni(l);
+  k = uni(k);
+  ldo = uni(ldo);
+  auto X = as_global(uni(X_));
+  auto W = as_global(uni(W_));
+  auto out = as_global(uni(out_));
+  PLds& S = g_S;
+  for (int e = threadIdx.x; e < LP * LP; e += NT) {
+    const int c = e / LP, i = e % LP;  // column c of W stored contiguously
+    S.u.W[e] = (i < l && c < k) ? (float)W[i * LP + c] : 0.f;
+  }
+  __syncthreads();
+  for (int row = threadIdx.x; row < rows; row += NT) {
+    asm volatile("" ::: "memory");  // read the factor from LDS inside the loop
+    float x[LP];
+    auto src = X + (int64_t)row * LP;
+#pragma unroll
+    for (int c = 0; c < LP; c += 4) {
+      const f32x4 v = *reinterpret_cast<const GAS f32x4*>(src + c);
+      x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
+    }
+    for (int c = 0; c < k; ++c) {
+      const float* w = S.u.W + c * LP;
+      float s = 0.f;
+#pragma unroll
+      for (int i = 0; i < LP; ++i) s += x[i] * w[i];
+      out[(int64_t)row * ldo + c] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// sign convention on U (m x k) and V (n x k, nullable)
+__device__ __attribute__((noinline)) void p_sign(float* U_, int64_t ldu, int m, int k, float* V_,
+                                                 int64_t ldv, int n) {
+  ldu = uni(ldu);
+  m = uni(m);
+  k = uni(k);
+  ldv = uni(ldv);
+  n = uni(n);
+  auto U = as_global(uni(U_));
+  auto V = as_global(uni(V_));
+  PLds& S = g_S;
+  const int tid = threadIdx.x, q = tid & 63, gi = tid >> 6;
+  unsigned long long best = 0ull;
+  if (q < k)
+    for (int r = gi; r < m; r += NWAVE) {
+      const unsigned long long key = abs_key(U[(int64_t)r * ldu + q], r);
+      best = key > best ? key : best;
+    }
+  S.u.kred[gi * 64 + q] = best;
+  __syncthreads();
+  if (tid < k) {
+    unsigned long long b = 0ull;
+    for (int h = 0; h < NWAVE; ++h) b = S.u.kred[h * 64 + tid] > b ? S.u.kred[h * 64 + tid] : b;
+    const int r = (int)(~(unsigned)b);
+    S.sgn[tid] = (U[(int64_t)r * ldu + tid] < 0.f) ? -1.f : 1.f;
+  }
+  __syncthreads();
+  for (int e = tid; e < m * k; e += NT) {
+    const int r = e / k, c = e % k;
+    if (S.sgn[c] < 0.f) U[(int64_t)r * ldu + c] = -U[(int64_t)r * ldu + c];
+  }
+  if (V)
+    for (int e = tid; e < n * k; e += NT) {
+      const int r = e / k, c = e % k;
+      if (S.sgn[c] < 0.f) V[(int64_t)r * ldv + c] = -V[(int64_t)r * ldv + c];
+    }
+  __syncthreads();
+}
+
+// ||X||_F^2 over the first l columns, float64 (every thread gets the value)
+template <int LP>
+__device__ __attribute__((noinline)) double p_fro2(const float* X_, int rows, int l) {
+  rows = uni(rows);
+  l = uni(l);
+  auto X = as_global(uni(X_));
+  PLds& S = g_S;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < rows * LP; e += NT)
+    if ((e % LP) < l) {
+      const double v = X[e];
+      s += v * v;
+    }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) S.u.red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < NWAVE; ++w) t += S.u.red[w];
+  __syncthreads();
+  return t;
+}
+
+// Nystrom: Cholesky of (G + G^T)/2 + nu I with nu multiplied by 10 while it
+// fails (at most max_retries times); the identity if it never succeeds.
+template <int LP>
+__device__ __attribute__((noinline)) double p_chol_nystrom(const double* G_, int l, double fro2, double n_sqrt_u,
+                                 int max_retries) {
+  l = uni(l);
+  max_retries = uni(max_retries);
+  auto G = as_global(uni(G_));
+  PLds& S = g_S;
+  double nu = n_sqrt_u * sqrt(fro2);
+  if (!(nu > 0.0)) nu = 1e-300;
+  bool ok = false;
+  for (int retry = 0; retry <= max_retries; ++retry) {
+    __syncthreads();
+    ok = chol_par<LP, NT>(G_, true, l, 0.0, nu, S.zero, 0.0, S.u.tri.R, S.ubuf);
+    if (ok) break;
+    if (retry < max_retries) nu *= 10.0;
+  }
+  __syncthreads();
+  if (!ok)
+    for (int e = threadIdx.x; e < LP * LP; e += NT) {
+      const int i = e / LP, c = e % LP;
+      S.u.tri.R[e] = (i == c && i < l) ? 1.f : 0.f;
+    }
+  __syncthreads();
+  p_tri_finish<LP>(l);
+  return nu;
+}
+
+template <int LP>
+__device__ __attribute__((noinline)) void jacobi_wg(const double* G, int l, int transpose, Buf& b) {
+  l = uni(l);
+  transpose = uni(transpose);
+  PLds& S = g_S;
+  jacobi_body<LP, false, 16>((const double*)as_global(uni(G)), l, transpose,
+                             (double*)as_global(uni(b.sv)), (double*)as_global(uni(b.Wacc)),
+                             (double*)as_global(uni(b.Xn)), S.u.jac.M, S.u.jac.V,
+                             S.u.jac.sig, S.u.jac.perm, S.u.jac.rot, S.u.jac.big);
+  __syncthreads();
+}
+
+template <int LP>
+__device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b) {
+  PLds& S = g_S;
+  const float* A = p.A;
+  const int m = p.m, n = p.n, l = p.l;
+  const bool center = p.center != 0;
+  auto mid = [&](float* T, int rows) {
+    if (p.orth_all) p_orth<LP>(T, rows, l, false, b.T, b.G, p.seed);
+    else p_lu<LP>(T, rows, l);
+  };
+  auto apply_a = [&](const float* X) {  // Y = A X (centered when asked)
+    p_pack<LP>(X, n, l, false, b.P);
+    p_ax<LP>(A, p.lda, m, n, b.P, b.Y);
+    if (center) {
+      p_colmean<LP>(b.Y, m, l);
+      p_sub_mu<LP>(b.Y, m, l);
+    }
+  };
+  auto apply_at = [&]() {  // Z = A_c^T Y
+    if (center) p_colmean<LP>(b.Y, m, l);
+    p_pack<LP>(b.Y, m, l, center, b.P);
+    p_atx<LP>(A, p.lda, m, n, b.P, b.Z);
+  };
+  p_omega<LP>(p.seed, n, l, b.Z);
+  apply_a(b.Z);
+  if (p.its == 0) p_orth<LP>(b.Y, m, l, false, b.T, b.G, p.seed);
+  else mid(b.Y, m);
+  for (int it = 1; it <= p.its; ++it) {
+    apply_at();
+    mid(b.Z, n);
+    apply_a(b.Z);
+    if (it < p.its) mid(b.Y, m);
+    else p_orth<LP>(b.Y, m, l, false, b.T, b.G, p.seed);
+  }
+  // Rayleigh-Ritz: A_c^T Q = Q2 R, R = W S X^T (Jacobi), U = Q W, V = Q2 X
+  apply_at();
+  p_orth<LP>(b.Z, n, l, true, b.T, b.G, p.seed + 1);
+  jacobi_wg<LP>(b.G, l, 0, b);
+  p_small_gemm<LP>(b.Y, m, l, b.Wacc, p.k, p.U, p.ldu);
+  p_small_gemm<LP>(b.Z, n, l, b.Xn, p.k, p.V, p.ldv);
+  if (threadIdx.x < p.k) p.S[threadIdx.x] = b.sv[threadIdx.x];
+  p_sign(p.U, p.ldu, m, p.k, p.V, p.ldv, n);
+}
+
+template <int LP>
+__device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b) {
+  const float* A = p.A;
+  const int n = p.n, l = p.l;
+  float* Q = b.Y;
+  float* Q2 = b.Z;
+  p_omega<LP>(p.seed, n, l, Q);
+  if (p.its == 0) p_orth<LP>(Q, n, l, false, b.T, b.G, p.seed);
+  for (int it = 1; it <= p.its; ++it) {
+    p_pack<LP>(Q, n, l, false, b.P);
+    p_ax<LP>(A, p.lda, n, n, b.P, Q2);
+    float* t = Q;
+    Q = Q2;
+    Q2 = t;
+    if (it < p.its && !p.orth_all) p_lu<LP>(Q, n, l);
+    else p_orth<LP>(Q, n, l, false, b.T, b.G, p.seed);
+  }
+  // B1 = A Q (start); B2 = Q^T B1 (second), shifted; C = chol (Cholesky)
+  p_pack<LP>(Q, n, l, false, b.P);
+  p_ax<LP>(A, p.lda, n, n, b.P, Q2);
+  const double fro2 = p_fro2<LP>(Q2, n, l);
+  p_gram<LP>(Q, Q2, n, b.G);
+  const double nu = p_chol_nystrom<LP>(b.G, l, fro2, sqrt((double)n) * 0x1p-24, 10);
+  // F = (B1 + nu Q) C^-1 (pseudo), F = QF R, R^T = ... (Jacobi on R^T)
+  p_trsm<LP>(Q2, n, l, Q, (float)nu);
+  p_orth<LP>(Q2, n, l, true, b.T, b.G, p.seed + 1);
+  jacobi_wg<LP>(b.G, l, 1, b);
+  p_small_gemm<LP>(Q2, n, l, b.Wacc, p.k, p.U, p.ldu);
+  if (threadIdx.x < p.k) {
+    const double s = b.sv[threadIdx.x];
+    p.S[threadIdx.x] = fmax(s * s - nu, 0.0);
+  }
+  p_sign(p.U, p.ldu, n, p.k, nullptr, 0, 0);
+}
+
+__global__ void __launch_bounds__(NT) persistent_kernel(const PersProblem* __restrict__ probs,
+                                                        int count, int* counter, float* ws,
+                                                        int64_t slot_floats, int64_t R) {
+  __shared__ PLds S;
+  const int tid = threadIdx.x;
+  if (tid < 64) S.zero[tid] = 0.0;
+  Buf b = carve(ws + (int64_t)blockIdx.x * slot_floats, R);
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) S.idx = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = S.idx;
+    if (idx >= count) break;
+    const PersProblem p = probs[idx];
+    if (p.l <= 32) {
+      if (p.kind == 0) solve_svd<32>(p, b);
+      else solve_psd<32>(p, b);
+    } else {
+      if (p.kind == 0) solve_svd<64>(p, b);
+      else solve_psd<64>(p, b);
+    }
+  }
+}
+
+// The problem table travels in kernel arguments (32 entries per launch) and
+// is written on the stream, so a captured graph replays its own table.
+constexpr int kTabChunk = 32;
+struct TabChunk {
+  PersProblem p[kTabChunk];
+};
+
+__global__ void __launch_bounds__(kTabChunk) table_kernel(TabChunk c, int cnt, PersProblem* dst) {
+  if ((int)threadIdx.x < cnt) dst[threadIdx.x] = c.p[threadIdx.x];
+}
+
+}  // namespace
+
+void launch_pers_table(hipStream_t st, const PersProblem* host, int count, PersProblem* dev) {
+  for (int c0 = 0; c0 < count; c0 += kTabChunk) {
+    TabChunk c;
+    const int cnt = count - c0 < kTabChunk ? count - c0 : kTabChunk;
+    for (int i = 0; i < cnt; ++i) c.p[i] = host[c0 + i];
+    hipLaunchKernelGGL(table_kernel, dim3(1), dim3(kTabChunk), 0, st, c, cnt, dev + c0);
+  }
+}
+
+int64_t pers_rows(int64_t maxdim) { return round_up(maxdim > 0 ? maxdim : 1, 64); }
+
+int64_t pers_slot_floats(int64_t maxdim) {
+  return 4 * pers_rows(maxdim) * 64 + 2 * (3 * 4096 + 64);
+}
+
+void launch_persistent(hipStream_t st, const PersProblem* probs, int count, int* counter,
+                       float* ws, int64_t maxdim, int grid) {
+  if (count <= 0 || grid <= 0) return;
+  hipLaunchKernelGGL(persistent_kernel, dim3(grid), dim3(NT), 0, st, probs, count, counter, ws,
+                     pers_slot_floats(maxdim), pers_rows(maxdim));
+}
+
+}  // namespace rpca

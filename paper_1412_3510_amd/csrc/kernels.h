@@ -179,4 +179,33 @@ void launch_spectral(hipStream_t st, const float* A, int64_t lda, int64_t m, int
                      const SpecSparse* sp);
 size_t spectral_work_bytes(int64_t m, int64_t n, int k);
 
+// ---- persistent batched solver (batch.hip) --------------------------------------
+// One problem of the persistent launch (float32 A, row-major; all pointers
+// device memory).  kind 0: randomized SVD (center: of the column-centered A);
+// kind 1: Nystrom for a PSD A (m == n).  orth_all: Cholesky QR in place of
+// every LU renormalization.
+struct PersProblem {
+  const float* A;
+  int64_t lda;
+  float* U;
+  int64_t ldu;
+  double* S;
+  float* V;
+  int64_t ldv;
+  uint64_t seed;
+  int32_t m, n, kind, k, l, its, center, orth_all;
+};
+static constexpr int kPersMaxDim = 8192;  // largest m, n
+static constexpr int kPersMaxL = 64;      // largest l
+// rows of each slot buffer and floats per workgroup slot for problems up to maxdim
+int64_t pers_rows(int64_t maxdim);
+int64_t pers_slot_floats(int64_t maxdim);
+// write ``count`` entries of the problem table to ``dev`` on the stream (kernel
+// arguments carry the host entries, so the copy is graph-capturable)
+void launch_pers_table(hipStream_t st, const PersProblem* host, int count, PersProblem* dev);
+// ``count`` problems (device table) over ``grid`` workgroups; ``counter`` (device int,
+// zero at launch) hands out the problems; ``ws`` holds grid * pers_slot_floats floats.
+void launch_persistent(hipStream_t st, const PersProblem* probs, int count, int* counter,
+                       float* ws, int64_t maxdim, int grid);
+
 }  // namespace rpca

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <list>
 #include <map>
 #include <cmath>
 #include <cstdio>
@@ -57,6 +58,18 @@ struct rpca_ctx_s {
   hipEvent_t fork = nullptr;
   // autotuned configurations by shape class (ceil log2 m, ceil log2 n, lp, dtype)
   std::map<std::array<int, 4>, TuneCfg> tune;
+  int batch_streams = 8;  // streams rpca_svd_batched spreads a batch over
+  int batch_mode = 0;     // 0: persistent launch for the problems it takes; 1: streams only
+  // persistent batched launch: the device problem table (rewritten by every
+  // call, on the stream, so a captured graph carries its own table), the work
+  // counter, the working memory, and memory superseded by larger buffers
+  // (graphs captured earlier still use it, so it is kept until rpca_destroy)
+  rpca::PersProblem* pers_tab = nullptr;
+  int pers_tab_cap = 0;
+  int* pers_counter = nullptr;
+  float* pers_ws = nullptr;
+  int64_t pers_ws_floats = 0;
+  std::vector<void*> pers_retired;
 };
 
 namespace {
@@ -548,6 +561,10 @@ rpca_status rpca_destroy(rpca_ctx ctx) {
     if (b.stream) (void)hipStreamDestroy(b.stream);
   }
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->pers_tab) (void)hipFree(ctx->pers_tab);
+  if (ctx->pers_counter) (void)hipFree(ctx->pers_counter);
+  if (ctx->pers_ws) (void)hipFree(ctx->pers_ws);
+  for (void* q : ctx->pers_retired) (void)hipFree(q);
   delete ctx;
   return RPCA_OK;
 }
@@ -897,12 +914,110 @@ rpca_status rpca_reset_stats(rpca_ctx ctx) {
 }
 
 
+}  // extern "C"
+
+namespace {
+struct ctx_s_pers_plan {
+  std::vector<PersProblem> table;  // largest problems first
+  int64_t maxdim = 0;
+  int grid = 0;
+};
+
+// grow a device buffer outside capture; the old one is kept for graphs that use it
+template <class T>
+rpca_status pers_grow(rpca_ctx ctx, T*& buf, size_t bytes, const char* what) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, RPCA_ERR_NO_MEMORY, std::string("persistent batch: allocation of the ") +
+                                             what + " failed");
+  }
+  if (buf) ctx->pers_retired.push_back(buf);
+  buf = static_cast<T*>(q);
+  return RPCA_OK;
+}
+
+// Table (largest problems first) and working memory of the persistent launch.
+rpca_status pers_prepare(rpca_ctx ctx, const rpca_problem* problems, const std::vector<int>& pers,
+                         bool capturing, ctx_s_pers_plan& plan) {
+  std::vector<PersProblem> tab;
+  std::vector<double> cost;
+  int64_t maxdim = 1;
+  for (int p : pers) {
+    const rpca_problem& q = problems[p];
+    const rpca_matrix* A = q.A;
+    PersProblem e{};
+    e.A = static_cast<const float*>(A->data);
+    e.lda = A->ld;
+    e.U = q.U;
+    e.ldu = q.ldu;
+    e.S = q.S;
+    e.V = q.kind == 0 ? q.V : nullptr;
+    e.ldv = q.kind == 0 ? q.ldv : 0;
+    e.seed = q.seed;
+    e.m = (int32_t)A->m;
+    e.n = (int32_t)A->n;
+    e.kind = q.kind;
+    e.k = q.k;
+    e.l = q.l > 0 ? q.l : q.k + 2;
+    e.its = q.its;
+    e.center = (q.flags & RPCA_CENTER) ? 1 : 0;
+    e.orth_all = (q.flags & RPCA_RENORM_ORTH) ? 1 : 0;
+    tab.push_back(e);
+    const double passes = q.kind == 0 ? 2.0 * q.its + 2.0 : q.its + 1.0;
+    cost.push_back(passes * (double)A->m * (double)A->n * (e.l <= 32 ? 32 : 64) +
+                   4096.0 * (double)(A->m + A->n) * e.l);
+    maxdim = std::max<int64_t>(maxdim, std::max(A->m, A->n));
+  }
+  std::vector<int> ord(tab.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  for (int i : ord) plan.table.push_back(tab[i]);
+  const int cnt = (int)plan.table.size();
+  const int grid = (int)std::min<int64_t>(cnt, ctx->num_cus);
+  const int64_t need = (int64_t)grid * pers_slot_floats(maxdim);
+  if (ctx->pers_ws_floats < need || ctx->pers_tab_cap < cnt || !ctx->pers_counter) {
+    if (capturing) return fail(ctx, RPCA_ERR_UNSUPPORTED, "run the batch once before capturing it");
+    if (ctx->ws_limit && (size_t)need * sizeof(float) > ctx->ws_limit)
+      return fail(ctx, RPCA_ERR_NO_MEMORY, "batch workspace exceeds the limit");
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    rpca_status s = RPCA_OK;
+    if (ctx->pers_ws_floats < need) {
+      s = pers_grow(ctx, ctx->pers_ws, (size_t)need * sizeof(float), "working memory");
+      if (s != RPCA_OK) return s;
+      ctx->pers_ws_floats = need;
+    }
+    if (ctx->pers_tab_cap < cnt) {
+      s = pers_grow(ctx, ctx->pers_tab, (size_t)cnt * sizeof(PersProblem), "problem table");
+      if (s != RPCA_OK) return s;
+      ctx->pers_tab_cap = cnt;
+    }
+    if (!ctx->pers_counter) {
+      s = pers_grow(ctx, ctx->pers_counter, 256, "work counter");
+      if (s != RPCA_OK) return s;
+    }
+  }
+  plan.maxdim = maxdim;
+  plan.grid = grid;
+  return RPCA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rpca_status rpca_set_batch_mode(rpca_ctx ctx, int32_t mode) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (mode != 0 && mode != 1) return fail(ctx, RPCA_ERR_INVALID_ARG, "batch mode must be 0 or 1");
+  ctx->batch_mode = mode;
+  return RPCA_OK;
+}
+
 rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* problems,
                              unsigned flags) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
   if (count < 0 || (count > 0 && !problems)) return fail(ctx, RPCA_ERR_INVALID_ARG, "bad batch");
   if (count == 0) return RPCA_OK;
-  constexpr int kSlots = 8;
+  const int kSlots = ctx->batch_streams;
   // check every problem and size its workspace
   std::vector<size_t> ws_need(count), ctr_need(count);
   std::vector<double> cost(count);
@@ -927,10 +1042,18 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     ctr_need[p] = (size_t)w.lu_ctr + 16;
     cost[p] = (double)q.A->m * q.A->n * (2.0 * q.its + 2.0) + 1e6;
   }
-  const int ns = std::min(kSlots, count);
+  // problems the persistent launch takes: dense float32, m, n <= 8192, l <= 64
+  std::vector<int> pers, rest;
+  for (int p = 0; p < count; ++p) {
+    const rpca_problem& q = problems[p];
+    const int l = q.l > 0 ? q.l : q.k + 2;
+    const bool ok = ctx->batch_mode == 0 && !is_sparse(q.A) && q.A->dtype == RPCA_F32 &&
+                    l <= kPersMaxL && q.A->m <= kPersMaxDim && q.A->n <= kPersMaxDim;
+    (ok ? pers : rest).push_back(p);
+  }
+  const int ns = std::min(kSlots, (int)rest.size());
   // largest problems first, each to the least loaded stream
-  std::vector<int> order(count), slot_of(count);
-  for (int p = 0; p < count; ++p) order[p] = p;
+  std::vector<int> order(rest), slot_of(count);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   std::vector<double> load(ns, 0.0);
   std::vector<size_t> ws_max(ns, 0), ctr_max(ns, 0);
@@ -944,6 +1067,12 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_OK(hipStreamIsCapturing(ctx->stream, &cap));
   const bool capturing = cap != hipStreamCaptureStatusNone;
+  // the persistent launch's table and working memory (allocated outside capture only)
+  ctx_s_pers_plan plan;
+  if (!pers.empty()) {
+    rpca_status s = pers_prepare(ctx, problems, pers, capturing, plan);
+    if (s != RPCA_OK) return s;
+  }
   if ((int)ctx->slots.size() < ns && capturing)
     return fail(ctx, RPCA_ERR_UNSUPPORTED, "run the batch once before capturing it");
   if (!ctx->fork) HIP_OK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
@@ -990,6 +1119,15 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
   // fork: every stream starts after the work already on the context stream
   HIP_OK(hipEventRecord(ctx->fork, ctx->stream));
   for (int b = 0; b < ns; ++b) HIP_OK(hipStreamWaitEvent(ctx->slots[b].stream, ctx->fork, 0));
+  // the persistent launch runs on the context stream beside them
+  if (!pers.empty()) {
+    launch_pers_table(ctx->stream, plan.table.data(), (int)plan.table.size(), ctx->pers_tab);
+    launch_fill_zero(ctx->stream, reinterpret_cast<float*>(ctx->pers_counter), 4);
+    launch_persistent(ctx->stream, ctx->pers_tab, (int)pers.size(), ctx->pers_counter,
+                      ctx->pers_ws, plan.maxdim, plan.grid);
+    HIP_OK(hipGetLastError());
+    ctx->stats.calls += pers.size();
+  }
   // issue each problem on its stream with that stream's workspace
   const hipStream_t st0 = ctx->stream;
   char* const ws0 = ctx->ws;
@@ -997,7 +1135,8 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
   unsigned* const ctr0 = ctx->counters;
   const size_t ctrn0 = ctx->counters_n;
   rpca_status res = RPCA_OK;
-  for (int p = 0; p < count && res == RPCA_OK; ++p) {
+  for (size_t r = 0; r < rest.size() && res == RPCA_OK; ++r) {
+    const int p = rest[r];
     const rpca_problem& q = problems[p];
     BatchSlot& sl = ctx->slots[slot_of[p]];
     ctx->stream = sl.stream;
@@ -1186,6 +1325,14 @@ rpca_status rpca_tune_load(rpca_ctx ctx, const char* path) {
     return fail(ctx, RPCA_ERR_INVALID_ARG,
                 std::string("tune: malformed line ") + std::to_string(lineno) + " of " + path);
   for (const auto& kv : add) ctx->tune[kv.first] = kv.second;
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_batch_streams(rpca_ctx ctx, int32_t streams) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (streams < 1 || streams > 64)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "batch streams must be in [1, 64]");
+  ctx->batch_streams = streams;
   return RPCA_OK;
 }
 

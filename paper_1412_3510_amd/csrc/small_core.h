@@ -1,0 +1,281 @@
+// Single-workgroup float64 building blocks shared by the small-matrix kernels
+// and the persistent batched solver: Newton-refined reciprocal and square
+// root, the register-blocked Cholesky factorization, and the one-sided Jacobi
+// SVD.
+#pragma once
+#include "common.h"
+
+namespace rpca {
+
+// state[] layout (int):
+//   0  the current orthonormalization shifted a Cholesky factorization
+//   1  extra passes 3 and 4 are needed
+//   2  dependent columns were replaced by random ones
+//   3  Nystrom shift retries
+//   4  Nystrom: no positive definite shifted B2 found
+//   5  non-finite values met
+//   8..11  bit mask of dependent columns (128 bits)
+static constexpr double kTauRel = 1e-10;   // relative Cholesky pivot that marks dependence
+static constexpr double kShiftRel = 1e-8;  // relative diagonal shift when dependence is met
+static constexpr double kJunkNorm2 = 1e-2; // squared column norm after a shifted pass
+
+// Cholesky G + shift = R^T R (R upper) of the leading l x l block by one
+// workgroup of NTH threads (1024 unless given).  Thread (g, c) -- g = tid / LP, c = tid % LP --
+// keeps the entries (i, c), i = g + RG q (RG = NTH / LP row groups), in
+// registers.  Step j: every thread reads the current row u = G[j][.] from a
+// double-buffered LDS row (published by its owners at the end of step j - 1)
+// and the pivot d = u[j]; row j of R, u[c] / sqrt(d), goes to the LDS factor
+// Rs (float32, row-major stride LP); the trailing entries are updated,
+// G[i][c] -= u[i] u[c] / d for j < i <= c; the owners of row j + 1 publish it;
+// one barrier.  1/sqrt(d) is v_rsq_f64 refined by two Newton steps, which
+// keeps division and square root off the step's critical path.  Nothing in
+// the loop touches global memory, so the barrier waits for LDS only.
+// Returns false at the first pivot d <= tau * diag[j] (or not finite): all
+// threads read the same d, so all agree.
+static constexpr int kCholThreads = 1024;  // default workgroup size of chol_par
+
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
+template <int LP, int NTH = kCholThreads>
+__device__ bool chol_par(const double* __restrict__ G, bool sym, int l, double srel, double sabs,
+                         const double* diag, double tau, float* Rs, double* ubuf) {
+  constexpr int RG = NTH / LP;  // row groups
+  constexpr int RPT = LP / RG;           // rows per thread
+  const int tid = threadIdx.x, g = tid / LP, c = tid % LP;
+  double v[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = g + RG * q;
+    double x = 0.0;
+    if (i < l && c < l) x = sym ? 0.5 * (G[i * LP + c] + G[c * LP + i]) : G[i * LP + c];
+    if (i == c && c < l) x += srel * diag[c] + sabs;
+    v[q] = x;
+  }
+  if (g == 0) ubuf[c] = v[0];  // row 0
+  __syncthreads();
+  for (int j = 0; j < l; ++j) {
+    const double* u = ubuf + (j & 1) * LP;
+    const double d = u[j];
+    if (!(d > tau * diag[j]) || !(d > 0.0) || !(d < 1e300)) return false;
+    const double uc = u[c];
+    const double y = rsqrt_nr(d);
+    const double f = uc * (y * y);
+    if (g == 0) Rs[j * LP + c] = (c < l && c >= j) ? (float)((c == j) ? d * y : uc * y) : 0.f;
+    double nxt = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = g + RG * q;
+      if (i > j && i <= c && c < l) v[q] -= u[i] * f;
+      if (i == j + 1) nxt = v[q];
+    }
+    if (g == (j + 1) % RG) ubuf[((j + 1) & 1) * LP + c] = (c > j && c < l) ? nxt : 0.0;
+    __syncthreads();
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of M (or M^T), l <= LP, in float64.
+// Columns are stored contiguously in LDS (Mc[j*CS + i] = column j, row i,
+// CS = LP + 2 so columns of different pairs fall in different banks).
+// Column pairs follow the round-robin (circle) ordering, lp2/2 disjoint
+// pairs per round; each pair is handled by G = 16 lanes (one row block of
+// RPT = LP/G consecutive rows each), whose partial inner products are
+// combined with DPP lane permutations.  With M Wacc = Xn diag(s):
+//   s    -- column norms, sorted descending
+//   Wacc -- accumulated rotations (orthogonal), columns in the same order
+//   Xn   -- normalized columns of M Wacc (zero where s = 0)
+// For M = R (B^T = Q2 R) the left singular vectors of B are Wacc and the
+// right ones Q2 Xn; for M = R^T (F = QF R) the left ones of F are QF Wacc.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  // ctrl_sel: 0 = quad_perm [1,0,3,2], 1 = quad_perm [2,3,0,1], 2 = row_half_mirror
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  int lo2, hi2;
+  if (ctrl_sel == 0) {
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+  } else if (ctrl_sel == 1) {
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+  } else if (ctrl_sel == 2) {
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+  } else {  // row_mirror
+    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+  }
+  return __hiloint2double(hi2, lo2);
+}
+
+// sum over the G (8 or 16) aligned lanes of a group (all G get the sum)
+template <int G>
+__device__ __forceinline__ double sum_group(double v) {
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  v += dpp_f64(v, 2);
+  if (G == 16) v += dpp_f64(v, 3);
+  return v;
+}
+
+// The workgroup runs jacobi_body with at least NT = G LP / 2 threads (extra
+// threads only join the barriers).  Mc and Vc hold LP * CS doubles each
+// (CS = LP + 2 in LDS; LP in global memory for GLOBAL), sig LP doubles, perm
+// LP ints; s_rot and s_big are two LDS ints.
+template <int LP, bool GLOBAL>
+constexpr int jacobi_cs() { return GLOBAL ? LP : LP + 2; }
+
+template <int LP, bool GLOBAL, int G>
+__device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l, int transpose,
+                                            double* __restrict__ s_out,
+                                            double* __restrict__ Wacc, double* __restrict__ Xn,
+                                            double* Mc, double* Vc, double* sig, int* perm,
+                                            int& s_rot, int& s_big) {
+  constexpr int CS = jacobi_cs<LP, GLOBAL>();
+  constexpr int RPT = LP / G;     // rows per lane
+  constexpr int NT = G * LP / 2;  // G lanes for each of the LP/2 pair slots
+  const int tid = threadIdx.x;
+  for (int e = tid; tid < NT && e < LP * LP; e += NT) {
+    const int j = e / LP, i = e % LP;
+    double v = 0.0;
+    if (i < l && j < l) v = transpose ? M[j * LP + i] : M[i * LP + j];
+    Mc[j * CS + i] = v;
+    Vc[j * CS + i] = (i == j) ? 1.0 : 0.0;
+  }
+  const int lp2 = l + (l & 1);
+  const int npairs = lp2 / 2;
+  const int k = tid / G, gl = tid % G;  // pair slot, lane in the group of G
+  const bool active = (k < npairs);
+  const int i0 = gl * RPT;  // this lane's first row
+  const double tol = 1e-13;
+  // cyclic Jacobi converges quadratically: a sweep that starts with every
+  // |cos of the pair angle| <= 1e-6 leaves them near 1e-12 or below, which
+  // puts the column norms (the singular values) within about 1e-16 relative
+  // and the accumulated rotations within about 1e-12 of the converged ones;
+  // the sweeps after it only confirm that, and are skipped
+  const double quiet = 1e-6;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    __syncthreads();
+    if (tid == 0) {
+      s_rot = 0;
+      s_big = 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < lp2 - 1; ++r) {
+      int p = 0, q = 0;
+      if (active) {
+        const int a = k, b = lp2 - 1 - k;
+        p = (a == 0) ? 0 : 1 + (a - 1 + r) % (lp2 - 1);
+        q = (b == 0) ? 0 : 1 + (b - 1 + r) % (lp2 - 1);
+      }
+      const bool go = active && p < l && q < l;
+      double mp[RPT], mq[RPT];
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (go) {
+#pragma unroll
+        for (int u = 0; u < RPT; u += 2) {
+          const double2 x = *reinterpret_cast<const double2*>(Mc + p * CS + i0 + u);
+          const double2 y = *reinterpret_cast<const double2*>(Mc + q * CS + i0 + u);
+          mp[u] = x.x; mp[u + 1] = x.y;
+          mq[u] = y.x; mq[u + 1] = y.y;
+        }
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          al += mp[u] * mp[u];
+          be += mq[u] * mq[u];
+          ga += mp[u] * mq[u];
+        }
+      }
+      al = sum_group<G>(al);
+      be = sum_group<G>(be);
+      ga = sum_group<G>(ga);
+      if (go && al > 0.0 && be > 0.0 && ga * ga > (quiet * quiet) * (al * be) && gl == 0)
+        s_big = 1;
+      if (go && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
+        // Rutishauser's rotation, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+        // with zeta = (be - al) / (2 ga), evaluated as
+        // t = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (one
+        // reciprocal fewer on the critical path); reciprocals and square
+        // roots from the hardware approximations refined by Newton steps
+        // (rcp_nr, rsqrt_nr)
+        const double d = be - al;
+        double t;
+        if (fabs(d) < 1e150 && fabs(ga) < 1e150) {
+          const double h2 = fma(d, d, 4.0 * ga * ga);
+          const double h = h2 * rsqrt_nr(h2);
+          // sign(zeta) = sign(d) sign(ga), with d = +0 counting as positive
+          t = copysign(2.0 * fabs(ga) * rcp_nr(fabs(d) + h), d >= 0.0 ? ga : -ga);
+        } else {  // huge entries: the zeta form, which cannot overflow in h2
+          const double zeta = d * (0.5 * rcp_nr(ga));
+          t = (fabs(zeta) < 1e150)
+                  ? copysign(rcp_nr(fabs(zeta) + fma(zeta, zeta, 1.0) * rsqrt_nr(fma(zeta, zeta, 1.0))), zeta)
+                  : 0.5 * rcp_nr(zeta);
+        }
+        const double c = rsqrt_nr(fma(t, t, 1.0)), s = c * t;
+#pragma unroll
+        for (int u = 0; u < RPT; u += 2) {
+          *reinterpret_cast<double2*>(Mc + p * CS + i0 + u) =
+              make_double2(c * mp[u] - s * mq[u], c * mp[u + 1] - s * mq[u + 1]);
+          *reinterpret_cast<double2*>(Mc + q * CS + i0 + u) =
+              make_double2(s * mp[u] + c * mq[u], s * mp[u + 1] + c * mq[u + 1]);
+          const double2 vp = *reinterpret_cast<const double2*>(Vc + p * CS + i0 + u);
+          const double2 vq = *reinterpret_cast<const double2*>(Vc + q * CS + i0 + u);
+          *reinterpret_cast<double2*>(Vc + p * CS + i0 + u) =
+              make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
+          *reinterpret_cast<double2*>(Vc + q * CS + i0 + u) =
+              make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
+        }
+        if (gl == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    if (s_rot == 0 || s_big == 0) break;
+  }
+  __syncthreads();
+  if (tid < LP) {
+    double s = 0.0;
+    if (tid < l)
+      for (int i = 0; i < l; ++i) s += Mc[tid * CS + i] * Mc[tid * CS + i];
+    sig[tid] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid < l) {
+    int rank = 0;
+    for (int i = 0; i < l; ++i)
+      if (sig[i] > sig[tid] || (sig[i] == sig[tid] && i < tid)) ++rank;
+    perm[rank] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; tid < NT && e < LP * LP; e += NT) {
+    const int i = e / LP, rr = e % LP;  // output row i, column rr
+    double w = 0.0, x = 0.0;
+    if (i < l && rr < l) {
+      const int j = perm[rr];
+      w = Vc[j * CS + i];
+      x = (sig[j] > 0.0) ? Mc[j * CS + i] / sig[j] : 0.0;
+    }
+    Wacc[e] = w;
+    Xn[e] = x;
+  }
+  if (tid < LP) s_out[tid] = (tid < l) ? sig[perm[tid]] : 0.0;
+}
+
+}  // namespace rpca

@@ -1,12 +1,13 @@
 """Batched solves (rpca_svd_batched) on the GPU.
 
-  * every problem of a mixed batch (dense of uneven shapes, centered or not,
-    symmetric PSD, sparse) gives bit for bit what the single call gives: the
-    same kernels run on the same inputs, only on other streams;
+  * in streams mode, every problem of a mixed batch (dense of uneven shapes,
+    centered or not, symmetric PSD, sparse) gives bit for bit what the single
+    call gives: the same kernels run on the same inputs, only on other streams;
   * sampled problems match the FP64 oracle (singular values within 1e-4);
   * the batch captured into a HIP graph (through torch.cuda.graph) and replayed
     several times, with unrelated eager work and synchronizations between the
-    replays, reproduces the eager outputs exactly on every replay.
+    replays, reproduces the eager outputs exactly on every replay (the dense
+    problems go to the persistent launch, the sparse one to a stream).
 """
 
 import numpy as np
@@ -63,8 +64,13 @@ def _single(ctx, pr):
 
 
 def test_batched_equals_single_calls(ctx, gpu_lib):
+    # streams mode: the single-problem kernels, so bit-identical results
     probs, host = _batch(gpu_lib)
-    outs = ctx.svd_batched(probs, sync=True)
+    ctx.set_batch_mode(1)
+    try:
+        outs = ctx.svd_batched(probs, sync=True)
+    finally:
+        ctx.set_batch_mode(0)
     for pr, got in zip(probs, outs):
         want = _single(ctx, pr)
         for g, w in zip(got, want):
