@@ -91,9 +91,10 @@ struct PLds {
       int rot, big;
     } jac;
     struct {
-      unsigned long long key[2][NWAVE];
+      float key[2][NWAVE];
+      int kidx[2][NWAVE];
       float row[2][NWAVE][PB];
-      float U12[PB][64];
+      float U12[PB][64] __attribute__((aligned(16)));
       int piv[64];
     } lu;
     struct {
@@ -105,6 +106,7 @@ struct PLds {
     unsigned long long kred[NWAVE * 64];
     float W[64 * 64];
   } u;
+  float at[NWAVE][32 * 68] __attribute__((aligned(16)));  // A-pass row tiles (pitch 68)
   double ubuf[2 * 64];
   double diag[64];
   double zero[64];
@@ -158,17 +160,6 @@ __device__ __forceinline__ void split8(const float (&a)[8], bf16x8& hi, bf16x8& 
     hi[j] = h;
     lo[j] = l;
   }
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, o, 64);
-    const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), o, 64);
-    const unsigned long long w = ((unsigned long long)hi << 32) | lo;
-    v = (w > v) ? w : v;
-  }
-  return v;
 }
 
 // |v| in the high word (larger wins), the complement of the index in the low
@@ -239,14 +230,23 @@ __device__ __attribute__((noinline)) void p_pack(const float* src_, int rows, in
   __syncthreads();
 }
 
-// stage chunk ch (4 steps) of the packed operand into ring buffer buf
+// Chunk ch (4 steps) of the packed operand: loaded into registers one chunk
+// ahead, written to ring buffer buf after the current chunk's products.
 template <int LP>
-__device__ __forceinline__ void stage_chunk(const GAS __bf16* Pk, int ch, int buf) {
-  PLds& S = g_S;
-  constexpr int CH = 4 * (LP / 32) * 2 * 64;  // uint4 per chunk
-  const GAS u32x4* src = reinterpret_cast<const GAS u32x4*>(Pk) + (int64_t)ch * CH;
-  for (int e = threadIdx.x; e < CH; e += NT) S.u.xs[buf][e] = src[e];
-}
+struct Stage {
+  static constexpr int CH = 4 * (LP / 32) * 2 * 64;  // 16-byte pieces per chunk
+  static constexpr int PER = CH / NT;                 // per thread (1 or 2)
+  u32x4 v[PER];
+  __device__ __forceinline__ void load(const GAS __bf16* Pk, int ch) {
+    const GAS u32x4* src = reinterpret_cast<const GAS u32x4*>(Pk) + (int64_t)ch * CH;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) v[i] = src[threadIdx.x + NT * i];
+  }
+  __device__ __forceinline__ void store(int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) g_S.u.xs[buf][threadIdx.x + NT * i] = v[i];
+  }
+};
 
 // ---- Y (m x LP) = A X, X packed (n side, >= ceil(n/64)*4 steps) -----------
 template <int LP>
@@ -262,51 +262,66 @@ __device__ __attribute__((noinline)) void p_ax(const float* __restrict__ A_, int
   constexpr int NB = LP / 32;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c = lane & 31, g = lane >> 5;
   const int nchunk = (n + 63) / 64;
-  const bool vec = ((lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  constexpr int AP = 68;  // pitch of the per-wave LDS tile (floats)
+  float* tile = S.at[wave];
   for (int r0 = 0; r0 < m; r0 += 32 * NWAVE) {
     const int rbase = r0 + 32 * wave;
     const bool live = rbase < m;
-    const int row = rbase + c;
-    const bool rok = row < m;
-    const GAS float* arow = A + (int64_t)(rok ? row : 0) * lda;
     f32x16 acc[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
-    float a[4][8];
+    // A arrives row by row with the lanes along k (each load is one 256-byte
+    // segment of a row), one chunk ahead, and is turned into the MFMA layout
+    // through the wave's LDS tile; rows past m and columns past n read the
+    // last row or column and are zeroed on the way into the tile
+    float v[32];
     auto load_a = [&](int ch) {
+      const int col = min(64 * ch + lane, n - 1);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k0 = 64 * ch + 16 * s + 8 * g;
-        if (vec && k0 + 8 <= n) {
-          const f32x4 v0 = *reinterpret_cast<const GAS f32x4*>(arow + k0);
-          const f32x4 v1 = *reinterpret_cast<const GAS f32x4*>(arow + k0 + 4);
-          a[s][0] = v0.x; a[s][1] = v0.y; a[s][2] = v0.z; a[s][3] = v0.w;
-          a[s][4] = v1.x; a[s][5] = v1.y; a[s][6] = v1.z; a[s][7] = v1.w;
-        } else {  // the tail (or an unaligned A): clamped loads, zero past n
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float v = arow[min(k0 + j, n - 1)];
-            a[s][j] = (k0 + j < n) ? v : 0.f;
-          }
-        }
-        if (!rok)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) a[s][j] = 0.f;
+      for (int r = 0; r < 32; ++r) {
+        const int rr = min(rbase + r, m - 1);
+        v[r] = A[(int64_t)rr * lda + col];
       }
     };
-    stage_chunk<LP>(Xp, 0, 0);
-    if (live) load_a(0);
+    auto put_a = [&](int ch) {
+      if (64 * ch + 64 <= n && rbase + 32 <= m) {  // an interior chunk: no masking
+#pragma unroll
+        for (int r = 0; r < 32; ++r) tile[r * AP + lane] = v[r];
+      } else {
+        const bool colok = 64 * ch + lane < n;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) tile[r * AP + lane] = (colok && rbase + r < m) ? v[r] : 0.f;
+      }
+    };
+    Stage<LP> stg;
+    stg.load(Xp, 0);
+    stg.store(0);
+    if (nchunk > 1) stg.load(Xp, 1);
+    if (live) {
+      load_a(0);
+      put_a(0);
+      if (nchunk > 1) load_a(1);
+    }
     __syncthreads();
     for (int ch = 0; ch < nchunk; ++ch) {
       const int buf = ch & 1;
-      if (ch + 1 < nchunk) stage_chunk<LP>(Xp, ch + 1, buf ^ 1);
       if (live) {
         bf16x8 ah[4], al[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) split8(a[s], ah[s], al[s]);
-        if (ch + 1 < nchunk) load_a(ch + 1);
+        for (int s = 0; s < 4; ++s) {
+          float a8[8];
+          const f32x4 t0 = *reinterpret_cast<const f32x4*>(tile + c * AP + 16 * s + 8 * g);
+          const f32x4 t1 = *reinterpret_cast<const f32x4*>(tile + c * AP + 16 * s + 8 * g + 4);
+          a8[0] = t0.x; a8[1] = t0.y; a8[2] = t0.z; a8[3] = t0.w;
+          a8[4] = t1.x; a8[5] = t1.y; a8[6] = t1.z; a8[7] = t1.w;
+          split8(a8, ah[s], al[s]);
+        }
+        if (ch + 1 < nchunk) {  // the next chunk into the tile (after this one's reads), and one more ahead
+          put_a(ch + 1);
+          if (ch + 2 < nchunk) load_a(ch + 2);
+        }
         const bf16x8* xs = reinterpret_cast<const bf16x8*>(S.u.xs[buf]);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -316,6 +331,10 @@ __device__ __attribute__((noinline)) void p_ax(const float* __restrict__ A_, int
             const bf16x8 xl = xs[((s * NB + cb) * 2 + 1) * 64 + lane];
             acc[cb] = mfma3s(ah[s], al[s], xh, xl, acc[cb]);
           }
+      }
+      if (ch + 1 < nchunk) {  // chunk ch + 1 into the other buffer, chunk ch + 2 into registers
+        stg.store(buf ^ 1);
+        if (ch + 2 < nchunk) stg.load(Xp, ch + 2);
       }
       __syncthreads();
     }
@@ -357,26 +376,42 @@ __device__ __attribute__((noinline)) void p_atx(const float* __restrict__ A_, in
     for (int i = 0; i < NB; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+    // raw loads (clamped rows) one chunk ahead, masked when split
     float a[4][8];
     auto load_a = [&](int ch) {
+      if (64 * ch + 64 <= m) {  // every row of the chunk exists: offsets from one base
+        const GAS float* p0 = acol + (int64_t)(64 * ch + 8 * g) * lda;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k0 = 64 * ch + 16 * s + 8 * g;
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {  // clamped row, zero past m
-          const float v = acol[(int64_t)min(k0 + j, m - 1) * lda];
-          a[s][j] = (cok && k0 + j < m) ? v : 0.f;
-        }
+          for (int j = 0; j < 8; ++j) a[s][j] = p0[(int64_t)(16 * s + j) * lda];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            a[s][j] = acol[(int64_t)min(64 * ch + 16 * s + 8 * g + j, m - 1) * lda];
       }
     };
-    stage_chunk<LP>(Qp, 0, 0);
+    auto mask_a = [&](int ch) {
+      if (64 * ch + 64 <= m && cbase + 32 <= n) return;  // an interior chunk
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (!(cok && 64 * ch + 16 * s + 8 * g + j < m)) a[s][j] = 0.f;
+    };
+    Stage<LP> stg;
+    stg.load(Qp, 0);
+    stg.store(0);
+    if (nchunk > 1) stg.load(Qp, 1);
     if (live) load_a(0);
     __syncthreads();
     for (int ch = 0; ch < nchunk; ++ch) {
       const int buf = ch & 1;
-      if (ch + 1 < nchunk) stage_chunk<LP>(Qp, ch + 1, buf ^ 1);
       if (live) {
         bf16x8 ah[4], al[4];
+        mask_a(ch);
 #pragma unroll
         for (int s = 0; s < 4; ++s) split8(a[s], ah[s], al[s]);
         if (ch + 1 < nchunk) load_a(ch + 1);
@@ -389,6 +424,10 @@ __device__ __attribute__((noinline)) void p_atx(const float* __restrict__ A_, in
             const bf16x8 xl = xs[((s * NB + cb) * 2 + 1) * 64 + lane];
             acc[cb] = mfma3s(ah[s], al[s], xh, xl, acc[cb]);
           }
+      }
+      if (ch + 1 < nchunk) {  // chunk ch + 1 into the other buffer, chunk ch + 2 into registers
+        stg.store(buf ^ 1);
+        if (ch + 2 < nchunk) stg.load(Qp, ch + 2);
       }
       __syncthreads();
     }
@@ -416,7 +455,14 @@ __device__ __attribute__((noinline)) void p_colmean(const float* X_, int rows, i
   const int tid = threadIdx.x, c = tid % LP, gi = tid / LP;
   double s = 0.0;
   if (c < l)
-    for (int r = gi; r < rows; r += NG) s += (double)X[(int64_t)r * LP + c];
+    for (int r0 = gi; r0 < rows; r0 += 8 * NG) {  // eight loads in flight
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = X[(int64_t)min(r0 + j * NG, rows - 1) * LP + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (r0 + j * NG < rows) s += (double)v[j];
+    }
   S.u.red[gi * LP + c] = s;
   __syncthreads();
   if (tid < LP) {
@@ -453,6 +499,7 @@ __device__ __attribute__((noinline)) void p_lu(float* Y_, int rows, int l) {
   for (int c0 = 0; c0 < l; c0 += PB) {
     const int pw = min(PB, l - c0);
     const unsigned done0 = done;
+    // the panel of this thread's remaining rows (others read as zero)
     float pan[RPT][PB];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -466,41 +513,52 @@ __device__ __attribute__((noinline)) void p_lu(float* Y_, int rows, int l) {
     for (int jj = 0; jj < PB; ++jj) {
       if (jj < pw) {
         const int j = c0 + jj;
-        unsigned long long best = 0ull;
+        // this thread's candidate: largest |entry| of column j over its
+        // remaining rows (rows ascend with r, so ties keep the smaller row)
+        float best = -1.f;
+        int bi = 0x7fffffff;
         float bv[PB];
 #pragma unroll
         for (int q = 0; q < PB; ++q) bv[q] = 0.f;
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
+        for (int r = 0; r < RPT; ++r) {  // selects only: no branch per row
           const int i = tid + NT * r;
-          if (i < rows && !((done >> r) & 1u)) {
-            const unsigned long long key = abs_key(pan[r][jj], i);
-            if (key > best) {
-              best = key;
+          float a = fabsf(pan[r][jj]);
+          a = (a == a) ? a : 3.0e38f;  // a NaN entry is still a candidate (never none)
+          const bool take = (i < rows) && !((done >> r) & 1u) && (a > best);
+          best = take ? a : best;
+          bi = take ? i : bi;
 #pragma unroll
-              for (int q = 0; q < PB; ++q) bv[q] = pan[r][q];
-            }
-          }
+          for (int q = 0; q < PB; ++q) bv[q] = take ? pan[r][q] : bv[q];
         }
-        const unsigned long long wbest = wave_max_u64(best);
-        if (best == wbest && best != 0ull) {
-          S.u.lu.key[ph][wave] = best;
+        // the wave's (DPP), then the workgroup's: larger |entry|, ties to the smaller row
+        float wk = best;
+        int wi = bi;
+        wave_argmax_fast(wk, wi);
+        if (bi == wi && best == wk && best >= 0.f) {
+          S.u.lu.key[ph][wave] = wk;
+          S.u.lu.kidx[ph][wave] = wi;
 #pragma unroll
           for (int q = 0; q < PB; ++q) S.u.lu.row[ph][wave][q] = bv[q];
         }
-        if (lane == 0 && wbest == 0ull) S.u.lu.key[ph][wave] = 0ull;
+        if (lane == 0 && !(wk >= 0.f)) {
+          S.u.lu.key[ph][wave] = -1.f;
+          S.u.lu.kidx[ph][wave] = 0x7fffffff;
+        }
         __syncthreads();
-        unsigned long long kb = 0ull;
-        int wb = 0;
+        float kb = -1.f;
+        int p = 0x7fffffff, wb = 0;
 #pragma unroll
         for (int w = 0; w < NWAVE; ++w) {
-          const unsigned long long k = S.u.lu.key[ph][w];
-          if (k > kb) {
+          const float k = S.u.lu.key[ph][w];
+          const int ki = S.u.lu.kidx[ph][w];
+          if (k > kb || (k == kb && ki < p)) {
             kb = k;
+            p = ki;
             wb = w;
           }
         }
-        const int p = (int)(~(unsigned)kb);
+        p = min(max(p, 0), rows - 1);  // always a valid row (j < l <= rows leaves one)
         float pr[PB];
 #pragma unroll
         for (int q = 0; q < PB; ++q) pr[q] = S.u.lu.row[ph][wb][q];
@@ -511,14 +569,13 @@ __device__ __attribute__((noinline)) void p_lu(float* Y_, int rows, int l) {
         for (int r = 0; r < RPT; ++r)
           if (tid + NT * r == p) done |= 1u << r;
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
+        for (int r = 0; r < RPT; ++r) {  // selects only: no branch per row
           const int i = tid + NT * r;
-          if (i < rows && !((done >> r) & 1u)) {
-            const float f = pan[r][jj] * rp;
-            pan[r][jj] = f;
+          const bool upd = (i < rows) && !((done >> r) & 1u);
+          const float f = pan[r][jj] * rp;
+          pan[r][jj] = upd ? f : pan[r][jj];
 #pragma unroll
-            for (int q = jj + 1; q < PB; ++q) pan[r][q] = fmaf(-f, pr[q], pan[r][q]);
-          }
+          for (int q = jj + 1; q < PB; ++q) pan[r][q] = upd ? fmaf(-f, pr[q], pan[r][q]) : pan[r][q];
         }
         ph ^= 1;
       }
@@ -536,35 +593,59 @@ __device__ __attribute__((noinline)) void p_lu(float* Y_, int rows, int l) {
     const int cs = c0 + pw;  // first trailing column
     if (cs < l) {
       // U12: the pivot rows' trailing entries after this panel's eliminations
-      if (tid < l - cs) {
-        const int col = cs + tid;
+      // (zero outside the trailing columns, so the update below can run over
+      // whole rows)
+      if (tid < LP) {
+        const int col = tid;
+        const bool trail = col >= cs && col < l;
         float u[PB];
 #pragma unroll
         for (int t = 0; t < PB; ++t) {
-          if (t < pw) {
+          u[t] = 0.f;
+          if (t < pw && trail) {
             const int pt = S.u.lu.piv[c0 + t];
             float v = Y[(int64_t)pt * LP + col];
 #pragma unroll
             for (int s2 = 0; s2 < t; ++s2) v = fmaf(-Y[(int64_t)pt * LP + c0 + s2], u[s2], v);
             u[t] = v;
             Y[(int64_t)pt * LP + col] = v;
-            S.u.lu.U12[t][col] = v;
           }
+          S.u.lu.U12[t][col] = u[t];
         }
       }
       __syncthreads();
+      // the remaining rows: one vector load and store of the whole row each
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int i = tid + NT * r;
         if (i < rows && !((done >> r) & 1u)) {
+          asm volatile("" ::: "memory");  // read U12 from LDS per row (no hoisting)
           auto yr = Y + (int64_t)i * LP;
-          for (int col = cs; col < l; ++col) {
-            float v = yr[col];
+          float mlt[PB];
 #pragma unroll
-            for (int t = 0; t < PB; ++t)
-              if (t < pw) v = fmaf(-pan[r][t], S.u.lu.U12[t][col], v);
-            yr[col] = v;
+          for (int t = 0; t < PB; ++t) mlt[t] = pan[r][t];
+          float x[LP];
+#pragma unroll
+          for (int c = 0; c < LP; c += 4) {
+            const f32x4 v = *reinterpret_cast<const GAS f32x4*>(yr + c);
+            x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
           }
+#pragma unroll
+          for (int c = 0; c < LP; c += 4) {
+            f32x4 uu[PB];
+#pragma unroll
+            for (int t = 0; t < PB; ++t) uu[t] = *reinterpret_cast<const f32x4*>(&S.u.lu.U12[t][c]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              float v = x[c + e];
+#pragma unroll
+              for (int t = 0; t < PB; ++t) v = fmaf(-mlt[t], uu[t][e], v);
+              x[c + e] = v;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < LP; c += 4)
+            *reinterpret_cast<GAS f32x4*>(yr + c) = f32x4{x[c], x[c + 1], x[c + 2], x[c + 3]};
         }
       }
     }
@@ -604,14 +685,32 @@ __device__ __attribute__((noinline)) void p_gram(const float* X_, const float* X
   for (int u = 0; u < T; ++u)
 #pragma unroll
     for (int v = 0; v < T; ++v) acc[u][v] = 0.0;
+  // slices of SL rows, two per step (one per group of 256 threads); the next
+  // step's values are loaded into registers while the current one is used
+  constexpr int PER = SL * LP / 256;
+  float pa[PER], pb[PER];
+  auto load = [&](int rs) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = t + 256 * q, rr = e / LP, c = e % LP, r = rs + rr;
+      const int rc = min(r, rows - 1);
+      const float va = X[(int64_t)rc * LP + c];
+      pa[q] = (r < rows) ? va : 0.f;
+      if (!same) {
+        const float vb = X2[(int64_t)rc * LP + c];
+        pb[q] = (r < rows) ? vb : 0.f;
+      }
+    }
+  };
+  load(grp * SL);
   for (int r0 = 0; r0 < rows; r0 += 2 * SL) {
-    const int rs = r0 + grp * SL;
-    for (int e = t; e < SL * LP; e += 256) {
-      const int rr = e / LP, c = e % LP, r = rs + rr;
-      sa[e] = (r < rows) ? (double)X[(int64_t)r * LP + c] : 0.0;
-      if (!same) sb[e] = (r < rows) ? (double)X2[(int64_t)r * LP + c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      sa[t + 256 * q] = (double)pa[q];
+      if (!same) sb[t + 256 * q] = (double)pb[q];
     }
     __syncthreads();
+    if (r0 + 2 * SL < rows) load(r0 + 2 * SL + grp * SL);
     for (int rr = 0; rr < SL; ++rr) {
       double a[T], b[T];
 #pragma unroll
@@ -847,9 +946,16 @@ __device__ __attribute__((noinline)) void p_sign(float* U_, int64_t ldu, int m, 
   const int tid = threadIdx.x, q = tid & 63, gi = tid >> 6;
   unsigned long long best = 0ull;
   if (q < k)
-    for (int r = gi; r < m; r += NWAVE) {
-      const unsigned long long key = abs_key(U[(int64_t)r * ldu + q], r);
-      best = key > best ? key : best;
+    for (int r0 = gi; r0 < m; r0 += 8 * NWAVE) {  // eight loads in flight
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = U[(int64_t)min(r0 + j * NWAVE, m - 1) * ldu + q];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = r0 + j * NWAVE;
+        const unsigned long long key = (r < m) ? abs_key(v[j], r) : 0ull;
+        best = key > best ? key : best;
+      }
     }
   S.u.kred[gi * 64 + q] = best;
   __syncthreads();
@@ -880,11 +986,17 @@ __device__ __attribute__((noinline)) double p_fro2(const float* X_, int rows, in
   auto X = as_global(uni(X_));
   PLds& S = g_S;
   double s = 0.0;
-  for (int e = threadIdx.x; e < rows * LP; e += NT)
-    if ((e % LP) < l) {
-      const double v = X[e];
-      s += v * v;
+  const int total = rows * LP;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * NT) {  // eight loads in flight
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = X[min(e0 + j * NT, total - 1)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + j * NT;
+      if (e < total && (e % LP) < l) s += (double)v[j] * (double)v[j];
     }
+  }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) S.u.red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -901,14 +1013,14 @@ __device__ __attribute__((noinline)) double p_chol_nystrom(const double* G_, int
                                  int max_retries) {
   l = uni(l);
   max_retries = uni(max_retries);
-  auto G = as_global(uni(G_));
+  const double* G = uni(G_);
   PLds& S = g_S;
   double nu = n_sqrt_u * sqrt(fro2);
   if (!(nu > 0.0)) nu = 1e-300;
   bool ok = false;
   for (int retry = 0; retry <= max_retries; ++retry) {
     __syncthreads();
-    ok = chol_par<LP, NT>(G_, true, l, 0.0, nu, S.zero, 0.0, S.u.tri.R, S.ubuf);
+    ok = chol_par<LP, NT>(G, true, l, 0.0, nu, S.zero, 0.0, S.u.tri.R, S.ubuf);
     if (ok) break;
     if (retry < max_retries) nu *= 10.0;
   }
@@ -937,7 +1049,6 @@ __device__ __attribute__((noinline)) void jacobi_wg(const double* G, int l, int 
 
 template <int LP>
 __device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b) {
-  PLds& S = g_S;
   const float* A = p.A;
   const int m = p.m, n = p.n, l = p.l;
   const bool center = p.center != 0;
@@ -1014,18 +1125,24 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
   p_sign(p.U, p.ldu, n, p.k, nullptr, 0, 0);
 }
 
+// The next problem index for the workgroup (the LDS block is only touched from
+// non-inlined routines: LDS used both by a kernel and by the functions it
+// calls would be allocated twice).
+__device__ __attribute__((noinline)) int next_problem(int* counter) {
+  PLds& S = g_S;
+  if (threadIdx.x < 64) S.zero[threadIdx.x] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) S.idx = atomicAdd(counter, 1);
+  __syncthreads();
+  return S.idx;
+}
+
 __global__ void __launch_bounds__(NT) persistent_kernel(const PersProblem* __restrict__ probs,
                                                         int count, int* counter, float* ws,
                                                         int64_t slot_floats, int64_t R) {
-  __shared__ PLds S;
-  const int tid = threadIdx.x;
-  if (tid < 64) S.zero[tid] = 0.0;
   Buf b = carve(ws + (int64_t)blockIdx.x * slot_floats, R);
   for (;;) {
-    __syncthreads();
-    if (tid == 0) S.idx = atomicAdd(counter, 1);
-    __syncthreads();
-    const int idx = S.idx;
+    const int idx = next_problem(counter);
     if (idx >= count) break;
     const PersProblem p = probs[idx];
     if (p.l <= 32) {
