@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--precision-steps", type=int, default=10)
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 512-problem batched workload report")
+    p.add_argument("--batched-only", action="store_true",
+                   help="run only the 512-problem batched workload (for profiling it) and print "
+                        "its report")
     p.add_argument("--no-tune", action="store_true",
                    help="skip the autotuner (built-in tile configurations)")
     p.add_argument("--no-sparse", action="store_true",
@@ -234,8 +237,9 @@ def sparse_workload(ctx, steps, renorm):
 
 
 def batched_workload(ctx, steps):
-    """512 small problems (256 dense, 256 PSD) in one rpca_svd_batched call,
-    eager and replayed from a captured graph: problems/s and err / sigma_{k+1}."""
+    """512 small problems (256 dense, 256 PSD) in one rpca_svd_batched call:
+    the persistent launch, eager and replayed from a captured graph, and the
+    same batch on streams for comparison; problems/s and err / sigma_{k+1}."""
     import torch
     from synth import dense
     t0 = time.perf_counter()
@@ -251,21 +255,11 @@ def batched_workload(ctx, steps):
             probs.append(dict(A=A, k=q["k"], l=q["l"], its=q["its"], seed=q["seed"], kind="psd"))
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
-    # the autotuner: one problem of each shape class (log2 m, log2 n, padded l)
-    t1 = time.perf_counter()
-    classes = {}
-    for pr in probs:
-        m_, n_ = pr["A"].shape
-        key = ((m_ - 1).bit_length(), (n_ - 1).bit_length(), 32 if pr["l"] <= 32 else 64)
-        classes.setdefault(key, pr)
-    for pr in classes.values():
-        ctx.tune(pr["A"], pr["l"], reps=2)
-    tune_s = time.perf_counter() - t1
     s = torch.cuda.Stream()
     ctx.set_stream(s)
     try:
         with torch.cuda.stream(s):
-            outs = ctx.svd_batched(probs)   # sizes the per-stream workspaces
+            outs = ctx.svd_batched(probs)   # sizes the persistent working memory
             s.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -286,7 +280,18 @@ def batched_workload(ctx, steps):
             e1.record(s)
             s.synchronize()
             ms_graph = e0.elapsed_time(e1) / steps
+            # the same batch on streams (single-problem kernels)
+            ctx.set_batch_mode(1)
+            ctx.svd_batched(probs)
+            s.synchronize()
+            e0.record(s)
+            for _ in range(steps):
+                ctx.svd_batched(probs)
+            e1.record(s)
+            s.synchronize()
+            ms_streams = e0.elapsed_time(e1) / steps
     finally:
+        ctx.set_batch_mode(0)
         ctx.set_stream(torch.cuda.current_stream())
     ratios = []
     for q, pr, o in zip(params, probs, gouts):
@@ -301,8 +306,9 @@ def batched_workload(ctx, steps):
     return {"workload": "512 problems: 256 dense (m~logU[256,8192], n~logU[64,2048], "
                         "sigma_j=j^-1.5) + 256 PSD Nystrom (n~logU[128,4096], lambda_j=e^-j/10); "
                         "k~U{5..40}, l=k+5, its=2",
+            "mode": "persistent launch (one workgroup per problem)",
             "ms_per_batch_eager": round(ms_eager, 3), "ms_per_batch_graph": round(ms_graph, 3),
-            "autotuned_classes": len(classes), "autotune_s": round(tune_s, 1),
+            "ms_per_batch_streams": round(ms_streams, 3),
             "problems_per_s": round(512 * 1e3 / ms_graph, 1),
             "err_over_sigma_k1": {"p50": round(float(np.median(r)), 4),
                                   "p99": round(float(np.quantile(r, 0.99)), 4),
@@ -325,6 +331,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.batched_only:
+        print(json.dumps(batched_workload(rp.Context(), args.steps)), flush=True)
+        return
     m, n, k, l, its = args.m, args.n, args.k, args.l, args.its
     sigma = dense.spectrum_tall(min(m, n))
     t0 = time.perf_counter()
