@@ -144,8 +144,15 @@ def _cholqr2_torch(G, chunk=16384):
     import torch
     for _ in range(2):
         R = torch.linalg.cholesky(G.T @ G, upper=True)
-        eye = torch.eye(R.shape[0], device=G.device, dtype=G.dtype)
-        Rinv = torch.linalg.solve_triangular(R, eye, upper=True)
+        if R.shape[0] > 4096:
+            # the device triangular solve's workspace allocation fails at
+            # this order; the r x r inverse is cheap on the host
+            Rh = R.cpu()
+            Rinv = torch.linalg.solve_triangular(Rh, torch.eye(R.shape[0], dtype=G.dtype),
+                                                 upper=True).to(G.device)
+        else:
+            eye = torch.eye(R.shape[0], device=G.device, dtype=G.dtype)
+            Rinv = torch.linalg.solve_triangular(R, eye, upper=True)
         for i in range(0, G.shape[0], chunk):
             G[i:i + chunk] = G[i:i + chunk] @ Rinv
     return G
