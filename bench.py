@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--precision-steps", type=int, default=10)
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 512-problem batched workload report")
+    p.add_argument("--precision-only", action="store_true",
+                   help="run only the precision-form configuration (200000x8000, k=100, l=120, "
+                        "its=3) and print its report")
     p.add_argument("--batched-only", action="store_true",
                    help="run only the 512-problem batched workload (for profiling it) and print "
                         "its report")
@@ -203,6 +206,51 @@ def precision_form(ctx, A, k, l, its, seed, sk1, ms_f32, err_f32, steps, renorm)
     return res
 
 
+def precision_form_full(ctx, steps, renorm):
+    """The precision form's own configuration: 200000 x 8000 (the same spectral
+    law, not centered), k = 100, l = 120, its = 3; float32, bfloat16 and E4M3
+    range finders (float32 Rayleigh-Ritz product in all three): solves/s,
+    pass rates, speedup over float32 and err / sigma_{k+1} (FP64 power
+    estimate on the device)."""
+    import torch
+    import paper_1412_3510_amd as rp
+    from synth import dense
+    m, n, k, l, its, seed = 200000, 8000, 100, 120, 3, 2003
+    sig = dense.spectrum_tall(n)
+    t0 = time.perf_counter()
+    A, _, _ = dense.dense_torch(m, n, sig, seed=1003, device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    sk1 = float(sig[k])
+    U = torch.empty(m, k, device="cuda", dtype=torch.float32)
+    S = torch.empty(k, device="cuda", dtype=torch.float64)
+    V = torch.empty(n, k, device="cuda", dtype=torch.float32)
+    res = {"workload": "dense %dx%d, sigma_j=1/j (j<=50) then 1e-3*exp(-(j-51)/200), not "
+                       "centered; k=%d l=%d its=%d" % (m, n, k, l, its),
+           "sigma_k_plus_1": sk1, "generation_s": round(gen_s, 1)}
+    mat = rp.dense(A)
+    ms32, st = time_solves(ctx, A, k, l, its, seed, (U, S, V), mat, steps, 2, renorm, center=False)
+    err = ctx.spectral_err(A, U, S, V, iters=20, seed=7, mat=mat)
+    res["f32"] = {"solves_per_s": round(1e3 / ms32, 3), "ms_per_step": round(ms32, 4),
+                  "err_over_sigma_k1": round(err / sk1, 5), "passes": pass_rates(st)}
+    for kind in ("bf16", "fp8"):
+        q, sc = ctx.quantize(A, kind)
+        mat = rp.dense(q, col_scale=sc, A_f32=A)
+        ms, st = time_solves(ctx, q, k, l, its, seed, (U, S, V), mat, steps, 2, renorm,
+                             center=False)
+        err = ctx.spectral_err(q, U, S, V, iters=20, seed=7, mat=mat)
+        res[kind] = {"solves_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 4),
+                     "speedup_vs_f32": round(ms32 / ms, 3),
+                     "err_over_sigma_k1": round(err / sk1, 5),
+                     "meets_1.1_bound": bool(err <= 1.1 * sk1),
+                     "passes_low_precision": pass_rates(st, "_lp"),
+                     "passes_f32_rayleigh_ritz": pass_rates(st)}
+        del q, sc, mat
+    del A, U, S, V
+    torch.cuda.empty_cache()
+    return res
+
+
 def sparse_workload(ctx, steps, renorm):
     """The 10^6 x 10^6 sparse workload (10 entries per row, k = 20, l = 30,
     its = 4): solves/s, compulsory GB/s per pass, err / sigma_{k+1}."""
@@ -334,6 +382,9 @@ def main():
     if args.batched_only:
         print(json.dumps(batched_workload(rp.Context(), args.steps)), flush=True)
         return
+    if args.precision_only:
+        print(json.dumps(precision_form_full(rp.Context(), args.steps, args.renorm)), flush=True)
+        return
     m, n, k, l, its = args.m, args.n, args.k, args.l, args.its
     sigma = dense.spectrum_tall(min(m, n))
     t0 = time.perf_counter()
@@ -435,7 +486,8 @@ def main():
         "err_over_sigma_k1": round(err_f32 / sk1, 5),
     }
     if prec is not None:
-        out["precision_form"] = prec
+        out["precision_form"] = precision_form_full(ctx, args.precision_steps, args.renorm)
+        out["precision_form_on_timed_workload"] = prec
     if not args.no_sparse:
         out["sparse"] = sparse_workload(ctx, args.precision_steps, args.renorm)
     if not args.no_batched:

@@ -672,7 +672,7 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
   apply_At(ctx, A, Ar, w, w.Y, w.Z, center);
   orth_renorm(ctx, w, w.Z, n, true, seed + 1);
-  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
+  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
   // U = Q W, V = Q2 X, S = top k
   launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu);
   launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv);
@@ -731,7 +731,7 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
   launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp);
   orth_renorm(ctx, w, w.Y2, n, true, seed + 1);
-  launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork);
+  launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
   launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu);
   launch_finish_values(st, w.sv, k, w.scal + 1, lambda);
   launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
@@ -866,7 +866,8 @@ rpca_status rpca_op_small_svd(rpca_ctx ctx, int l, const double* M, double* s, d
   HIP_OK(hipMemsetAsync(w.G, 0, (size_t)w.lp * w.lp * sizeof(double), st));
   HIP_OK(hipMemcpy2DAsync(w.G, w.lp * sizeof(double), M, l * sizeof(double), l * sizeof(double), l,
                           hipMemcpyDeviceToDevice, st));
-  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork);
+  // the accumulating form at every size: this entry promises orthogonality to rounding
+  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, nullptr);
   HIP_OK(hipMemcpyAsync(s, w.sv, l * sizeof(double), hipMemcpyDeviceToDevice, st));
   // M = Xn diag(s) Wacc^T: left vectors Xn, right vectors Wacc
   HIP_OK(hipMemcpy2DAsync(W, l * sizeof(double), w.Xn, w.lp * sizeof(double), l * sizeof(double), l,

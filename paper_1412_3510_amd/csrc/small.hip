@@ -146,29 +146,43 @@ void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const d
 }
 
 
-template <int LP, bool GLOBAL, int G>
+template <int LP, bool GLOBAL, int G, bool ACC>
 __global__ void __launch_bounds__(G * LP / 2) jacobi_kernel(const double* __restrict__ M, int l,
                                                      int transpose, double* __restrict__ s_out,
                                                      double* __restrict__ Wacc,
                                                      double* __restrict__ Xn,
-                                                     double* __restrict__ gwork) {
+                                                     double* __restrict__ gwork, int* flag,
+                                                     const int* __restrict__ skip_unless,
+                                                     int kneed) {
+  if (skip_unless && *skip_unless == 0) return;
   constexpr int CS = jacobi_cs<LP, GLOBAL>();
   __shared__ __attribute__((aligned(16))) double sM[GLOBAL ? 2 : LP * CS];
-  __shared__ __attribute__((aligned(16))) double sV[GLOBAL ? 2 : LP * CS];
+  __shared__ __attribute__((aligned(16))) double sV[(GLOBAL || !ACC) ? 2 : LP * CS];
   __shared__ double sig[LP];
   __shared__ int perm[LP];
   __shared__ int s_rot, s_big;
   double* Mc = GLOBAL ? gwork : sM;
   double* Vc = GLOBAL ? gwork + LP * CS : sV;
-  jacobi_body<LP, GLOBAL, G>(M, l, transpose, s_out, Wacc, Xn, Mc, Vc, sig, perm, s_rot, s_big);
+  jacobi_body<LP, GLOBAL, G, ACC>(M, l, transpose, s_out, Wacc, Xn, Mc, Vc, sig, perm, s_rot,
+                                  s_big, flag, kneed);
 }
 
 void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
-                       double* Wacc, double* Xn, double* work) {
+                       double* Wacc, double* Xn, double* work, int* flag, int kneed) {
   switch (lp) {
-    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false, 16>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
-    case 64: hipLaunchKernelGGL((jacobi_kernel<64, false, 16>), dim3(1), dim3(512), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
-    case 128: hipLaunchKernelGGL((jacobi_kernel<128, true, 16>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work); break;
+    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false, 16, true>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, nullptr, 0); break;
+    case 64: hipLaunchKernelGGL((jacobi_kernel<64, false, 16, true>), dim3(1), dim3(512), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, nullptr, 0); break;
+    case 128:
+      if (flag) {
+        // the columns alone fit in LDS: rotate them there, recover the
+        // rotations by a product, and run the accumulating form (in global
+        // memory) only when the flag says the product is not accurate enough
+        hipLaunchKernelGGL((jacobi_kernel<128, false, 16, false>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work, flag, nullptr, kneed);
+        hipLaunchKernelGGL((jacobi_kernel<128, true, 16, true>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, flag, 0);
+      } else {
+        hipLaunchKernelGGL((jacobi_kernel<128, true, 16, true>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, nullptr, 0);
+      }
+      break;
     default: break;
   }
 }

@@ -143,12 +143,25 @@ __device__ __forceinline__ double sum_group(double v) {
 template <int LP, bool GLOBAL>
 constexpr int jacobi_cs() { return GLOBAL ? LP : LP + 2; }
 
-template <int LP, bool GLOBAL, int G>
+// ACC = false: the rotations are not accumulated (Vc is not used).  With M0
+// the starting matrix and M0 = X diag(s) W^T, the rotations are then
+// recovered as W = M0^T X diag(s)^-1, column j from M0^T (M0 W)_j / s_j^2.
+// The rounding of that product grows like c eps (s_1 / s_j)^2, with c about
+// the square root of the rotations a column takes part in (~30: the rounding
+// they leave in M0 W), so it is used only when the kneed largest s_j are all
+// >= kJacobiRecover s_1, which keeps those columns of W within about 3e-7 of
+// orthonormal, below the rounding of the float32 factors they multiply (the
+// callers read only the first kneed columns of W); otherwise *flag is set to
+// 1 (0 when the outputs are good) and the caller runs the accumulating form.
+static constexpr double kJacobiRecover = 1e-4;
+
+template <int LP, bool GLOBAL, int G, bool ACC = true>
 __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l, int transpose,
                                             double* __restrict__ s_out,
                                             double* __restrict__ Wacc, double* __restrict__ Xn,
                                             double* Mc, double* Vc, double* sig, int* perm,
-                                            int& s_rot, int& s_big) {
+                                            int& s_rot, int& s_big, int* flag = nullptr,
+                                            int kneed = 0) {
   constexpr int CS = jacobi_cs<LP, GLOBAL>();
   constexpr int RPT = LP / G;     // rows per lane
   constexpr int NT = G * LP / 2;  // G lanes for each of the LP/2 pair slots
@@ -158,7 +171,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
     double v = 0.0;
     if (i < l && j < l) v = transpose ? M[j * LP + i] : M[i * LP + j];
     Mc[j * CS + i] = v;
-    Vc[j * CS + i] = (i == j) ? 1.0 : 0.0;
+    if constexpr (ACC) Vc[j * CS + i] = (i == j) ? 1.0 : 0.0;
   }
   const int lp2 = l + (l & 1);
   const int npairs = lp2 / 2;
@@ -236,12 +249,14 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
               make_double2(c * mp[u] - s * mq[u], c * mp[u + 1] - s * mq[u + 1]);
           *reinterpret_cast<double2*>(Mc + q * CS + i0 + u) =
               make_double2(s * mp[u] + c * mq[u], s * mp[u + 1] + c * mq[u + 1]);
-          const double2 vp = *reinterpret_cast<const double2*>(Vc + p * CS + i0 + u);
-          const double2 vq = *reinterpret_cast<const double2*>(Vc + q * CS + i0 + u);
-          *reinterpret_cast<double2*>(Vc + p * CS + i0 + u) =
-              make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
-          *reinterpret_cast<double2*>(Vc + q * CS + i0 + u) =
-              make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
+          if constexpr (ACC) {
+            const double2 vp = *reinterpret_cast<const double2*>(Vc + p * CS + i0 + u);
+            const double2 vq = *reinterpret_cast<const double2*>(Vc + q * CS + i0 + u);
+            *reinterpret_cast<double2*>(Vc + p * CS + i0 + u) =
+                make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
+            *reinterpret_cast<double2*>(Vc + q * CS + i0 + u) =
+                make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
+          }
         }
         if (gl == 0) s_rot = 1;
       }
@@ -264,12 +279,26 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
     perm[rank] = tid;
   }
   __syncthreads();
+  if constexpr (!ACC) {
+    if (tid == 0) {
+      const int kk = (kneed > 0 && kneed < l) ? kneed : l;
+      const double smax = sig[perm[0]], smin = sig[perm[kk - 1]];
+      *flag = (smin >= kJacobiRecover * smax && smax < 1e300) ? 0 : 1;
+    }
+  }
   for (int e = tid; tid < NT && e < LP * LP; e += NT) {
     const int i = e / LP, rr = e % LP;  // output row i, column rr
     double w = 0.0, x = 0.0;
     if (i < l && rr < l) {
       const int j = perm[rr];
-      w = Vc[j * CS + i];
+      if constexpr (ACC) {
+        w = Vc[j * CS + i];
+      } else {  // W[i][rr] = sum_t M0[t][i] (M0 W)[t][j] / s_j^2
+        double acc = 0.0;
+        for (int t = 0; t < l; ++t)
+          acc += (transpose ? M[i * LP + t] : M[t * LP + i]) * Mc[j * CS + t];
+        w = (sig[j] > 0.0) ? acc / (sig[j] * sig[j]) : 0.0;
+      }
       x = (sig[j] > 0.0) ? Mc[j * CS + i] / sig[j] : 0.0;
     }
     Wacc[e] = w;

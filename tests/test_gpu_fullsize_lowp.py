@@ -77,3 +77,5 @@ def test_fullsize_lowp(workload, kind):
         # E4M3's 2^-4 rounding moves the unconverged tail further (~3e-3)
         np.testing.assert_allclose(Sh[lead], S0[lead], rtol=1e-4)
         np.testing.assert_allclose(Sh[~lead], S0[~lead], rtol=5e-3)
+        assert _orth_err(U.cpu().numpy()) < 1e-4
+        assert _orth_err(V.cpu().numpy()) < 1e-4

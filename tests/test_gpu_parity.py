@@ -202,6 +202,18 @@ def test_svd_shapes(ctx, m, n, k, l, its):
     _check_svd(ctx, A, k, l, its, 7 + its, sk1=sig[k] if its > 0 else None, err_factor=1.2)
 
 
+def test_svd_l120_vectors(ctx):
+    # l = 120 (lp = 128): the small SVD rotates the columns in LDS and recovers
+    # the rotations as W = M^T X diag(s)^-2 (sigma_l / sigma_1 ~ 7e-4 here);
+    # the singular vectors must match the oracle's column by column
+    m, n, k, l = 3000, 600, 30, 120
+    sig = dense.spectrum_tall(n)
+    A = dense.dense(m, n, sig, seed=4321)
+    U, S, V, U0, S0, V0 = _check_svd(ctx, A, k, l, 2, 99, sk1=sig[k])
+    assert np.max(np.abs(U - U0)) < 1e-4
+    assert np.max(np.abs(V - V0)) < 1e-4
+
+
 @pytest.mark.parametrize("m,n,k,l,its", [(3000, 200, 20, 30, 2), (4000, 400, 50, 60, 3),
                                          (2000, 300, 90, 120, 2)])
 def test_svd_orth_renorm(ctx, m, n, k, l, its):
