@@ -158,10 +158,10 @@ void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const d
 // One-sided Jacobi SVD of M (l x l, float64 row-major ld lp) or of M^T:
 // s (descending), Wacc (accumulated rotations, columns sorted), Xn
 // (normalized columns of M Wacc, sorted).  ``work`` holds 2*lp*lp doubles.
-// ``flag`` (device int, nullable): for lp = 128 the LDS form without
-// accumulated rotations runs first and the global-memory form only when the
-// ``kneed`` largest singular values (the columns of Wacc the caller reads) are
-// too spread for its recovery of the rotations.
+// ``flag`` (device int, nullable): at lp = 128 the form without accumulated
+// rotations (columns in LDS) runs first and the accumulating form (global
+// memory) only when the ``kneed`` largest singular values (the columns of
+// Wacc the caller reads) are too spread for its recovery of the rotations.
 void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
                        double* Wacc, double* Xn, double* work, int* flag = nullptr,
                        int kneed = 0);

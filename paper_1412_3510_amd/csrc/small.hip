@@ -169,22 +169,24 @@ __global__ void __launch_bounds__(G * LP / 2) jacobi_kernel(const double* __rest
 
 void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
                        double* Wacc, double* Xn, double* work, int* flag, int kneed) {
+  // lp <= 64: the accumulating form in LDS (a round costs its barrier and
+  // reductions, not the rotation of W).  lp = 128, with a flag: rotate the
+  // columns alone (in LDS) and recover the rotations by a product; the
+  // accumulating form (global memory) runs after it only when the flag says
+  // the product is not accurate enough.  Without a flag: the accumulating form.
+#define JAC_GO(LP_, GL_, ACC_, NT_, FLAG_, SKIP_, KN_)                                           \
+  hipLaunchKernelGGL((jacobi_kernel<LP_, GL_, 16, ACC_>), dim3(1), dim3(NT_), 0, st, M, l,      \
+                     transpose, s, Wacc, Xn, work, FLAG_, SKIP_, KN_)
   switch (lp) {
-    case 32: hipLaunchKernelGGL((jacobi_kernel<32, false, 16, true>), dim3(1), dim3(256), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, nullptr, 0); break;
-    case 64: hipLaunchKernelGGL((jacobi_kernel<64, false, 16, true>), dim3(1), dim3(512), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, nullptr, 0); break;
+    case 32: JAC_GO(32, false, true, 256, nullptr, nullptr, 0); break;
+    case 64: JAC_GO(64, false, true, 512, nullptr, nullptr, 0); break;
     case 128:
-      if (flag) {
-        // the columns alone fit in LDS: rotate them there, recover the
-        // rotations by a product, and run the accumulating form (in global
-        // memory) only when the flag says the product is not accurate enough
-        hipLaunchKernelGGL((jacobi_kernel<128, false, 16, false>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work, flag, nullptr, kneed);
-        hipLaunchKernelGGL((jacobi_kernel<128, true, 16, true>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, flag, 0);
-      } else {
-        hipLaunchKernelGGL((jacobi_kernel<128, true, 16, true>), dim3(1), dim3(1024), 0, st, M, l, transpose, s, Wacc, Xn, work, nullptr, nullptr, 0);
-      }
+      if (flag) JAC_GO(128, false, false, 1024, flag, nullptr, kneed);
+      JAC_GO(128, true, true, 1024, nullptr, flag, 0);
       break;
     default: break;
   }
+#undef JAC_GO
 }
 
 // out[j] = s[j] (nu == nullptr) or max(s[j]^2 - nu, 0)
