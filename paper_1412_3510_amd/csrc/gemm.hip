@@ -463,17 +463,22 @@ bool dma_ok_shape(const void* A, int64_t lda, int64_t n) {
 struct PassChoice {
   int nw, S;
 };
+// 8 waves: a 256-row tile; the ring has 4 stages (40 KB each) for nb = 2 and
+// 3 (48 KB each) for nb = 4
+static int ring8(int nb) { return nb == 4 ? 3 : 4; }
+
 static PassChoice ax_choice(int nb, int64_t m, int num_cus, const TuneCfg* cfg) {
-  PassChoice c{(nb == 2 && m >= (int64_t)num_cus * 256) ? 8 : 4, 0};
-  if (cfg && cfg->ax_waves == 8 && nb == 2) c.nw = 8;
+  const bool can8 = (nb == 2 || nb == 4);
+  PassChoice c{(can8 && m >= (int64_t)num_cus * 256) ? 8 : 4, 0};
+  if (cfg && cfg->ax_waves == 8 && can8) c.nw = 8;
   if (cfg && cfg->ax_waves == 4) c.nw = 4;
-  c.S = c.nw == 8 ? 4 : ((cfg && cfg->ax_ring >= 2 && cfg->ax_ring <= 4) ? cfg->ax_ring : ring_depth(nb));
+  c.S = c.nw == 8 ? ring8(nb) : ((cfg && cfg->ax_ring >= 2 && cfg->ax_ring <= 4) ? cfg->ax_ring : ring_depth(nb));
   return c;
 }
 
 int ax_candidates(int nb, int (*out)[2]) {
   int k = 0;
-  if (nb == 2) { out[k][0] = 8; out[k][1] = 4; ++k; }
+  if (nb == 2 || nb == 4) { out[k][0] = 8; out[k][1] = ring8(nb); ++k; }
   for (int S = 2; S <= 4; ++S) { out[k][0] = 4; out[k][1] = S; ++k; }
   return k;
 }
@@ -493,6 +498,12 @@ static void launch_ax_dma(hipStream_t st, const float* A, int64_t lda, int64_t m
   if constexpr (NB == 2) {
     if (c.nw == 8) {
       hipLaunchKernelGGL((ax_dma_kernel<2, 4, 8>), grid, dim3(512), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per);
+      return;
+    }
+  }
+  if constexpr (NB == 4) {
+    if (c.nw == 8) {
+      hipLaunchKernelGGL((ax_dma_kernel<4, 3, 8>), grid, dim3(512), 0, st, A, lda, m, n, Xp, Y, ldy, rows_per);
       return;
     }
   }
@@ -630,10 +641,13 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
 static PassChoice atx_choice(int64_t m, int64_t n, int nb, int num_cus, int dtype,
                              const TuneCfg* cfg) {
   if (dtype != 0) return PassChoice{4, 0};
+  // built in: 8 waves for nb = 2 only (at nb = 4 the 4-wave form measured
+  // faster: 1.42 against 1.55 ms at 200000 x 8000); the autotuner may pick 8
+  const bool can8 = (nb == 2 || nb == 4);
   PassChoice c{(nb == 2 && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4, 0};
-  if (cfg && cfg->atx_waves == 8 && nb == 2) c.nw = 8;
+  if (cfg && cfg->atx_waves == 8 && can8) c.nw = 8;
   if (cfg && cfg->atx_waves == 4) c.nw = 4;
-  c.S = c.nw == 8 ? 4 : ((cfg && cfg->atx_ring >= 2 && cfg->atx_ring <= 4) ? cfg->atx_ring : ring_depth(nb));
+  c.S = c.nw == 8 ? ring8(nb) : ((cfg && cfg->atx_ring >= 2 && cfg->atx_ring <= 4) ? cfg->atx_ring : ring_depth(nb));
   return c;
 }
 
@@ -684,6 +698,12 @@ void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m
     const int S = plan.ring;
     if (plan.waves == 8 && nb == 2) {
       hipLaunchKernelGGL((atx_dma_kernel<2, 4, 8>), dim3((unsigned)(plan.gtiles * plan.nsplit)),
+                         dim3(512), 0, st, Af, lda, m, n, Xp, P, plan.gtiles, plan.ntiles,
+                         plan.rows_per);
+      return;
+    }
+    if (plan.waves == 8 && nb == 4) {
+      hipLaunchKernelGGL((atx_dma_kernel<4, 3, 8>), dim3((unsigned)(plan.gtiles * plan.nsplit)),
                          dim3(512), 0, st, Af, lda, m, n, Xp, P, plan.gtiles, plan.ntiles,
                          plan.rows_per);
       return;

@@ -24,7 +24,7 @@ void launch_pack(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int 
 // class; the launchers fall back to the built-in choice for values they do
 // not support.
 struct TuneCfg {
-  int ax_waves = 0;   // waves per workgroup of Y = A X: 4 or 8 (8: lp = 64 only)
+  int ax_waves = 0;   // waves per workgroup of Y = A X: 4 or 8 (8: lp = 64 or 128)
   int ax_ring = 0;    // LDS ring stages of the 4-wave form: 2, 3 or 4
   int atx_waves = 0;  // the same for A^T X
   int atx_ring = 0;

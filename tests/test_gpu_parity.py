@@ -48,10 +48,13 @@ def _product_bound(A, X, K):
     return (2.0 ** -15 + K * 2.0 ** -24) * (np.abs(A) @ np.abs(X)) + 1e-30
 
 
-# n % 4 == 0 takes the LDS-DMA kernels, other n the register-staged ones
+# n % 4 == 0 takes the LDS-DMA kernels, other n the register-staged ones;
+# m >= 65536 takes the 8-wave form of A X (at l = 60 and 120) and, with
+# n >= 1024 at l = 60, of A^T X
 @pytest.mark.parametrize("m,n,l", [(1000, 500, 12), (777, 333, 60), (300, 1000, 120),
                                    (65, 97, 33), (4099, 257, 64), (4099, 260, 64),
-                                   (131, 1028, 120), (70001, 400, 60), (33, 36, 30)])
+                                   (131, 1028, 120), (70001, 400, 60), (33, 36, 30),
+                                   (70001, 1028, 120)])
 def test_ax_and_atx(ctx, m, n, l):
     rng = np.random.default_rng(m + n + l)
     A = rng.standard_normal((m, n)).astype(np.float32)

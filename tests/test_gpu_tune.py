@@ -82,6 +82,30 @@ def test_forced_configuration_matches_oracle(ctx, case, tmp_path, cfg):
         ctx.tune_clear()
 
 
+def test_forced_8wave_lp128_matches_oracle(ctx, tmp_path):
+    # l = 120 (lp = 128): the 8-wave forms of both passes (3-stage rings),
+    # forced for this shape class, against the oracle
+    m, n, k, l = 20000, 1024, 100, 120
+    sig = dense.spectrum_tall(n)
+    A = dense.dense(m, n, sig, seed=778)
+    U0, S0, V0 = rsvd.rsvd(A, k, l, ITS, philox.omega(SEED, n, l))
+    err0 = spectral.spectral_err_exact(A, U0, S0, V0)
+    path = tmp_path / "tune128.txt"
+    path.write_text("# forced\n%s 8 3 8 3 512\n" % _class(m, n, 128))
+    ctx.tune_clear()
+    ctx.tune_load(str(path))
+    try:
+        U, S, V = ctx.svd(torch.from_numpy(A).cuda(), k, l, ITS, SEED, sync=True)
+    finally:
+        ctx.tune_clear()
+    U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+    np.testing.assert_allclose(S, S0, rtol=1e-4)
+    assert np.linalg.norm(U.T.astype(np.float64) @ U - np.eye(k), 2) < 1e-5
+    assert np.linalg.norm(V.T.astype(np.float64) @ V - np.eye(k), 2) < 1e-5
+    err = spectral.spectral_err_exact(A, U, S, V)
+    assert err <= err0 * (1 + 1e-3) + 1e-6 * S0[0]
+
+
 def test_tune_table_round_trip(ctx, case, tmp_path, gpu_lib):
     _, dA, _, _ = case
     ctx.tune_clear()
