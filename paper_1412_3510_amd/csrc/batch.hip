@@ -14,17 +14,20 @@
 //   * Omega from Philox4x32-10 (the same values as the single solve);
 //   * Y = A X and Z = A^T X on MFMA (v_mfma_f32_32x32x16_bf16, float32
 //     operands split into bfloat16 pairs, three products per tile): each wave
-//     owns 32 rows of the output tile (32 columns of A for A^T X) and loads
-//     its A values straight from memory; the packed small operand is staged
-//     through a two-buffer LDS ring shared by the 8 waves;
+//     owns 32 rows of the output tile (32 columns of A for A^T X).  For A X a
+//     wave reads its rows as whole 256-byte segments (lanes along k) and turns
+//     them into the MFMA layout through its own LDS tile; for A^T X each half
+//     wave reads 32 consecutive entries of a row.  A is read one chunk ahead
+//     of the products, and the packed small operand is staged through a
+//     two-buffer LDS ring shared by the 8 waves;
 //   * centering (Section 2: A_c = A - 1 mu): Y minus its column means after
 //     A X; the m-side operand minus its column means before A^T X;
 //   * LU renormalization (Section 5): a right-looking partial-pivoting LU,
 //     blocked by 4 columns, without physical row swaps.  Every thread keeps
 //     16 rows of the 4-column panel in registers; a step finds the pivot with
-//     one wave reduction and one barrier (the winning lane of each wave
+//     one DPP wave argmax and one barrier (the winning lane of each wave
 //     publishes its row), scales the multipliers and updates the panel; the
-//     trailing columns get one rank-4 update per panel.  The result P L
+//     trailing columns get one rank-4 update per panel (whole rows).  The result P L
 //     (rows in the original order) overwrites Y; a zero pivot leaves the
 //     unit vector of its pivot row as that column of L;
 //   * orthonormalization: Cholesky QR twice with a float64 Gram matrix (up to
@@ -1113,7 +1116,8 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
   const double fro2 = p_fro2<LP>(Q2, n, l);
   p_gram<LP>(Q, Q2, n, b.G);
   const double nu = p_chol_nystrom<LP>(b.G, l, fro2, sqrt((double)n) * 0x1p-24, 10);
-  // F = (B1 + nu Q) C^-1 (pseudo), F = QF R, R^T = ... (Jacobi on R^T)
+  // F = (B1 + nu Q) C^-1 (pseudo); F = QF R, and the Jacobi SVD of R^T gives
+  // F = QF W diag(s) X^T, so U = QF W
   p_trsm<LP>(Q2, n, l, Q, (float)nu);
   p_orth<LP>(Q2, n, l, true, b.T, b.G, p.seed + 1);
   jacobi_wg<LP>(b.G, l, 1, b);
