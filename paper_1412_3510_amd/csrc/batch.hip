@@ -23,8 +23,8 @@
 //   * centering (Section 2: A_c = A - 1 mu): Y minus its column means after
 //     A X; the m-side operand minus its column means before A^T X;
 //   * LU renormalization (Section 5): a right-looking partial-pivoting LU,
-//     blocked by 4 columns, without physical row swaps.  Every thread keeps
-//     16 rows of the 4-column panel in registers; a step finds the pivot with
+//     blocked by 8 columns, without physical row swaps.  Every thread keeps
+//     16 rows of the 8-column panel in registers; a step finds the pivot with
 //     one DPP wave argmax and one barrier (the winning lane of each wave
 //     publishes its row), scales the multipliers and updates the panel; the
 //     trailing columns get one rank-4 update per panel (whole rows).  The result P L
@@ -79,7 +79,7 @@ __device__ __forceinline__ T* uni(T* p) { return (T*)(uintptr_t)uni((int64_t)(ui
 constexpr int NT = 512;                  // threads per workgroup
 constexpr int NWAVE = NT / 64;           // waves per workgroup
 constexpr int RPT = kPersMaxDim / NT;    // rows per thread in the LU (16)
-constexpr int PB = 4;                    // LU panel width
+constexpr int PB = 8;                    // LU panel width
 
 // LDS of one workgroup.  The union holds the buffers of one step at a time.
 struct PLds {
