@@ -27,9 +27,9 @@
 //     16 rows of the 8-column panel in registers; a step finds the pivot with
 //     one DPP wave argmax and one barrier (the winning lane of each wave
 //     publishes its row), scales the multipliers and updates the panel; the
-//     trailing columns get one rank-4 update per panel (whole rows).  The result P L
-//     (rows in the original order) overwrites Y; a zero pivot leaves the
-//     unit vector of its pivot row as that column of L;
+//     trailing columns get one rank-8 update per panel (whole rows).  The
+//     result P L (rows in the original order) overwrites Y; a zero pivot
+//     leaves the unit vector of its pivot row as that column of L;
 //   * orthonormalization: Cholesky QR twice with a float64 Gram matrix (up to
 //     four passes with a shifted factorization and completion of dependent
 //     columns, exactly as in the multi-kernel path);
