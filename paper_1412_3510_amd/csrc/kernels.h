@@ -113,7 +113,7 @@ void launch_fro2_d(hipStream_t st, const float* X, int64_t ldx, int64_t rows, in
 // with the pivoted-LU convention for zero pivots (see tall.hip).
 void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int lp,
                  const float* Ut, const int* piv, const int* skip_flag, const float* nu,
-                 const float* addX, int64_t ldadd);
+                 const float* addX, int64_t ldadd, int num_cus);
 // Y (rows x k) = X (rows x lp) W (lp x k, float64, row-major ld ldw)
 void launch_small_gemm(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,
                        const double* W, int ldw, int k, float* Y, int64_t ldy);

@@ -168,8 +168,7 @@ struct Gepp {
     }
   }
 
-  // The NW steps of super-step B, then the next super-step.  Returns at the
-  // end or when no candidate row is left (the same for every wave).
+  // The NW steps of super-step B, then the next super-step, up to column l.
   template <int B>
   static __device__ __forceinline__ void steps(float (&a)[RPL][CPW], unsigned& cm,
                                                const Ctx& c) {
@@ -186,8 +185,10 @@ struct Gepp {
           const float4 v = src[s / 4];
           m[s] = v.x; m[s + 1] = v.y; m[s + 2] = v.z; m[s + 3] = v.w;
         }
+        // key 0: no candidate row is left; the step then eliminates nothing
+        // and records no pivot (no early exit, so the multiplier reads above
+        // are issued together with this one)
         const unsigned key = (unsigned)__builtin_amdgcn_readfirstlane((int)c.s_key[j & 1]);
-        if (key == 0u) return;
         const bool nz = (key & ~KMASK) >= TINY;
         const int lr = R - (int)(key & KMASK), ls = lr & 63, ss = lr >> 6;
         float u[CPW];
@@ -209,16 +210,22 @@ struct Gepp {
             if ((lm >> t) & 1u) c.sU[j * LP + c.w + NW * t] = u[t];
         }
         if (!nz) lm = 0u;
+        const int jn = j + 1;
+        const bool next = jn < c.l && c.w == (wp + 1) % NW;
+        // the wave that publishes column j + 1 is the critical path of the
+        // step: it takes issue priority over the other wave on its SIMD until
+        // it has published
+        if (next) __builtin_amdgcn_s_setprio(2);
         update<B>(a, m, u, lm);
         if constexpr (B + 1 < CPW) update<B + 1>(a, m, u, lm);
-        const int jn = j + 1;
-        if (jn < c.l && c.w == (wp + 1) % NW) {
+        if (next) {
           // column j + 1: slot B, or slot B + 1 when it starts the next super-step
           if (wp != NW - 1) {
             publish<B>(a, cm, c, jn);
           } else {
             if constexpr (B + 1 < CPW) publish<B + 1>(a, cm, c, jn);
           }
+          __builtin_amdgcn_s_setprio(0);
         }
         update_from<B + 2>(a, m, u, lm);
       }

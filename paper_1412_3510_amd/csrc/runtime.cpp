@@ -391,7 +391,8 @@ void run_atx(rpca_ctx ctx, const AView& A, const Work& w, const __bf16* Qp) {
 void lu_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
   const LuPlan plan = plan_lu(rows, w.lp, w.cfg.lu_rows);
   launch_lu_tree(ctx->stream, Y, w.lp, rows, w.l, plan, w.cand, ctx->counters, w.Ulu, w.piv);
-  launch_trsm(ctx->stream, Y, w.lp, rows, w.l, w.lp, w.Ulu, w.piv, nullptr, nullptr, nullptr, 0);
+  launch_trsm(ctx->stream, Y, w.lp, rows, w.l, w.lp, w.Ulu, w.piv, nullptr, nullptr, nullptr, 0,
+              ctx->num_cus);
 }
 
 // Y (rows x lp) <- Q with Y = Q R, Q orthonormal (Cholesky QR, float64 Gram,
@@ -407,7 +408,7 @@ void orth_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows, bool want_r, uin
     const int* skip = (pass >= 3) ? (w.state + 1) : nullptr;
     launch_gram(st, Y, w.lp, rows, w.lp, nullptr, 0, w.gpart, w.G, skip);
     launch_chol_qr_step(st, w.G, w.l, w.lp, pass, w.Rf, w.state);
-    launch_trsm(st, Y, w.lp, rows, w.l, w.lp, w.Rf, nullptr, skip, nullptr, nullptr, 0);
+    launch_trsm(st, Y, w.lp, rows, w.l, w.lp, w.Rf, nullptr, skip, nullptr, nullptr, 0, ctx->num_cus);
     if (pass == 2) launch_complete(st, Y, w.lp, rows, w.l, w.state, seed ^ 0x5bd1e995u);
   }
   if (want_r) launch_gram(st, Y, w.lp, rows, w.lp, w.Bk, w.lp, w.gpart, w.G, nullptr);
@@ -729,7 +730,7 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   launch_chol_nystrom(st, w.G, l, w.lp, w.scal, std::sqrt((double)n) * u, w.Rf, w.scal + 1,
                       w.nu_f, w.state, 10);
   // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
-  launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp);
+  launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp, ctx->num_cus);
   orth_renorm(ctx, w, w.Y2, n, true, seed + 1);
   launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
   launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu);

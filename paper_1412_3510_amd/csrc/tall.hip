@@ -350,15 +350,88 @@ __global__ void __launch_bounds__(256) trsm_kernel(float* __restrict__ X, int64_
     *reinterpret_cast<float4*>(dst + c) = make_float4(x[c], x[c + 1], x[c + 2], x[c + 3]);
 }
 
+// The same solve, right-looking: the results are bitwise those of
+// trsm_kernel. once x_i is final, row i of U updates the entries to
+// its right, so each x_j still accumulates x_i U[i][j] in increasing i.  Row
+// i of U is the same for every lane: the compiler reads it with scalar loads
+// (U is never written here) and the products take it as a scalar operand,
+// with no LDS traffic per product.  The loads' latency is hidden only with
+// several waves per SIMD, so launch_trsm takes this form for large row
+// counts; with U in LDS instead (trsm_kernel), every product reads LDS,
+// whose bandwidth bounds the large cases.
+// ------------------------------------------------------------------------
+template <int LP>
+__global__ void __launch_bounds__(256) trsm_rows_kernel(float* __restrict__ X, int64_t ldx,
+                                                        int64_t rows, int l,
+                                                        const float* __restrict__ Ut,
+                                                        const int* __restrict__ piv,
+                                                        const int* __restrict__ skip_flag,
+                                                        const float* __restrict__ nu,
+                                                        const float* __restrict__ addX,
+                                                        int64_t ldadd) {
+  if (skip_flag && *skip_flag == 0) return;
+  __shared__ float sd[LP];
+  __shared__ int sp[LP];
+  if (threadIdx.x < LP) {
+    const int j = threadIdx.x;
+    const float d = (j < l) ? Ut[j * LP + j] : 0.f;
+    sd[j] = (d != 0.f) ? 1.0f / d : 0.f;
+    sp[j] = (piv && j < l) ? piv[j] : -1;
+  }
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= rows) return;
+  float x[LP];
+  const float* src = X + row * ldx;
+#pragma unroll
+  for (int c = 0; c < LP; c += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src + c);
+    x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
+  }
+  if (addX) {
+    const float s = *nu;
+    const float* a = addX + row * ldadd;
+#pragma unroll
+    for (int c = 0; c < LP; c += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(a + c);
+      x[c] += s * v.x; x[c + 1] += s * v.y; x[c + 2] += s * v.z; x[c + 3] += s * v.w;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < LP; ++i) {
+    if (i < l) {
+      const float d = sd[i];
+      x[i] = (d != 0.f) ? x[i] * d : ((row == sp[i]) ? 1.f : 0.f);
+      // (columns at or beyond l are updated too, and zeroed when reached)
+      const float* ui = Ut + i * LP;
+#pragma unroll
+      for (int j = i + 1; j < LP; ++j) x[j] -= x[i] * ui[j];
+    } else {
+      x[i] = 0.f;
+    }
+  }
+  float* dst = X + row * ldx;
+#pragma unroll
+  for (int c = 0; c < LP; c += 4)
+    *reinterpret_cast<float4*>(dst + c) = make_float4(x[c], x[c + 1], x[c + 2], x[c + 3]);
+}
+
 void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int lp,
                  const float* Ut, const int* piv, const int* skip_flag, const float* nu,
-                 const float* addX, int64_t ldadd) {
+                 const float* addX, int64_t ldadd, int num_cus) {
   if (rows == 0) return;
   const dim3 grid((unsigned)ceil_div(rows, 256));
+  // lp = 128 with at least three waves per SIMD: U rows from scalar loads
+  const bool rows_form = lp == 128 && rows >= (int64_t)num_cus * 4 * 64 * 3;
   switch (lp) {
     case 32: hipLaunchKernelGGL(trsm_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
     case 64: hipLaunchKernelGGL(trsm_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
-    case 128: hipLaunchKernelGGL(trsm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
+    case 128:
+      if (rows_form)
+        hipLaunchKernelGGL(trsm_rows_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd);
+      else
+        hipLaunchKernelGGL(trsm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd);
+      break;
     default: break;
   }
 }

@@ -89,7 +89,9 @@ def test_centered_products(ctx):
 
 
 # ---------------------------------------------------------------- renormalization
-@pytest.mark.parametrize("rows,l", [(1000, 12), (5000, 60), (70000, 60), (3000, 120), (257, 33)])
+# 200000 x 120: the triangular solve takes its scalar-row form there
+@pytest.mark.parametrize("rows,l", [(1000, 12), (5000, 60), (70000, 60), (3000, 120), (257, 33),
+                                    (200000, 120)])
 def test_lu_renorm(ctx, rows, l):
     rng = np.random.default_rng(rows + l)
     Y = (rng.standard_normal((rows, l)) @ np.diag(np.logspace(0, -3, l))).astype(np.float32)
@@ -123,7 +125,7 @@ def test_lu_renorm_zero_pivots(ctx):
 
 
 @pytest.mark.parametrize("rows,l,cond", [(1000, 12, 1e2), (20000, 60, 1e4), (3000, 120, 1e3),
-                                         (5000, 40, 1e9)])
+                                         (5000, 40, 1e9), (200000, 120, 1e3)])
 def test_orth_renorm(ctx, rows, l, cond):
     rng = np.random.default_rng(int(cond) % 1000 + rows)
     Y = (rng.standard_normal((rows, l)) @ np.diag(np.logspace(0, -np.log10(cond), l))).astype(np.float32)
