@@ -51,28 +51,36 @@ struct LpCfg {
   static constexpr int ABYTES = 16384;
 };
 
-template <int NB, int E>
+// stage bytes: A (4 NW KB: 32 NW rows of 128 bytes in the ax kernel, RS rows
+// of 128 columns in the atx kernel, NW = 4) plus the KS x NB X fragments
+template <int NB, int E, int NW = 4>
 constexpr int lp_stage_bytes() {
-  return LpCfg<E>::ABYTES + LpCfg<E>::KS * NB * 1024;
+  return NW * 4096 + LpCfg<E>::KS * NB * 1024;
 }
 
 // ---------------- Y = A X --------------------------------------------------
-// Stage: KC columns of a 128-row tile (rows 8b..8b+7 per 1 KB DMA block b; the
-// 16-byte chunk c of row R sits at position c ^ ((R >> 1) & 7)) plus the
-// matching KS x NB high-part X fragments.
-template <int NB, int S, int E>
-__global__ void __launch_bounds__(256) ax_lp_kernel(const unsigned char* __restrict__ A,
-                                                    int64_t lda, int64_t m, int64_t n,
-                                                    const __bf16* __restrict__ Xp,
-                                                    float* __restrict__ Y, int64_t ldy,
-                                                    int64_t rows_per_wg) {
+// NW waves on a 32 NW-row tile.  Stage: KC columns of the tile (rows 8b..8b+7
+// per 1 KB DMA block b; the 16-byte chunk c of row R sits at position
+// c ^ ((R >> 1) & 7)) plus the matching KS x NB high-part X fragments.  The X
+// fragments of a stage serve every row of the tile, so the 256-row tile of
+// NW = 8 moves half the X bytes per byte of A of the 128-row one.  As in the
+// float32 kernel, a wave whose rows are all past the end of a short last
+// tile loads only its X fragments and skips its products.
+template <int NB, int S, int E, int NW>
+__global__ void __launch_bounds__(64 * NW) ax_lp_kernel(const unsigned char* __restrict__ A,
+                                                        int64_t lda, int64_t m, int64_t n,
+                                                        const __bf16* __restrict__ Xp,
+                                                        float* __restrict__ Y, int64_t ldy,
+                                                        int64_t rows_per_wg) {
   using C = LpCfg<E>;
-  constexpr int KC = C::KC, KS = C::KS, ABYTES = C::ABYTES;
+  constexpr int KC = C::KC, KS = C::KS;
+  constexpr int TR = 32 * NW;       // tile rows
+  constexpr int ABYTES = TR * 128;
   constexpr int XFR = KS * NB;  // X fragments per stage
-  constexpr int STAGE = lp_stage_bytes<NB, E>();
-  constexpr int XPW = XFR / 4;
+  constexpr int STAGE = lp_stage_bytes<NB, E, NW>();
+  constexpr int XPW = XFR / NW;
   constexpr int PER = 4 + XPW;
-  static_assert(XFR % 4 == 0 && (S - 1) * PER < 64, "stage shape");
+  static_assert(XPW * NW == XFR && (S - 1) * PER < 64, "stage shape");
   static_assert(S * STAGE <= 160 * 1024, "LDS ring");
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(256) ax_lp_kernel(const unsigned char* __restr
   const int lrow = lane >> 3;
   const int g = lane >> 5;
 
-  for (int64_t row0 = rbeg; row0 < rend; row0 += 128) {
+  for (int64_t row0 = rbeg; row0 < rend; row0 += TR) {
     const unsigned char* rowp[4];
     int cofs[4];  // element offset of this lane's chunk within the stage
 #pragma unroll
@@ -94,16 +102,19 @@ __global__ void __launch_bounds__(256) ax_lp_kernel(const unsigned char* __restr
       rowp[i] = A + grow * lda * E;
       cofs[i] = ((lane & 7) ^ ((R >> 1) & 7)) * (16 / E);
     }
+    const bool live = row0 + 32 * wave < rend;  // this wave has rows in the tile
 #define AXL_ISSUE(STG)                                                                    \
   do {                                                                                    \
     const int64_t stg_ = (STG);                                                           \
     char* slot_ = ring + (int)(stg_ % S) * STAGE;                                         \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
-      const int64_t col_ = stg_ * KC + cofs[i];                                           \
-      dma16(rowp[i] + (col_ < n ? col_ : 0) * E, slot_ + (4 * wave + i) * 1024);          \
+    if (live) {                                                                           \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                     \
+        const int64_t col_ = stg_ * KC + cofs[i];                                         \
+        dma16(rowp[i] + (col_ < n ? col_ : 0) * E, slot_ + (4 * wave + i) * 1024);        \
+      }                                                                                   \
     }                                                                                     \
     _Pragma("unroll") for (int i = 0; i < XPW; ++i) {                                     \
-      const int blk_ = wave + 4 * i;                                                      \
+      const int blk_ = wave + NW * i;                                                     \
       dma16(xg + ((stg_ * XFR + blk_) * 2) * 1024 + 16 * lane, slot_ + ABYTES + blk_ * 1024); \
     }                                                                                     \
   } while (0)
@@ -122,11 +133,15 @@ __global__ void __launch_bounds__(256) ax_lp_kernel(const unsigned char* __restr
     for (int64_t stg = 0; stg < nstage; ++stg) {
       if (stg + S - 1 < nstage) AXL_ISSUE(stg + S - 1);
       const int64_t last = min(nstage - 1, stg + S - 1);
-      wait_ahead<PER, S>((int)(last - stg));
+      // (both waits end in the workgroup barrier; a wave without rows
+      // still takes every barrier of the stage)
+      if (live) wait_ahead<PER, S>((int)(last - stg));
+      else wait_ahead<XPW, S>((int)(last - stg));
       const char* As = ring + (int)(stg % S) * STAGE;
       const char* Xs = As + ABYTES;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
+        if (!live) break;
         bf16x8 a;
         if (E == 2) {
           a = *reinterpret_cast<const bf16x8*>(As + R * 128 + 16 * ((2 * s + g) ^ sw));
@@ -275,9 +290,9 @@ __global__ void __launch_bounds__(256) atx_lp_kernel(const unsigned char* __rest
 // ---------------------------------------------------------------------------
 static int lp_elem_bytes(int dtype) { return dtype == 2 ? 1 : 2; }
 
-template <int NB, int E>
+template <int NB, int E, int NW = 4>
 constexpr int lp_ring() {
-  constexpr int st = lp_stage_bytes<NB, E>();
+  constexpr int st = lp_stage_bytes<NB, E, NW>();
   constexpr int s = (160 * 1024) / st;
   return s > 6 ? 6 : s;
 }
@@ -302,17 +317,33 @@ int lp_per_cu(int nb, int dtype) {
   return std::max(1, (160 * 1024) / (s * st));
 }
 
-template <int NB, int E>
-static void ax_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m, int64_t n,
-                     const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
-  constexpr int S = lp_ring<NB, E>();
-  const int per_cu = std::max(1, (160 * 1024) / (S * lp_stage_bytes<NB, E>()));
+template <int NB, int E, int NW>
+static void ax_lp_launch(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m,
+                         int64_t n, const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
+  constexpr int S = lp_ring<NB, E, NW>();
+  const int per_cu = std::max(1, (160 * 1024) / (S * lp_stage_bytes<NB, E, NW>()));
   int64_t G = (int64_t)num_cus * per_cu;
   G = std::min<int64_t>(G, ceil_div(m, 32));
   const int64_t rows_per = ceil_div(m, G);
   G = ceil_div(m, rows_per);
-  hipLaunchKernelGGL((ax_lp_kernel<NB, S, E>), dim3((unsigned)G), dim3(256), 0, st, A, lda, m, n,
-                     Xp, Y, ldy, rows_per);
+  hipLaunchKernelGGL((ax_lp_kernel<NB, S, E, NW>), dim3((unsigned)G), dim3(64 * NW), 0, st, A,
+                     lda, m, n, Xp, Y, ldy, rows_per);
+}
+
+// 8 waves (256-row tiles) when every CU gets a full tile, the X fragments of a
+// stage split evenly over 8 waves and the ring still holds three stages;
+// else 4 waves
+template <int NB, int E>
+static void ax_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m, int64_t n,
+                     const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
+  constexpr bool can8 = (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 3;
+  if constexpr (can8) {
+    if (m >= (int64_t)num_cus * 256) {
+      ax_lp_launch<NB, E, 8>(st, A, lda, m, n, Xp, Y, ldy, num_cus);
+      return;
+    }
+  }
+  ax_lp_launch<NB, E, 4>(st, A, lda, m, n, Xp, Y, ldy, num_cus);
 }
 
 void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
