@@ -640,7 +640,10 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
 // on wide, tall A, else 4; the low-precision kernels have one configuration.
 static PassChoice atx_choice(int64_t m, int64_t n, int nb, int num_cus, int dtype,
                              const TuneCfg* cfg) {
-  if (dtype != 0) return PassChoice{4, 0};
+  // low precision: 256-column tiles where the kernel has the form, on wide,
+  // tall A (its ring depth is fixed by the stage size)
+  if (dtype != 0)
+    return PassChoice{(lp_atx_can8(nb, dtype) && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4, 0};
   // built in: 8 waves for nb = 2 only (at nb = 4 the 4-wave form measured
   // faster: 1.42 against 1.55 ms at 200000 x 8000); the autotuner may pick 8
   const bool can8 = (nb == 2 || nb == 4);
@@ -661,8 +664,9 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype, const Tun
   const int rs = dtype == 0 ? 32 : lp_rows_per_stage(dtype);  // rows per stage
   const int64_t stages = ceil_div(m, rs);
   // workgroups resident per CU for the LDS ring of the DMA kernel
-  const int per_cu = dtype == 0 ? (p.waves == 8 ? 1 : std::max(1, (160 * 1024) / (p.ring * dma_stage_bytes(nb))))
-                                : lp_per_cu(nb, dtype);
+  const int per_cu = p.waves == 8 ? 1
+                     : dtype == 0 ? std::max(1, (160 * 1024) / (p.ring * dma_stage_bytes(nb)))
+                                  : lp_per_cu(nb, dtype);
   int64_t want = (int64_t)per_cu * num_cus / p.gtiles;
   if (want < 1) want = 1;
   int64_t maxs = stages / 4;

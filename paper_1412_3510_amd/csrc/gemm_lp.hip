@@ -172,34 +172,40 @@ __global__ void __launch_bounds__(64 * NW) ax_lp_kernel(const unsigned char* __r
 }
 
 // ---------------- partials of A^T X -----------------------------------------
-// Stage: RS rows of a 128-column tile (16 KB; DMA block b holds rows
-// (RS/16) b .. + RS/16 - 1, LPR lanes of 16 bytes per row; chunk c of row r
-// sits at c ^ (LPR/2 ((r >> 3) & 1))) plus the matching KS x NB fragments of
-// the packed m-side operand.
-template <int NB, int S, int E>
-__global__ void __launch_bounds__(256) atx_lp_kernel(const unsigned char* __restrict__ A,
-                                                     int64_t lda, int64_t m, int64_t n,
-                                                     const __bf16* __restrict__ Xp,
-                                                     float* __restrict__ P, int ntiles,
-                                                     int64_t rows_per) {
+// NW waves on a 32 NW-column tile (wave w: columns 32w..32w+31 of it).
+// Stage: RS rows of the tile (4 NW KB; DMA block b holds rows RB b ..
+// RB b + RB - 1, LPR lanes of 16 bytes per row; chunk c of row r sits at
+// c ^ (LPR/2 ((r >> 3) & 1))) plus the matching KS x NB fragments of the
+// packed m-side operand, which serve every column of the tile: the 256-column
+// tile of NW = 8 moves half their bytes per byte of A.  The workgroup index
+// gives (split, tile) over gtiles tiles per split; partials are laid out by
+// 32-column block, ntiles * 4 blocks per split (ntiles = ceil(n / 128)).
+template <int NB, int S, int E, int NW>
+__global__ void __launch_bounds__(64 * NW) atx_lp_kernel(const unsigned char* __restrict__ A,
+                                                         int64_t lda, int64_t m, int64_t n,
+                                                         const __bf16* __restrict__ Xp,
+                                                         float* __restrict__ P, int gtiles,
+                                                         int ntiles, int64_t rows_per) {
   using C = LpCfg<E>;
-  constexpr int RS = C::RS, KS = C::KS, ABYTES = C::ABYTES;
-  constexpr int ROWB = 128 * E;        // bytes per row of the 128-column tile
+  constexpr int RS = C::RS, KS = C::KS;
+  constexpr int TC = 32 * NW;          // tile columns
+  constexpr int ABYTES = NW * 4096;
+  constexpr int ROWB = TC * E;         // bytes per row of the tile
   constexpr int LPR = ROWB / 16;       // lanes per row in a DMA block
   constexpr int RB = 64 / LPR;         // rows per DMA block
   constexpr int SWZ = LPR / 2;
   constexpr int XFR = KS * NB;
-  constexpr int STAGE = lp_stage_bytes<NB, E>();
-  constexpr int XPW = XFR / 4;
+  constexpr int STAGE = lp_stage_bytes<NB, E, NW>();
+  constexpr int XPW = XFR / NW;
   constexpr int PER = 4 + XPW;
-  static_assert(RB * 16 == RS && XFR % 4 == 0 && (S - 1) * PER < 64, "stage shape");
+  static_assert(RB * 4 * NW == RS && XPW * NW == XFR && (S - 1) * PER < 64, "stage shape");
   static_assert(S * STAGE <= 160 * 1024, "LDS ring");
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int split = t / ntiles, tile = t % ntiles;
-  const int64_t col0 = (int64_t)tile * 128;
+  const int split = t / gtiles, tile = t % gtiles;
+  const int64_t col0 = (int64_t)tile * TC;
   const int64_t rbeg = (int64_t)split * rows_per;
   const int64_t rend = (rbeg + rows_per < m) ? rbeg + rows_per : m;
   const int64_t nstage = (rend > rbeg) ? ceil_div(rend - rbeg, RS) : 0;
@@ -224,7 +230,7 @@ __global__ void __launch_bounds__(256) atx_lp_kernel(const unsigned char* __rest
       dma16(A + (grow_ * lda + colc[i]) * E, slot_ + (4 * wave + i) * 1024);              \
     }                                                                                     \
     _Pragma("unroll") for (int i = 0; i < XPW; ++i) {                                     \
-      const int blk_ = wave + 4 * i;                                                      \
+      const int blk_ = wave + NW * i;                                                     \
       dma16(xg + ((stg_ * XFR + blk_) * 2) * 1024 + 16 * lane, slot_ + ABYTES + blk_ * 1024); \
     }                                                                                     \
   } while (0)
@@ -277,7 +283,9 @@ __global__ void __launch_bounds__(256) atx_lp_kernel(const unsigned char* __rest
     }
     barrier_mem();
   }
-  float* out = P + ((int64_t)(split * ntiles + tile) * 4 + wave) * NB * 1024;
+  const int blk32 = tile * NW + wave;  // 32-column block of this wave
+  if (blk32 >= ntiles * 4) return;      // columns past the partial layout (beyond n)
+  float* out = P + ((int64_t)split * ntiles * 4 + blk32) * NB * 1024;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
@@ -295,6 +303,18 @@ constexpr int lp_ring() {
   constexpr int st = lp_stage_bytes<NB, E, NW>();
   constexpr int s = (160 * 1024) / st;
   return s > 6 ? 6 : s;
+}
+
+// the 8-wave form of both low-precision kernels: the X fragments of a stage
+// split evenly over 8 waves and the ring still holds three stages
+template <int NB, int E>
+constexpr bool lp_can8() {
+  return (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 3;
+}
+
+bool lp_atx_can8(int nb, int dtype) {
+  if (dtype == 2) return nb == 1 ? lp_can8<1, 1>() : nb == 2 ? lp_can8<2, 1>() : lp_can8<4, 1>();
+  return nb == 1 ? lp_can8<1, 2>() : nb == 2 ? lp_can8<2, 2>() : lp_can8<4, 2>();
 }
 
 int lp_rows_per_stage(int dtype) { return dtype == 2 ? LpCfg<1>::RS : LpCfg<2>::RS; }
@@ -330,14 +350,12 @@ static void ax_lp_launch(hipStream_t st, const unsigned char* A, int64_t lda, in
                      lda, m, n, Xp, Y, ldy, rows_per);
 }
 
-// 8 waves (256-row tiles) when every CU gets a full tile, the X fragments of a
-// stage split evenly over 8 waves and the ring still holds three stages;
-// else 4 waves
+// 8 waves (256-row tiles) when the kernel has the form (lp_can8) and every CU
+// gets a full tile; else 4 waves
 template <int NB, int E>
 static void ax_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m, int64_t n,
                      const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
-  constexpr bool can8 = (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 3;
-  if constexpr (can8) {
+  if constexpr (lp_can8<NB, E>()) {
     if (m >= (int64_t)num_cus * 256) {
       ax_lp_launch<NB, E, 8>(st, A, lda, m, n, Xp, Y, ldy, num_cus);
       return;
@@ -369,10 +387,19 @@ void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t
 template <int NB, int E>
 static void atx_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m, int64_t n,
                       const __bf16* Xp, float* P, const AtxPlan& plan) {
+  if constexpr (lp_can8<NB, E>()) {
+    if (plan.waves == 8) {
+      constexpr int S = lp_ring<NB, E, 8>();
+      hipLaunchKernelGGL((atx_lp_kernel<NB, S, E, 8>), dim3((unsigned)(plan.gtiles * plan.nsplit)),
+                         dim3(512), 0, st, A, lda, m, n, Xp, P, plan.gtiles, plan.ntiles,
+                         plan.rows_per);
+      return;
+    }
+  }
   constexpr int S = lp_ring<NB, E>();
   const dim3 grid((unsigned)(plan.ntiles * plan.nsplit));
-  hipLaunchKernelGGL((atx_lp_kernel<NB, S, E>), grid, dim3(256), 0, st, A, lda, m, n, Xp, P,
-                     plan.ntiles, plan.rows_per);
+  hipLaunchKernelGGL((atx_lp_kernel<NB, S, E, 4>), grid, dim3(256), 0, st, A, lda, m, n, Xp, P,
+                     plan.ntiles, plan.ntiles, plan.rows_per);
 }
 
 void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,

@@ -44,7 +44,7 @@ bool dma_ok_shape(const void* A, int64_t lda, int64_t n);
 // Split-K partial products of A^T X (X packed on the m side).
 struct AtxPlan {
   int ntiles;        // ceil(n / 128): the partials hold 4 * ntiles 32-column blocks per split
-  int waves;         // waves per workgroup of the float32 DMA kernel (4 or 8)
+  int waves;         // waves per workgroup of the DMA kernel (4 or 8)
   int ring;          // its LDS ring stages
   int gtiles;        // column tiles of that kernel, ceil(n / (32 * waves))
   int nsplit;        // number of row splits
@@ -69,6 +69,9 @@ void launch_atx_reduce(hipStream_t st, const float* P, const AtxPlan& plan, int 
 bool lp_shape_ok(const void* A, int dtype, int64_t lda, int64_t n);
 int lp_rows_per_stage(int dtype);
 int lp_per_cu(int nb, int dtype);
+// whether the low-precision kernels have their 8-wave (256-row / 256-column
+// tile) form for this nb and dtype
+bool lp_atx_can8(int nb, int dtype);
 void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                   const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus);
 void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
