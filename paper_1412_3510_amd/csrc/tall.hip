@@ -302,9 +302,12 @@ __global__ void __launch_bounds__(256) trsm_kernel(float* __restrict__ X, int64_
   __shared__ __attribute__((aligned(16))) float sU[LP * LP];
   __shared__ float sd[LP];
   __shared__ int sp[LP];
+  // consecutive threads fill consecutive LDS words (the transposed writes of
+  // consecutive U entries would all hit one bank); U itself is small and read
+  // from L2
   for (int e = threadIdx.x; e < LP * LP; e += 256) {
-    const int i = e / LP, j = e % LP;
-    sU[j * LP + i] = Ut[e];
+    const int j = e / LP, i = e % LP;
+    sU[e] = Ut[i * LP + j];
   }
   if (threadIdx.x < LP) {
     const int j = threadIdx.x;
