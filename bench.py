@@ -370,8 +370,8 @@ def main():
         traffic_from_pmc(args)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1412_3510_amd as rp

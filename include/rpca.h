@@ -38,7 +38,7 @@ typedef struct rpca_ctx_s* rpca_ctx;
 typedef enum {
   RPCA_OK = 0,
   RPCA_ERR_INVALID_ARG = 1, /* bad sizes, null pointers, k > l, ...        */
-  RPCA_ERR_UNSUPPORTED = 2, /* a format/dtype/size this build does not do   */
+  RPCA_ERR_UNSUPPORTED = 2, /* a format/dtype/size the library lacks        */
   RPCA_ERR_NO_MEMORY = 3,   /* workspace allocation failed or over the limit */
   RPCA_ERR_HIP = 4,         /* a HIP runtime call failed                     */
   RPCA_ERR_NOT_PSD = 5,     /* Nystrom: shifted B2 never positive definite   */
