@@ -305,11 +305,19 @@ constexpr int lp_ring() {
   return s > 6 ? 6 : s;
 }
 
-// the 8-wave form of both low-precision kernels: the X fragments of a stage
-// split evenly over 8 waves and the ring still holds three stages
+// the 8-wave form of the low-precision A^T X kernel: the X fragments of a
+// stage split evenly over 8 waves and the ring still holds three stages
 template <int NB, int E>
 constexpr bool lp_can8() {
   return (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 3;
+}
+
+// the 8-wave form of the A X kernel also with a two-stage ring (E4M3 at
+// nb = 4: 64 KB stages); unlike the row splits of A^T X, the tile height does
+// not change the order of any sum, so the results are the same either way
+template <int NB, int E>
+constexpr bool lp_ax_can8() {
+  return (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 2;
 }
 
 bool lp_atx_can8(int nb, int dtype) {
@@ -350,12 +358,12 @@ static void ax_lp_launch(hipStream_t st, const unsigned char* A, int64_t lda, in
                      lda, m, n, Xp, Y, ldy, rows_per);
 }
 
-// 8 waves (256-row tiles) when the kernel has the form (lp_can8) and every CU
-// gets a full tile; else 4 waves
+// 8 waves (256-row tiles) when the kernel has the form (lp_ax_can8) and every
+// CU gets a full tile; else 4 waves
 template <int NB, int E>
 static void ax_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m, int64_t n,
                      const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
-  if constexpr (lp_can8<NB, E>()) {
+  if constexpr (lp_ax_can8<NB, E>()) {
     if (m >= (int64_t)num_cus * 256) {
       ax_lp_launch<NB, E, 8>(st, A, lda, m, n, Xp, Y, ldy, num_cus);
       return;
