@@ -112,13 +112,16 @@ def test_lu_renorm(ctx, rows, l):
     assert np.linalg.matrix_rank(Q) == l
 
 
-def test_lu_renorm_zero_pivots(ctx):
-    rows, l = 600, 10
+# 200000 x 70 (lp = 128): the zero pivots reach the scalar-row solve
+@pytest.mark.parametrize("rows,l,rank", [(600, 10, 7), (200000, 70, 60)])
+def test_lu_renorm_zero_pivots(ctx, rows, l, rank):
     rng = np.random.default_rng(1)
     Y = np.zeros((rows, l), np.float32)
-    Y[:7] = rng.standard_normal((7, l))   # rank 7: three zero pivots
+    Y[:rank] = rng.standard_normal((rank, l))   # only `rank` nonzero rows: l - rank zero pivots
     Q, piv = ctx.renorm(_dev(Y), "lu")
     Q = Q.cpu().numpy().astype(np.float64)
+    piv = piv.cpu().numpy()
+    assert len(set(piv.tolist())) == l and piv.min() >= 0 and piv.max() < rows
     assert np.linalg.matrix_rank(Q) == l
     Uf = np.linalg.lstsq(Q, Y.astype(np.float64), rcond=None)[0]
     assert np.linalg.norm(Q @ Uf - Y) < 1e-5 * np.linalg.norm(Y)
