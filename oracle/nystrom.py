@@ -13,8 +13,10 @@ QR after the last).
 Readings of the paper taken here:
   * its = 0 means Q = qr(Omega) (the loop body never runs);
   * the shift is nu = sqrt(n) * u_A * ||B1||_F with u_A the unit roundoff of
-    the precision A is stored in (2^-24 for float32); if the Cholesky factor
-    does not exist, nu is multiplied by 10, at most ``max_retries`` times;
+    the arithmetic B1 = A Q is computed in (2^-24 for float32 products,
+    2^-16 for the device's float32 path, whose products carry about 16
+    significant bits); if the Cholesky factor does not exist, nu is
+    multiplied by 10, at most ``max_retries`` times;
   * the shift enters as B1_nu = B1 + nu Q = (A + nu I) Q, and the computed
     eigenvalues are max(S^2 - nu, 0);
   * C is the upper triangular factor with C* C = B2 (MATLAB ``chol``), and
@@ -39,13 +41,17 @@ from .rsvd import lu_renorm, qr_renorm, sign_fix
 
 
 def range_psd(A, l, its, omega):
-    """Orthonormal Q (n x l) from the self-adjoint core loop of Section 5."""
-    A = np.asarray(A, dtype=np.float64)
+    """Orthonormal Q (n x l) from the self-adjoint core loop of Section 5.
+
+    A is an array (applied exactly) or an object whose ``matmul(X)`` is A X
+    (the precision form's low-precision copy, ``oracle.precision``)."""
+    if not hasattr(A, "matmul"):
+        A = np.asarray(A, dtype=np.float64)
     Q = np.asarray(omega, dtype=np.float64)
     if its == 0:
         return qr_renorm(Q)
     for it in range(1, its + 1):
-        Q = A @ Q
+        Q = A.matmul(Q) if hasattr(A, "matmul") else A @ Q
         Q = lu_renorm(Q) if it < its else qr_renorm(Q)
     return Q
 
@@ -58,8 +64,10 @@ def shift0(B1, n, u_A):
 def eig_psd(A, k, l, its, omega, u_A=2.0 ** -24, max_retries=10, A_range=None):
     """Rank-k approximation U diag(lam) U^T of the PSD matrix A.
 
-    ``A_range`` (optional) is the matrix the range finder applies instead of
-    A (a rounded copy, see ``oracle.precision``); B1 = A Q always uses A.
+    ``A_range`` (optional) is what the range finder applies instead of A (an
+    array, or the precision form's low-precision copy with its rounded
+    operand, see ``oracle.precision``); B1 = A Q always uses A.  ``u_A`` is
+    the unit roundoff of the product B1 = A Q that the shift has to dominate.
     Returns (U n x k, lam length k, nu used, retries).
     Raises np.linalg.LinAlgError if the shifted B2 is never positive definite.
     """

@@ -17,11 +17,25 @@ from the number formats themselves:
     code.  Column j is stored as a_ij / s_j with s_j = max_i |a_ij| / 448
     (s_j = 1 for a zero column), so A = A8 diag(s).
 
+The products of the range finder with such a copy are matrix-core
+products of two bfloat16 operands: the copy's values and the other operand
+rounded to bfloat16.  That rounding belongs to the definition of the
+precision form (``LowPrecisionA``): Y = A X is A_s bf16(diag(s) X) and
+A* Q is diag(s) A_s* bf16(Q), where A_s holds the stored values (bfloat16, or
+decoded E4M3) and s the column scales (all ones for bfloat16); the operand is
+held in float32 (diag(s) X formed in float32) before it is rounded, and the
+products are exact sums (float64 here).  The Rayleigh-Ritz product reads the
+float32 A and its operand is not rounded.
+
 Pins (tests/test_oracle_precision.py): the E4M3 value table against its
 closed-form corner values (448, 2^-6, 2^-9, 240, ...), monotonicity and
 symmetry; rounding against brute force over the table (nearest value, ties
 to even) and against PyTorch's own float8_e4m3fn and bfloat16 conversions
-(independent library routines); bfloat16 ties and relative error 2^-8.
+(independent library routines); bfloat16 ties and relative error 2^-8; the
+low-precision products against brute-force sums over operands rounded by
+PyTorch's bfloat16 conversion, exactness for operands that bfloat16
+represents, the side the column scales act on, and exact recovery of a
+matrix of rank <= l when the range finder reads a rounded copy.
 """
 
 import numpy as np
@@ -104,3 +118,44 @@ def from_bf16_bits(bits):
 def to_bf16(A):
     """float64 values of bfloat16(A)."""
     return from_bf16_bits(to_bf16_bits(A))
+
+
+def bf16_operand(X):
+    """The operand of a low-precision product: X held in float32, then rounded
+    to bfloat16 (nearest even); float64 values."""
+    return to_bf16(np.asarray(X, dtype=np.float32))
+
+
+class LowPrecisionA:
+    """A bfloat16 or E4M3 copy of an m x n A as the range finder applies it.
+
+    values -- m x n stored values (bfloat16 values, or decoded E4M3 codes)
+    scales -- length-n float32 column scales (E4M3), None for bfloat16
+
+    matmul(X)  = A_s bf16(fl32(diag(s) X))      (Y = A X)
+    rmatmul(Q) = diag(s) A_s^T bf16(fl32(Q))    (Z = A* Q)
+    both summed exactly (float64).
+    """
+
+    def __init__(self, values, scales=None):
+        self.values = np.asarray(values, dtype=np.float64)
+        self.scales = None if scales is None else np.asarray(scales, dtype=np.float32)
+        self.shape = self.values.shape
+
+    def dense(self):
+        """The matrix the copy stands for, A_s diag(s), in float64."""
+        if self.scales is None:
+            return self.values
+        return self.values * self.scales.astype(np.float64)[None, :]
+
+    def matmul(self, X):
+        X32 = np.asarray(X, dtype=np.float32)
+        if self.scales is not None:
+            X32 = (X32 * self.scales[:, None]).astype(np.float32)
+        return self.values @ bf16_operand(X32)
+
+    def rmatmul(self, Q):
+        Z = self.values.T @ bf16_operand(Q)
+        if self.scales is not None:
+            Z = Z * self.scales.astype(np.float64)[:, None]
+        return Z

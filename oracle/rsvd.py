@@ -73,9 +73,11 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
     omega   -- n x l test matrix (float32 values from ``oracle.philox.omega``)
     renorm  -- "lu" (the paper's choice) or "qr" (Householder everywhere; equal
                to "lu" in exact arithmetic by span invariance)
-    A_range -- optional m x n matrix the range finder applies instead of A
-               (a rounded copy of A, see ``oracle.precision``); the
-               Rayleigh-Ritz product B = Q* A always uses A
+    A_range -- optional operator the range finder applies instead of A: an
+               m x n array (applied exactly), or an object with
+               ``matmul(X)`` = A X and ``rmatmul(Q)`` = A* Q (the precision
+               form's low-precision copy, ``oracle.precision.LowPrecisionA``);
+               the Rayleigh-Ritz product B = Q* A always uses A
 
     Returns (U m x k, S length k, V n x k), all float64.
     """
@@ -90,24 +92,37 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
     m, n = A.shape
     if not (1 <= k <= l <= min(m, n)):
         raise ValueError("need 1 <= k <= l <= min(m, n)")
-    R = A if A_range is None else np.asarray(A_range, dtype=np.float64)
+    op = hasattr(A_range, "matmul")
+    R = A if A_range is None else (A_range if op else np.asarray(A_range, dtype=np.float64))
     if R.shape != A.shape:
         raise ValueError("A_range must have the shape of A")
     if center:
         # PCA after subtracting from each column its mean (Section 2).
         A = A - A.mean(axis=0, keepdims=True)
-        R = A if A_range is None else R - R.mean(axis=0, keepdims=True)
+        if not op:
+            R = A if A_range is None else R - R.mean(axis=0, keepdims=True)
     omega = np.asarray(omega, dtype=np.float64)
     mid = lu_renorm if renorm == "lu" else qr_renorm
 
+    def apply(X):  # A X (centered: the column means of the product removed)
+        if not op:
+            return R @ X
+        Y = R.matmul(X)
+        return Y - Y.mean(axis=0, keepdims=True) if center else Y
+
+    def apply_t(Q):  # A* Q, as (Q* A)* for an array; A_c* Q = A* (Q - 1 mean(Q))
+        if not op:
+            return np.asarray(Q.T @ R).T
+        return R.rmatmul(Q - Q.mean(axis=0, keepdims=True) if center else Q)
+
     # Apply A to l random vectors (Section 2, range finder).
-    Y = R @ omega
+    Y = apply(omega)
     Q = qr_renorm(Y) if its == 0 else mid(Y)
     for it in range(1, its + 1):
         # Apply A* as (Q* A)* without forming A* (Section 5).
-        Z = np.asarray(Q.T @ R).T
+        Z = apply_t(Q)
         Q = mid(Z)
-        Y = R @ Q
+        Y = apply(Q)
         # LU in all but the last iteration, QR in the last (Section 5).
         Q = mid(Y) if it < its else qr_renorm(Y)
 

@@ -80,3 +80,94 @@ def test_bf16_rounding():
     assert np.all(np.abs(b - y) <= 2.0 ** -8 * np.abs(y.astype(np.float64)))  # u = 2^-8
     want = torch.from_numpy(y).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     np.testing.assert_array_equal(pr.to_bf16_bits(y), want)
+
+
+# ---- the low-precision products of the precision form -------------------
+
+def _torch_bf16(x):
+    """bfloat16 rounding by PyTorch (an implementation independent of the oracle's)."""
+    import torch
+    return torch.tensor(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _lowp_pair(kind, m, n, seed):
+    rng = np.random.default_rng(seed)
+    A = (rng.standard_normal((m, n)) * np.logspace(-2, 1, n)).astype(np.float32)
+    if kind == "bf16":
+        return A, pr.LowPrecisionA(pr.to_bf16(A))
+    codes, s = pr.to_e4m3(A)
+    return A, pr.LowPrecisionA(pr.e4m3_decode(codes), s)
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_lowp_products_brute_force(kind):
+    import math
+    m, n, l = 9, 7, 3
+    A, op = _lowp_pair(kind, m, n, 3)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((n, l))
+    Q = rng.standard_normal((m, l))
+    vals = op.values
+    s = np.ones(n, dtype=np.float32) if op.scales is None else op.scales
+    # Y = A X: operand diag(s) X formed in float32, rounded to bfloat16 by torch
+    Xs = _torch_bf16(np.float32(1) * X.astype(np.float32) * s[:, None])
+    Y = np.array([[math.fsum(vals[i, j] * Xs[j, c] for j in range(n)) for c in range(l)]
+                  for i in range(m)])
+    np.testing.assert_allclose(op.matmul(X), Y, rtol=1e-14, atol=0)
+    # Z = A^T Q: the column scale applied after the sum
+    Qb = _torch_bf16(Q)
+    Z = np.array([[float(s[j]) * math.fsum(vals[i, j] * Qb[i, c] for i in range(m))
+                   for c in range(l)] for j in range(n)])
+    np.testing.assert_allclose(op.rmatmul(Q), Z, rtol=1e-14, atol=0)
+
+
+def test_lowp_product_exact_for_representable_operands():
+    A, op = _lowp_pair("bf16", 40, 30, 5)
+    X = pr.to_bf16(np.random.default_rng(6).standard_normal((30, 4)).astype(np.float32))
+    np.testing.assert_allclose(op.matmul(X), op.values @ X, rtol=1e-15)
+    # a perturbation below half a bfloat16 ulp rounds away, one above does not
+    tiny = X * (1 + 2.0 ** -10)
+    np.testing.assert_array_equal(pr.bf16_operand(tiny), X)
+    big = X * (1 + 2.0 ** -7)
+    assert np.all(pr.bf16_operand(big)[X != 0] != X[X != 0])
+
+
+def test_lowp_scales_act_on_the_right_side():
+    # the E4M3 copy stands for A8 diag(s): both products agree with that matrix
+    # up to the operand's bfloat16 rounding (2^-8 relative per term)
+    A, op = _lowp_pair("fp8", 200, 64, 7)
+    D = op.dense()
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((64, 5))
+    Q = rng.standard_normal((200, 5))
+    bound = 2.0 ** -8 * (np.abs(D) @ np.abs(X)) * 1.001
+    assert np.all(np.abs(op.matmul(X) - D @ X) <= bound)
+    bound_t = 2.0 ** -8 * (np.abs(D.T) @ np.abs(Q)) * 1.001
+    assert np.all(np.abs(op.rmatmul(Q) - D.T @ Q) <= bound_t)
+    # the bound is tight enough to see a dropped scale (s_j spans 1e-2 .. 10 / 448)
+    assert not np.all(np.abs(op.values @ X - D @ X) <= bound)
+    assert not np.all(np.abs(op.values.T @ Q - D.T @ Q) <= bound_t)
+
+
+@pytest.mark.parametrize("center", [False, True])
+def test_lowp_range_finder_recovers_rank_le_l(center):
+    # rank(A) = 6 <= l: the rounded operand moves only the basis of the sketch,
+    # whose span stays range(A); B = Q* A on the exact A then gives the exact SVD
+    from oracle import philox, rsvd
+    m, n, r, k, l = 300, 80, 6, 5, 10
+    rng = np.random.default_rng(9)
+    sig = np.linspace(1.0, 0.2, r)
+    U0 = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    V0 = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    A = pr.to_bf16(((U0 * sig) @ V0.T).astype(np.float32))  # bfloat16-exact
+    op = pr.LowPrecisionA(A)
+    _, S, _ = rsvd.rsvd(A, k, l, 2, philox.omega(3, n, l), center=center, A_range=op)
+    Ac = A - A.mean(axis=0) if center else A
+    np.testing.assert_allclose(S, np.linalg.svd(Ac, compute_uv=False)[:k], rtol=1e-10)
+    # with rank > l the rounding does show: the result differs from the exact-operand run
+    B = rng.standard_normal((m, n)).astype(np.float32)
+    opb = pr.LowPrecisionA(pr.to_bf16(B))
+    om = philox.omega(3, n, l)
+    _, S1, _ = rsvd.rsvd(B, k, l, 1, om, A_range=opb)
+    _, S2, _ = rsvd.rsvd(B, k, l, 1, om, A_range=opb.dense())
+    assert np.max(np.abs(S1 - S2) / S2) > 1e-6
