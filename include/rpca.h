@@ -17,7 +17,8 @@
  *    device has finished, unless RPCA_SYNC is passed (or the call returns a
  *    host value, which implies a synchronization).
  *  - On error nothing is launched (argument errors) or the outputs are left
- *    unspecified (device-side failures); the status says which, and
+ *    unspecified (device-side failures: RPCA_ERR_NOT_PSD, RPCA_ERR_NUMERICAL,
+ *    reported by the next synchronizing call); the status says which, and
  *    rpca_last_error() gives a message.
  *  - l <= 0 means l = k + 2 (the paper's default oversampling, Section 7).
  *    Supported range: 1 <= k <= l <= min(m, n) and l <= 128.
@@ -83,9 +84,20 @@ typedef struct {
 
 /* flags */
 enum {
-  RPCA_CENTER = 1u,     /* PCA of the column-centered matrix (Sections 2 and 5) */
-  RPCA_SYNC = 2u,       /* synchronize the stream before returning              */
-  RPCA_RENORM_ORTH = 4u /* renormalize by Cholesky QR after every application of
+  RPCA_CENTER = 1u, /* PCA of the column-centered matrix (Sections 2 and 5)     */
+  RPCA_SYNC = 2u,   /* synchronize the stream before returning, and report the
+                       device-side failures of every solve issued on the
+                       context since the last synchronizing call (see
+                       rpca_sync)                                              */
+  RPCA_DETERMINISTIC = 4u, /* use the built-in tile configurations even where
+                       the autotuner has stored others: every summation order
+                       and pivot tournament is then fixed by the shapes and the
+                       device's compute-unit count, so repeated calls (and
+                       calls on other contexts of the same device model) give
+                       bit-identical results.  Without it the results are still
+                       bit-identical run to run on one context whose autotune
+                       table does not change.                                  */
+  RPCA_RENORM_ORTH = 8u /* renormalize by Cholesky QR after every application of
                            A or A* instead of pivoted LU (Section 5 prefers LU
                            for its cost; the span, and so the result in exact
                            arithmetic, is the same)                           */
@@ -119,9 +131,14 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
 /* Shift-stabilized Nystrom method for a symmetric positive semidefinite n x n
  * A (Section 3, formulas (start)-(finish), after the self-adjoint core loop of
  * Section 5): U (n x k) and lambda (k, descending) with A ~ U diag(lambda) U*.
- * The shift is nu = sqrt(n) * u * ||A Q||_F (u = unit roundoff of the storage
- * precision), multiplied by 10 up to 10 times while the Cholesky factor does
- * not exist; then RPCA_ERR_NOT_PSD. */
+ * The shift is nu = sqrt(n) * u * ||A Q||_F, with u the unit roundoff of the
+ * product B1 = A Q (2^-16 for a float32 A, whose products are three bfloat16
+ * products of split operands; 2^-8 for a bfloat16 copy, 2^-4 for E4M3),
+ * multiplied by 10 up to rpca_set_nystrom_retries times (default 10) while
+ * the Cholesky factor does not exist.  Whether it was found is known on the
+ * device only: like every device-side failure it is reported as
+ * RPCA_ERR_NOT_PSD by the next synchronizing call on the context -- this one
+ * with RPCA_SYNC, else rpca_sync -- and lambda, U are then not meaningful. */
 rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
                          uint64_t seed, unsigned flags, float* U, int64_t ldu,
                          double* lambda);
@@ -144,7 +161,11 @@ typedef struct {
 } rpca_problem;
 
 /* Many independent solves in one call.  Every problem is checked before
- * anything is launched.
+ * anything is launched; device-side failures of single problems (a Nystrom
+ * factor never found, non-finite values) are reported per problem by
+ * rpca_batch_status and for the whole batch by the next synchronizing call
+ * (RPCA_SYNC, rpca_sync), which returns RPCA_ERR_NOT_PSD or
+ * RPCA_ERR_NUMERICAL; the other problems' outputs are valid.
  *
  * Problems with a dense float32 A, m, n <= 8192 and l <= 64 are solved by one
  * persistent launch on the context stream: each workgroup of 512 threads
@@ -170,11 +191,31 @@ typedef struct {
  * The call is ordered on the context stream like a single solve and can be
  * captured into a HIP graph there once an uncaptured call of the same batch
  * has sized the tables and workspaces (a capture that would need new ones
- * returns RPCA_ERR_UNSUPPORTED).  Unlike rpca_eig_psd, a PSD problem whose
- * shifted Cholesky factor never exists is not reported (nothing is read back
- * from the device); its eigenvalues are then not meaningful. */
+ * returns RPCA_ERR_UNSUPPORTED).  ``flags`` takes RPCA_SYNC and
+ * RPCA_DETERMINISTIC (for every problem); RPCA_CENTER and RPCA_RENORM_ORTH
+ * are per problem. */
 rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* problems,
                              unsigned flags);
+
+/* Per-problem outcome of the last rpca_svd_batched call on the context
+ * (synchronizes): status_host[i] (host, count <= that call's count) is
+ * RPCA_OK, RPCA_ERR_NUMERICAL (non-finite values) or RPCA_ERR_NOT_PSD
+ * (Nystrom factor never found) for problem i, in the order of the
+ * problems array.  Does not clear what rpca_sync reports. */
+rpca_status rpca_batch_status(rpca_ctx ctx, int32_t count, int32_t* status_host);
+
+/* Synchronize the context stream and report the device-side failures of the
+ * solves issued on the context since the last synchronizing call:
+ * RPCA_ERR_NUMERICAL when non-finite values were met (for instance a NaN or
+ * infinity in A), else RPCA_ERR_NOT_PSD when a Nystrom factor was never found
+ * (Section 3's shift retries exhausted), else RPCA_OK.  The report is then
+ * cleared.  Every device loop is bounded, so such inputs end normally with
+ * non-finite outputs. */
+rpca_status rpca_sync(rpca_ctx ctx);
+
+/* Number of times the Nystrom shift is multiplied by 10 before the solve is
+ * reported as not PSD (0 .. 30, default 10). */
+rpca_status rpca_set_nystrom_retries(rpca_ctx ctx, int32_t retries);
 
 /* Randomized power-method estimate of ||A - U diag(S) V^T||_2 (Section 4),
  * in float64: ``iters`` steps of X <- orth(E^T E X) from a Gaussian n x 4
@@ -239,7 +280,7 @@ typedef struct {
   int64_t n_ax, n_atx;    /* number of timed launches of each                */
   double bytes_ax;        /* algorithmic bytes of the timed A X launches      */
   double bytes_atx;       /* algorithmic bytes of the timed A^T X launches    */
-  int64_t shift_retries;  /* Nystrom shift retries (last call)               */
+  int64_t shift_retries;  /* Nystrom shift retries of the last Nystrom solve  */
   /* the same for passes over a bfloat16 / E4M3 copy of A                    */
   double ms_ax_lp, ms_atx_lp;
   int64_t n_ax_lp, n_atx_lp;

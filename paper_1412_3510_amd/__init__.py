@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rpca.h")
 
 F32, BF16, FP8_E4M3 = 0, 1, 2
 DENSE_ROWMAJOR, SPARSE_CSR = 0, 1
-CENTER, SYNC, RENORM_ORTH = 1, 2, 4
+CENTER, SYNC, DETERMINISTIC, RENORM_ORTH = 1, 2, 4, 8
 
 STATUS = {
     0: "RPCA_OK",
@@ -145,6 +145,9 @@ _SIGS = {
     "rpca_reset_stats": [P],
     "rpca_set_batch_streams": [P, I32],
     "rpca_set_batch_mode": [P, I32],
+    "rpca_batch_status": [P, I32, ctypes.POINTER(I32)],
+    "rpca_sync": [P],
+    "rpca_set_nystrom_retries": [P, I32],
     "rpca_tune": [P, ctypes.POINTER(Matrix), I32, I32, ctypes.POINTER(TuneResult)],
     "rpca_tune_save": [P, ctypes.c_char_p],
     "rpca_tune_load": [P, ctypes.c_char_p],
@@ -300,11 +303,13 @@ class Context:
 
     # ---- solvers -------------------------------------------------------
     def svd(self, A, k, l=None, its=2, seed=0, center=False, sync=False, out=None, mat=None,
-            renorm="lu"):
+            renorm="lu", deterministic=False):
         """U (m x k), S (k, float64), V (n x k) with U diag(S) V^T ~ A (or A - 1 c).
 
         renorm: "lu" (pivoted LU between applications, the paper's choice) or
-        "orth" (Cholesky QR every time)."""
+        "orth" (Cholesky QR every time).  sync: wait for the device and raise
+        on device-side failures (RpcaError with RPCA_ERR_NUMERICAL for
+        non-finite values)."""
         torch = self._torch
         mat, m, n = _as_mat(A, mat)
         l = k + 2 if l is None else l
@@ -316,17 +321,25 @@ class Context:
             U, S, V = out
         flags = (CENTER if center else 0) | (SYNC if sync else 0)
         flags |= RENORM_ORTH if renorm == "orth" else 0
+        flags |= DETERMINISTIC if deterministic else 0
         self._check(self.lib.rpca_svd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                       _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0)))
         return U, S, V
 
-    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="lu"):
+    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="lu",
+                deterministic=False):
+        """U (n x k), lambda (k, float64) with U diag(lambda) U^T ~ A (PSD A).
+
+        sync: wait for the device and raise RpcaError(RPCA_ERR_NOT_PSD) when the
+        shifted Cholesky factor was never found (else that surfaces at the next
+        synchronizing call, see ``sync``)."""
         torch = self._torch
         mat, n, _ = _as_mat(A, mat)
         l = k + 2 if l is None else l
         U = torch.empty(n, k, device="cuda", dtype=torch.float32)
         lam = torch.empty(k, device="cuda", dtype=torch.float64)
         flags = (SYNC if sync else 0) | (RENORM_ORTH if renorm == "orth" else 0)
+        flags |= DETERMINISTIC if deterministic else 0
         self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                           _ptr(U), U.stride(0), _ptr(lam)))
         return U, lam
@@ -367,7 +380,7 @@ class Context:
                                            out.stride(0), _ptr(scale)))
         return out, scale
 
-    def svd_batched(self, problems, sync=False):
+    def svd_batched(self, problems, sync=False, deterministic=False):
         """Solve many independent problems in one call.
 
         ``problems``: list of dicts with keys A (dense tensor or SparseMatrix),
@@ -399,9 +412,22 @@ class Context:
                 q.V, q.ldv = V.data_ptr(), V.stride(0)
             outs.append((U, S) if psd else (U, S, V))
         self._batch_keep = (arr, mats, problems)
-        self._check(self.lib.rpca_svd_batched(self.h, len(problems), ctypes.cast(arr, P),
-                                              SYNC if sync else 0))
+        flags = (SYNC if sync else 0) | (DETERMINISTIC if deterministic else 0)
+        self._check(self.lib.rpca_svd_batched(self.h, len(problems), ctypes.cast(arr, P), flags))
         return outs
+
+    def batch_status(self, count):
+        """Per-problem status codes (0 ok, 5 not PSD, 6 non-finite) of the last batch."""
+        out = (I32 * count)()
+        self._check(self.lib.rpca_batch_status(self.h, count, out))
+        return list(out)
+
+    def sync(self):
+        """Wait for the device; raise RpcaError for device-side failures since the last sync."""
+        self._check(self.lib.rpca_sync(self.h))
+
+    def set_nystrom_retries(self, retries):
+        self._check(self.lib.rpca_set_nystrom_retries(self.h, retries))
 
     # ---- single steps --------------------------------------------------
     def gaussian(self, seed, n, l, stream=0, words=False):

@@ -784,7 +784,10 @@ __device__ __attribute__((noinline)) void p_chol_qr(const double* G_, int l, int
     const bool ok = chol_par<LP, NT>(G_, false, l, srel, sabs, S.diag, attempt ? 0.0 : kTauRel,
                                      S.u.tri.R, S.ubuf);
     if (ok) break;
-    if (attempt == 1 && tid == 0) S.state[5] = 1;
+    if (attempt == 1 && tid == 0) {
+      S.state[5] = 1;
+      S.state[kStNonFinite] = 1;  // kept for the rest of the problem
+    }
     shifted = true;
   }
   __syncthreads();
@@ -1021,13 +1024,19 @@ __device__ __attribute__((noinline)) double p_chol_nystrom(const double* G_, int
   double nu = n_sqrt_u * sqrt(fro2);
   if (!(nu > 0.0)) nu = 1e-300;
   bool ok = false;
+  int used = 0;
   for (int retry = 0; retry <= max_retries; ++retry) {
     __syncthreads();
     ok = chol_par<LP, NT>(G, true, l, 0.0, nu, S.zero, 0.0, S.u.tri.R, S.ubuf);
+    used = retry;
     if (ok) break;
     if (retry < max_retries) nu *= 10.0;
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    S.state[kStRetries] = used;
+    S.state[kStNotPsd] = ok ? 0 : 1;
+  }
   if (!ok)
     for (int e = threadIdx.x; e < LP * LP; e += NT) {
       const int i = e / LP, c = e % LP;
@@ -1047,6 +1056,29 @@ __device__ __attribute__((noinline)) void jacobi_wg(const double* G, int l, int 
                              (double*)as_global(uni(b.sv)), (double*)as_global(uni(b.Wacc)),
                              (double*)as_global(uni(b.Xn)), S.u.jac.M, S.u.jac.V,
                              S.u.jac.sig, S.u.jac.perm, S.u.jac.rot, S.u.jac.big);
+  __syncthreads();
+}
+
+// The problem's status bits (small_core.h): non-finite returned values or
+// Cholesky input, and for Nystrom a shifted factor never found; OR-ed into
+// the caller's status word and stored in the problem's entry.
+__device__ __attribute__((noinline)) void p_status(const PersProblem& p, const double* sv_,
+                                                   double nu) {
+  PLds& S = g_S;
+  const double* sv = uni(sv_);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bits = S.state[kStNonFinite] ? kErrNonFinite : 0;
+    if (!isfinite(nu)) bits |= kErrNonFinite;
+    for (int j = 0; j < p.k; ++j)
+      if (!isfinite(sv[j])) bits |= kErrNonFinite;
+    if (p.kind == 1) {
+      if (S.state[kStNotPsd]) bits |= kErrNotPsd;
+      if (p.gstatus) p.gstatus[1] = S.state[kStRetries];
+    }
+    if (bits && p.gstatus) atomicOr(p.gstatus, bits);
+    if (p.status) *p.status = bits;
+  }
   __syncthreads();
 }
 
@@ -1090,11 +1122,13 @@ __device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b
   p_small_gemm<LP>(b.Y, m, l, b.Wacc, p.k, p.U, p.ldu);
   p_small_gemm<LP>(b.Z, n, l, b.Xn, p.k, p.V, p.ldv);
   if (threadIdx.x < p.k) p.S[threadIdx.x] = b.sv[threadIdx.x];
+  p_status(p, b.sv, 0.0);
   p_sign(p.U, p.ldu, m, p.k, p.V, p.ldv, n);
 }
 
 template <int LP>
-__device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b) {
+__device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b,
+                                                    int max_retries) {
   const float* A = p.A;
   const int n = p.n, l = p.l;
   float* Q = b.Y;
@@ -1115,7 +1149,8 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
   p_ax<LP>(A, p.lda, n, n, b.P, Q2);
   const double fro2 = p_fro2<LP>(Q2, n, l);
   p_gram<LP>(Q, Q2, n, b.G);
-  const double nu = p_chol_nystrom<LP>(b.G, l, fro2, sqrt((double)n) * 0x1p-24, 10);
+  // u = 2^-16: B1 is formed by three bfloat16 products of split operands
+  const double nu = p_chol_nystrom<LP>(b.G, l, fro2, sqrt((double)n) * 0x1p-16, max_retries);
   // F = (B1 + nu Q) C^-1 (pseudo); F = QF R, and the Jacobi SVD of R^T gives
   // F = QF W diag(s) X^T, so U = QF W
   p_trsm<LP>(Q2, n, l, Q, (float)nu);
@@ -1126,6 +1161,7 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
     const double s = b.sv[threadIdx.x];
     p.S[threadIdx.x] = fmax(s * s - nu, 0.0);
   }
+  p_status(p, b.sv, nu);
   p_sign(p.U, p.ldu, n, p.k, nullptr, 0, 0);
 }
 
@@ -1135,6 +1171,7 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
 __device__ __attribute__((noinline)) int next_problem(int* counter) {
   PLds& S = g_S;
   if (threadIdx.x < 64) S.zero[threadIdx.x] = 0.0;
+  if (threadIdx.x < 16) S.state[threadIdx.x] = 0;
   __syncthreads();
   if (threadIdx.x == 0) S.idx = atomicAdd(counter, 1);
   __syncthreads();
@@ -1143,7 +1180,8 @@ __device__ __attribute__((noinline)) int next_problem(int* counter) {
 
 __global__ void __launch_bounds__(NT) persistent_kernel(const PersProblem* __restrict__ probs,
                                                         int count, int* counter, float* ws,
-                                                        int64_t slot_floats, int64_t R) {
+                                                        int64_t slot_floats, int64_t R,
+                                                        int max_retries) {
   Buf b = carve(ws + (int64_t)blockIdx.x * slot_floats, R);
   for (;;) {
     const int idx = next_problem(counter);
@@ -1151,10 +1189,10 @@ __global__ void __launch_bounds__(NT) persistent_kernel(const PersProblem* __res
     const PersProblem p = probs[idx];
     if (p.l <= 32) {
       if (p.kind == 0) solve_svd<32>(p, b);
-      else solve_psd<32>(p, b);
+      else solve_psd<32>(p, b, max_retries);
     } else {
       if (p.kind == 0) solve_svd<64>(p, b);
-      else solve_psd<64>(p, b);
+      else solve_psd<64>(p, b, max_retries);
     }
   }
 }
@@ -1188,10 +1226,10 @@ int64_t pers_slot_floats(int64_t maxdim) {
 }
 
 void launch_persistent(hipStream_t st, const PersProblem* probs, int count, int* counter,
-                       float* ws, int64_t maxdim, int grid) {
+                       float* ws, int64_t maxdim, int grid, int max_retries) {
   if (count <= 0 || grid <= 0) return;
   hipLaunchKernelGGL(persistent_kernel, dim3(grid), dim3(NT), 0, st, probs, count, counter, ws,
-                     pers_slot_floats(maxdim), pers_rows(maxdim));
+                     pers_slot_floats(maxdim), pers_rows(maxdim), max_retries);
 }
 
 }  // namespace rpca

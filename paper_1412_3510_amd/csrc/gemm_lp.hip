@@ -438,10 +438,11 @@ void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_
 __global__ void __launch_bounds__(256) to_bf16_kernel(const float* __restrict__ A, int64_t lda,
                                                       int64_t m, int64_t n,
                                                       __bf16* __restrict__ out, int64_t ldo) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * n) return;
-  const int64_t i = e / n, j = e - i * n;
-  out[i * ldo + j] = static_cast<__bf16>(A[i * lda + j]);
+  const int64_t total = m * n, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / n, j = e - i * n;
+    out[i * ldo + j] = static_cast<__bf16>(A[i * lda + j]);
+  }
 }
 
 // column max |a| over row chunks of ``chunk`` rows: part[c][j]
@@ -495,10 +496,11 @@ __global__ void __launch_bounds__(256) to_e4m3_kernel(const float* __restrict__ 
                                                       const float* __restrict__ scale,
                                                       unsigned char* __restrict__ out,
                                                       int64_t ldo) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * n) return;
-  const int64_t i = e / n, j = e - i * n;
-  out[i * ldo + j] = e4m3_encode(A[i * lda + j] / scale[j]);
+  const int64_t total = m * n, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / n, j = e - i * n;
+    out[i * ldo + j] = e4m3_encode(A[i * lda + j] / scale[j]);
+  }
 }
 
 // rows per column-max chunk: 256, more when the chunk count would pass the
@@ -511,7 +513,9 @@ size_t quantize_work_bytes(int64_t m, int64_t n) {
 
 void launch_quantize(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, int dtype,
                      void* out, int64_t ldo, float* scale, float* work) {
-  const unsigned g = (unsigned)ceil_div(m * n, 256);
+  // grid-stride element kernels: at most 2^20 workgroups whatever m n is
+  const int64_t gb = ceil_div(m * n, 256);
+  const unsigned g = (unsigned)(gb < ((int64_t)1 << 20) ? gb : ((int64_t)1 << 20));
   if (dtype == 1) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(g), dim3(256), 0, st, A, lda, m, n,
                        static_cast<__bf16*>(out), ldo);

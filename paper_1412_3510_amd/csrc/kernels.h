@@ -168,8 +168,12 @@ void launch_chol_nystrom(hipStream_t st, const double* G, int l, int lp, const d
 void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int transpose, double* s,
                        double* Wacc, double* Xn, double* work, int* flag = nullptr,
                        int kneed = 0);
-// out[j] = s[j] (nu null) or max(s[j]^2 - nu, 0), j < k
-void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out);
+// out[j] = s[j] (nu null) or max(s[j]^2 - nu, 0), j < k.  The solve's status
+// (non-finite values; for Nystrom, no factor found) is OR-ed into status[0]
+// and written to *slot; status[1] gets the Nystrom retry count (state,
+// status and slot nullable; see small_core.h for the bits).
+void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out,
+                          const int* state, int* status, int* slot);
 
 // ---- spectral-norm estimate (spectral.hip) -------------------------------------
 // a sparse A for the error estimate: CSR (ptr, idx, val) and CSC (ptr_t, ...)
@@ -202,6 +206,8 @@ struct PersProblem {
   int64_t ldv;
   uint64_t seed;
   int32_t m, n, kind, k, l, its, center, orth_all;
+  int* status;   // the problem's status entry (bits of small_core.h), nullable
+  int* gstatus;  // the caller's status word: [0] OR of the bits, [1] Nystrom retries
 };
 static constexpr int kPersMaxDim = 8192;  // largest m, n
 static constexpr int kPersMaxL = 64;      // largest l
@@ -213,7 +219,8 @@ int64_t pers_slot_floats(int64_t maxdim);
 void launch_pers_table(hipStream_t st, const PersProblem* host, int count, PersProblem* dev);
 // ``count`` problems (device table) over ``grid`` workgroups; ``counter`` (device int,
 // zero at launch) hands out the problems; ``ws`` holds grid * pers_slot_floats floats.
+// max_retries: Nystrom shift retries before a problem is reported not PSD
 void launch_persistent(hipStream_t st, const PersProblem* probs, int count, int* counter,
-                       float* ws, int64_t maxdim, int grid);
+                       float* ws, int64_t maxdim, int grid, int max_retries);
 
 }  // namespace rpca

@@ -16,6 +16,7 @@
 #include "../../include/rpca.h"
 #include "common.h"
 #include "kernels.h"
+#include "small_core.h"
 
 using namespace rpca;
 
@@ -54,6 +55,14 @@ struct rpca_ctx_s {
   std::vector<hipEvent_t> event_pool;
   rpca_stats stats{};
   int* host_state = nullptr;  // pinned
+  // device status: [0] OR of the error bits (small_core.h) of the solves since
+  // the last synchronizing call, [1] Nystrom shift retries of the last solve
+  int* dstat = nullptr;
+  int nys_retries = 10;  // Nystrom shift retries before RPCA_ERR_NOT_PSD
+  // per-problem status of the last rpca_svd_batched call (device), its size
+  int* bstat = nullptr;
+  int bstat_cap = 0;
+  int bstat_count = 0;
   std::vector<BatchSlot> slots;
   hipEvent_t fork = nullptr;
   // autotuned configurations by shape class (ceil log2 m, ceil log2 n, lp, dtype)
@@ -140,6 +149,26 @@ rpca_status ensure_counters(rpca_ctx ctx, size_t n) {
   ctx->counters = static_cast<unsigned*>(p);
   ctx->counters_n = n;
   return RPCA_OK;
+}
+
+// Synchronize the stream and report the device-side failures of the solves
+// issued since the last such call (then forgotten).
+rpca_status sync_status(rpca_ctx ctx) {
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  HIP_OK(hipMemcpyAsync(ctx->host_state, ctx->dstat, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  const int bits = ctx->host_state[0];
+  ctx->stats.shift_retries = ctx->host_state[1];
+  if (!bits) return RPCA_OK;
+  launch_fill_zero(ctx->stream, reinterpret_cast<float*>(ctx->dstat), 4);
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  // non-finite values are the cause when both are set (a NaN also defeats
+  // every shifted Cholesky factorization)
+  if (bits & kErrNonFinite)
+    return fail(ctx, RPCA_ERR_NUMERICAL, "non-finite values met on the device (is A finite?)");
+  return fail(ctx, RPCA_ERR_NOT_PSD,
+              "shifted B2 = Q*(A + nu I)Q not positive definite after the shift retries");
 }
 
 hipEvent_t take_event(rpca_ctx ctx) {
@@ -280,6 +309,10 @@ const TuneCfg* tune_lookup(rpca_ctx ctx, int64_t m, int64_t n, int l, int dtype)
   auto it = ctx->tune.find(tune_key(m, n, lp_of(l), dtype));
   return it == ctx->tune.end() ? nullptr : &it->second;
 }
+
+// RPCA_DETERMINISTIC: the built-in tile configurations, whatever the autotuner
+// has stored (they fix every summation order and pivot tournament).
+const TuneCfg kBuiltin{};
 
 rpca_status prepare(rpca_ctx ctx, Work& w, int64_t m, int64_t n, int l, bool need_y2,
                     int dtype = RPCA_F32, const TuneCfg* force = nullptr) {
@@ -498,7 +531,72 @@ rpca_status check_kl(rpca_ctx ctx, int k, int& l, int64_t m, int64_t n) {
   return RPCA_OK;
 }
 
+// slot (nullable, device): the problem's status entry in a batch
+rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
+                     unsigned flags, float* U, int64_t ldu, double* S, float* V, int64_t ldv,
+                     int* slot) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  s = check_kl(ctx, k, l, A->m, A->n);
+  if (s != RPCA_OK) return s;
+  if (its < 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "its must be >= 0");
+  if (!U || !S || !V) return fail(ctx, RPCA_ERR_INVALID_ARG, "null output");
+  if (ldu < k || ldv < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu/ldv must be >= k");
+  const int64_t m = A->m, n = A->n;
+  const bool center = (flags & RPCA_CENTER) != 0;
+  const bool orth_all = (flags & RPCA_RENORM_ORTH) != 0;
+  Work w;
+  s = prepare(ctx, w, m, n, l, false, layout_kind(A),
+              (flags & RPCA_DETERMINISTIC) ? &kBuiltin : nullptr);
+  if (s != RPCA_OK) return s;
+  hipStream_t st = ctx->stream;
+  ctx->stats.calls++;
+  // the solve's own status slots start clear
+  launch_fill_zero(st, reinterpret_cast<float*>(w.state + kStRetries), 4);
+  const AView Av = native_view(A);  // range finder
+  const AView Ar = rr_view(A);      // Rayleigh-Ritz product
+  // intermediate renormalization: pivoted LU (Section 5), or Cholesky QR
+  auto mid_renorm = [&](float* T, int64_t rows) {
+    if (orth_all) orth_renorm(ctx, w, T, rows, false, seed);
+    else lu_renorm(ctx, w, T, rows);
+  };
+
+  // Omega (n x l, zero padded to lp) -> packed right operand
+  launch_fill_zero(st, w.Z, n * w.lp);
+  launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
+  // Y = A Omega
+  apply_A(ctx, A, Av, w, w.Z, w.Y);
+  if (center) center_rows(ctx, w, w.Y, m);
+  if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
+  else mid_renorm(w.Y, m);
+  for (int it = 1; it <= its; ++it) {
+    // Z = A^T Q, renormalized by LU
+    apply_At(ctx, A, Av, w, w.Y, w.Z, center);
+    mid_renorm(w.Z, n);
+    // Y = A Q; LU except after the last application, which is orthonormalized
+    apply_A(ctx, A, Av, w, w.Z, w.Y);
+    if (center) center_rows(ctx, w, w.Y, m);
+    if (it < its) mid_renorm(w.Y, m);
+    else orth_renorm(ctx, w, w.Y, m, false, seed);
+  }
+  // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
+  apply_At(ctx, A, Ar, w, w.Y, w.Z, center);
+  orth_renorm(ctx, w, w.Z, n, true, seed + 1);
+  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
+  // U = Q W, V = Q2 X, S = top k
+  launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu);
+  launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv);
+  launch_finish_values(st, w.sv, k, nullptr, S, w.state, ctx->dstat, slot);
+  launch_sign_fix(st, U, ldu, m, k, V, ldv, n, w.signwork);
+  HIP_OK(hipGetLastError());
+  if (flags & RPCA_SYNC) return sync_status(ctx);
+  return RPCA_OK;
+}
+
+
 }  // namespace
+
 
 // ============================================================================
 // C ABI
@@ -539,6 +637,20 @@ rpca_status rpca_create(rpca_ctx* out, void* hip_stream) {
     return RPCA_ERR_HIP;
   }
   ctx->host_state = static_cast<int*>(hs);
+  void* ds = nullptr;
+  if (hipMalloc(&ds, 64 * sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(hs);
+    delete ctx;
+    return RPCA_ERR_NO_MEMORY;
+  }
+  if (hipMemset(ds, 0, 64 * sizeof(int)) != hipSuccess) {
+    (void)hipFree(ds);
+    (void)hipHostFree(hs);
+    delete ctx;
+    return RPCA_ERR_HIP;
+  }
+  ctx->dstat = static_cast<int*>(ds);
   *out = ctx;
   return RPCA_OK;
 }
@@ -554,6 +666,8 @@ rpca_status rpca_destroy(rpca_ctx ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->counters) (void)hipFree(ctx->counters);
   if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+  if (ctx->dstat) (void)hipFree(ctx->dstat);
+  if (ctx->bstat) (void)hipFree(ctx->bstat);
   for (auto& b : ctx->slots) {
     if (b.stream) (void)hipStreamSynchronize(b.stream);
     if (b.ws) (void)hipFree(b.ws);
@@ -628,70 +742,18 @@ rpca_status rpca_gaussian(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t 
 
 rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
                      unsigned flags, float* U, int64_t ldu, double* S, float* V, int64_t ldv) {
-  if (!ctx) return RPCA_ERR_INVALID_ARG;
-  rpca_status s = check_matrix(ctx, A);
-  if (s != RPCA_OK) return s;
-  s = check_kl(ctx, k, l, A->m, A->n);
-  if (s != RPCA_OK) return s;
-  if (its < 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "its must be >= 0");
-  if (!U || !S || !V) return fail(ctx, RPCA_ERR_INVALID_ARG, "null output");
-  if (ldu < k || ldv < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu/ldv must be >= k");
-  const int64_t m = A->m, n = A->n;
-  const bool center = (flags & RPCA_CENTER) != 0;
-  const bool orth_all = (flags & RPCA_RENORM_ORTH) != 0;
-  Work w;
-  s = prepare(ctx, w, m, n, l, false, layout_kind(A));
-  if (s != RPCA_OK) return s;
-  hipStream_t st = ctx->stream;
-  ctx->stats.calls++;
-  const AView Av = native_view(A);  // range finder
-  const AView Ar = rr_view(A);      // Rayleigh-Ritz product
-  // intermediate renormalization: pivoted LU (Section 5), or Cholesky QR
-  auto mid_renorm = [&](float* T, int64_t rows) {
-    if (orth_all) orth_renorm(ctx, w, T, rows, false, seed);
-    else lu_renorm(ctx, w, T, rows);
-  };
-
-  // Omega (n x l, zero padded to lp) -> packed right operand
-  launch_fill_zero(st, w.Z, n * w.lp);
-  launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
-  // Y = A Omega
-  apply_A(ctx, A, Av, w, w.Z, w.Y);
-  if (center) center_rows(ctx, w, w.Y, m);
-  if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
-  else mid_renorm(w.Y, m);
-  for (int it = 1; it <= its; ++it) {
-    // Z = A^T Q, renormalized by LU
-    apply_At(ctx, A, Av, w, w.Y, w.Z, center);
-    mid_renorm(w.Z, n);
-    // Y = A Q; LU except after the last application, which is orthonormalized
-    apply_A(ctx, A, Av, w, w.Z, w.Y);
-    if (center) center_rows(ctx, w, w.Y, m);
-    if (it < its) mid_renorm(w.Y, m);
-    else orth_renorm(ctx, w, w.Y, m, false, seed);
-  }
-  // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
-  apply_At(ctx, A, Ar, w, w.Y, w.Z, center);
-  orth_renorm(ctx, w, w.Z, n, true, seed + 1);
-  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
-  // U = Q W, V = Q2 X, S = top k
-  launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu);
-  launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv);
-  launch_finish_values(st, w.sv, k, nullptr, S);
-  launch_sign_fix(st, U, ldu, m, k, V, ldv, n, w.signwork);
-  HIP_OK(hipGetLastError());
-  if (flags & RPCA_SYNC) HIP_OK(hipStreamSynchronize(st));
-  return RPCA_OK;
+  return svd_impl(ctx, A, k, l, its, seed, flags, U, ldu, S, V, ldv, nullptr);
 }
 
 }  // extern "C"
 
 namespace {
-// check_psd: read the Cholesky retry outcome back (synchronizes); the batched
-// path leaves it on the device.
+// slot (nullable, device): the problem's status entry in a batch.  Whether
+// the shifted factor was found is known on the device only: it reaches the
+// caller at the next synchronizing call (RPCA_SYNC here, rpca_sync, ...).
 rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
                          uint64_t seed, unsigned flags, float* U, int64_t ldu, double* lambda,
-                         bool check_psd) {
+                         int* slot) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
   rpca_status s = check_matrix(ctx, A, false);
   if (s != RPCA_OK) return s;
@@ -704,10 +766,12 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   if (flags & RPCA_CENTER) return fail(ctx, RPCA_ERR_INVALID_ARG, "centering does not apply to eig_psd");
   const int64_t n = A->n;
   Work w;
-  s = prepare(ctx, w, n, n, l, true, layout_kind(A));
+  s = prepare(ctx, w, n, n, l, true, layout_kind(A),
+              (flags & RPCA_DETERMINISTIC) ? &kBuiltin : nullptr);
   if (s != RPCA_OK) return s;
   hipStream_t st = ctx->stream;
   ctx->stats.calls++;
+  launch_fill_zero(st, reinterpret_cast<float*>(w.state + kStRetries), 4);
   const AView Av = native_view(A);  // the self-adjoint range finder
   const AView Ar = rr_view(A);      // B1 = A Q
 
@@ -725,25 +789,22 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   apply_A(ctx, A, Ar, w, w.Y, w.Y2);
   launch_fro2_d(st, w.Y2, w.lp, n, l, w.colpart, w.colpart2, w.scal);
   launch_gram(st, w.Y, w.lp, n, w.lp, w.Y2, w.lp, w.gpart, w.G, nullptr);
-  // unit roundoff of the copy of A that B1 was computed from
-  const double u = std::ldexp(1.0, Ar.dtype == RPCA_F32 ? -24 : (Ar.dtype == RPCA_BF16 ? -8 : -4));
+  // unit roundoff of the product B1 = A Q: a float32 A is multiplied as three
+  // bfloat16 products of split operands (about 16 significant bits), a
+  // bfloat16 / E4M3 copy with the operand rounded to bfloat16 (8 bits; 4 for
+  // the E4M3 values themselves)
+  const double u = std::ldexp(1.0, Ar.dtype == RPCA_F32 ? -16 : (Ar.dtype == RPCA_BF16 ? -8 : -4));
   launch_chol_nystrom(st, w.G, l, w.lp, w.scal, std::sqrt((double)n) * u, w.Rf, w.scal + 1,
-                      w.nu_f, w.state, 10);
+                      w.nu_f, w.state, ctx->nys_retries);
   // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
   launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp, ctx->num_cus);
   orth_renorm(ctx, w, w.Y2, n, true, seed + 1);
   launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
   launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu);
-  launch_finish_values(st, w.sv, k, w.scal + 1, lambda);
+  launch_finish_values(st, w.sv, k, w.scal + 1, lambda, w.state, ctx->dstat, slot);
   launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
   HIP_OK(hipGetLastError());
-  if (!check_psd) return RPCA_OK;
-  // the Cholesky retry outcome decides the status
-  HIP_OK(hipMemcpyAsync(ctx->host_state, w.state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_OK(hipStreamSynchronize(st));
-  ctx->stats.shift_retries = ctx->host_state[3];
-  if (ctx->host_state[4])
-    return fail(ctx, RPCA_ERR_NOT_PSD, "shifted B2 = Q*(A + nu I)Q not positive definite after retries");
+  if (flags & RPCA_SYNC) return sync_status(ctx);
   return RPCA_OK;
 }
 }  // namespace
@@ -752,7 +813,7 @@ extern "C" {
 
 rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
                          unsigned flags, float* U, int64_t ldu, double* lambda) {
-  return eig_psd_impl(ctx, A, k, l, its, seed, flags, U, ldu, lambda, true);
+  return eig_psd_impl(ctx, A, k, l, its, seed, flags, U, ldu, lambda, nullptr);
 }
 
 rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const float* U,
@@ -888,6 +949,11 @@ rpca_status rpca_set_timing(rpca_ctx ctx, int enable) {
 rpca_status rpca_get_stats(rpca_ctx ctx, rpca_stats* out) {
   if (!ctx || !out) return RPCA_ERR_INVALID_ARG;
   HIP_OK(hipStreamSynchronize(ctx->stream));
+  // the retry count of the last Nystrom solve (its status stays for rpca_sync)
+  HIP_OK(hipMemcpyAsync(ctx->host_state, ctx->dstat, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  ctx->stats.shift_retries = ctx->host_state[1];
   for (auto& t : ctx->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
@@ -965,6 +1031,8 @@ rpca_status pers_prepare(rpca_ctx ctx, const rpca_problem* problems, const std::
     e.its = q.its;
     e.center = (q.flags & RPCA_CENTER) ? 1 : 0;
     e.orth_all = (q.flags & RPCA_RENORM_ORTH) ? 1 : 0;
+    e.status = ctx->bstat + p;
+    e.gstatus = ctx->dstat;
     tab.push_back(e);
     const double passes = q.kind == 0 ? 2.0 * q.its + 2.0 : q.its + 1.0;
     cost.push_back(passes * (double)A->m * (double)A->n * (e.l <= 32 ? 32 : 64) +
@@ -1069,6 +1137,18 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_OK(hipStreamIsCapturing(ctx->stream, &cap));
   const bool capturing = cap != hipStreamCaptureStatusNone;
+  // per-problem status entries (allocated outside capture only; a buffer a
+  // larger one replaces is kept for the graphs that use it)
+  if (ctx->bstat_cap < count) {
+    if (capturing) return fail(ctx, RPCA_ERR_UNSUPPORTED, "run the batch once before capturing it");
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    rpca_status s = pers_grow(ctx, ctx->bstat, (size_t)round_up(count, 4) * sizeof(int),
+                              "status table");
+    if (s != RPCA_OK) return s;
+    ctx->bstat_cap = (int)round_up(count, 4);
+  }
+  ctx->bstat_count = count;
+  launch_fill_zero(ctx->stream, reinterpret_cast<float*>(ctx->bstat), round_up(count, 4));
   // the persistent launch's table and working memory (allocated outside capture only)
   ctx_s_pers_plan plan;
   if (!pers.empty()) {
@@ -1126,7 +1206,7 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     launch_pers_table(ctx->stream, plan.table.data(), (int)plan.table.size(), ctx->pers_tab);
     launch_fill_zero(ctx->stream, reinterpret_cast<float*>(ctx->pers_counter), 4);
     launch_persistent(ctx->stream, ctx->pers_tab, (int)pers.size(), ctx->pers_counter,
-                      ctx->pers_ws, plan.maxdim, plan.grid);
+                      ctx->pers_ws, plan.maxdim, plan.grid, ctx->nys_retries);
     HIP_OK(hipGetLastError());
     ctx->stats.calls += pers.size();
   }
@@ -1146,11 +1226,12 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     ctx->ws_bytes = sl.ws_bytes;
     ctx->counters = sl.counters;
     ctx->counters_n = sl.counters_n;
-    const unsigned f = q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH);
+    const unsigned f = (q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH)) | (flags & RPCA_DETERMINISTIC);
     if (q.kind == 0)
-      res = rpca_svd(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, q.V, q.ldv);
+      res = svd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, q.V, q.ldv,
+                     ctx->bstat + p);
     else
-      res = eig_psd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, false);
+      res = eig_psd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, ctx->bstat + p);
   }
   ctx->stream = st0;
   ctx->ws = ws0;
@@ -1163,7 +1244,36 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->slots[b].done, 0));
   }
   if (res != RPCA_OK) return res;
-  if (flags & RPCA_SYNC) HIP_OK(hipStreamSynchronize(ctx->stream));
+  if (flags & RPCA_SYNC) return sync_status(ctx);
+  return RPCA_OK;
+}
+
+rpca_status rpca_batch_status(rpca_ctx ctx, int32_t count, int32_t* status_host) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (count < 0 || count > ctx->bstat_count || (count > 0 && !status_host))
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "batch_status: count must be <= the last batch's");
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  if (count == 0) return RPCA_OK;
+  std::vector<int> bits(count);
+  HIP_OK(hipMemcpyAsync(bits.data(), ctx->bstat, count * sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < count; ++i)
+    status_host[i] = (bits[i] & kErrNonFinite) ? RPCA_ERR_NUMERICAL
+                     : (bits[i] & kErrNotPsd) ? RPCA_ERR_NOT_PSD : RPCA_OK;
+  return RPCA_OK;
+}
+
+rpca_status rpca_sync(rpca_ctx ctx) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  return sync_status(ctx);
+}
+
+rpca_status rpca_set_nystrom_retries(rpca_ctx ctx, int32_t retries) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (retries < 0 || retries > 30)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "Nystrom retries must be in [0, 30]");
+  ctx->nys_retries = retries;
   return RPCA_OK;
 }
 

@@ -36,7 +36,10 @@ __global__ void __launch_bounds__(kCholThreads) chol_qr_kernel(const double* __r
     const double sabs = attempt ? (1e-30 * maxd + 1e-300) : 0.0;
     const bool ok = chol_par<LP>(G, false, l, srel, sabs, diag, attempt ? 0.0 : kTauRel, Rs, ubuf);
     if (ok) break;
-    if (attempt == 1 && tid == 0) state[5] = 1;  // only non-finite input gets here
+    if (attempt == 1 && tid == 0) {  // only non-finite input gets here
+      state[5] = 1;
+      state[kStNonFinite] = 1;  // kept for the rest of the solve
+    }
     shifted = true;
   }
   __syncthreads();
@@ -78,20 +81,24 @@ __global__ void __launch_bounds__(256) complete_kernel(float* __restrict__ Q, in
                                                        const int* __restrict__ state,
                                                        uint64_t seed) {
   if (state[2] == 0) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = e / l;
-  const int j = (int)(e % l);
-  if (r >= rows) return;
-  if ((((unsigned)state[8 + (j >> 5)]) >> (j & 31)) & 1u)
-    Q[r * ldq + j] = philox_normal(seed, 3u, (uint64_t)r * 128u + (uint64_t)j);
+  const int64_t total = rows * l;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / l;
+    const int j = (int)(e % l);
+    if ((((unsigned)state[8 + (j >> 5)]) >> (j & 31)) & 1u)
+      Q[r * ldq + j] = philox_normal(seed, 3u, (uint64_t)r * 128u + (uint64_t)j);
+  }
 }
 
 void launch_complete(hipStream_t st, float* Q, int64_t ldq, int64_t rows, int l, const int* state,
                      uint64_t seed) {
   const int64_t total = rows * l;
   if (total == 0) return;
-  hipLaunchKernelGGL(complete_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, Q,
-                     ldq, rows, l, state, seed);
+  // grid-stride: at most 64 K workgroups whatever the size
+  const int64_t blocks = ceil_div(total, 256) < 65536 ? ceil_div(total, 256) : 65536;
+  hipLaunchKernelGGL(complete_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, rows, l,
+                     state, seed);
 }
 
 // ------------------------------------------------------------------------
@@ -122,8 +129,8 @@ __global__ void __launch_bounds__(kCholThreads) chol_nystrom_kernel(
   }
   __syncthreads();
   if (tid == 0) {
-    state[3] = ok ? retry : max_retries;
-    state[4] = ok ? 0 : 1;
+    state[kStRetries] = ok ? retry : max_retries;
+    state[kStNotPsd] = ok ? 0 : 1;
     nu_out[0] = nu;
     nu_f[0] = (float)nu;
   }
@@ -189,16 +196,45 @@ void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int trans
 #undef JAC_GO
 }
 
-// out[j] = s[j] (nu == nullptr) or max(s[j]^2 - nu, 0)
+// out[j] = s[j] (nu == nullptr) or max(s[j]^2 - nu, 0).  The status of the
+// solve -- kErrNotPsd when the Nystrom factor was never found (state slot
+// kStNotPsd), kErrNonFinite when a value returned here, the shift, or an
+// earlier Cholesky step (state slot kStNonFinite) was not finite -- is
+// OR-ed into status[0] (the caller's sticky word, read at its next
+// synchronization) and stored in *slot (nullable: the problem's entry of a
+// batch); status[1] receives the Nystrom retry count.
 __global__ void finish_values_kernel(const double* __restrict__ s, int k,
-                                     const double* __restrict__ nu, double* __restrict__ out) {
+                                     const double* __restrict__ nu, double* __restrict__ out,
+                                     const int* __restrict__ state, int* __restrict__ status,
+                                     int* __restrict__ slot) {
+  __shared__ int bad;
   const int j = threadIdx.x;
-  if (j >= k) return;
-  out[j] = nu ? fmax(s[j] * s[j] - nu[0], 0.0) : s[j];
+  if (j == 0) bad = 0;
+  __syncthreads();
+  if (j < k) {
+    const double v = nu ? fmax(s[j] * s[j] - nu[0], 0.0) : s[j];
+    out[j] = v;
+    if (!isfinite(s[j]) || (nu && !isfinite(nu[0]))) bad = 1;
+  }
+  __syncthreads();
+  if (j == 0) {
+    int bits = bad ? kErrNonFinite : 0;
+    if (state) {
+      if (state[kStNonFinite]) bits |= kErrNonFinite;
+      if (nu && state[kStNotPsd]) bits |= kErrNotPsd;
+    }
+    if (status) {
+      if (bits) atomicOr(status, bits);
+      if (nu && state) status[1] = state[kStRetries];
+    }
+    if (slot) *slot = bits;
+  }
 }
 
-void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out) {
-  hipLaunchKernelGGL(finish_values_kernel, dim3(1), dim3(128), 0, st, s, k, nu, out);
+void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out,
+                          const int* state, int* status, int* slot) {
+  hipLaunchKernelGGL(finish_values_kernel, dim3(1), dim3(128), 0, st, s, k, nu, out, state,
+                     status, slot);
 }
 
 }  // namespace rpca

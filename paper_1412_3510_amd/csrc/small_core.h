@@ -11,10 +11,19 @@ namespace rpca {
 //   0  the current orthonormalization shifted a Cholesky factorization
 //   1  extra passes 3 and 4 are needed
 //   2  dependent columns were replaced by random ones
-//   3  Nystrom shift retries
-//   4  Nystrom: no positive definite shifted B2 found
-//   5  non-finite values met
+//   5  non-finite values met (this orthonormalization)
+//   6, 7  Jacobi SVD flags
 //   8..11  bit mask of dependent columns (128 bits)
+// Slots 0 .. 11 belong to one orthonormalization (its first pass clears
+// them); slots 12 .. 15 belong to the whole solve (cleared when it starts):
+//   12 Nystrom shift retries, 13 Nystrom: no positive definite shifted B2
+//   found, 14 non-finite values met in any step.
+static constexpr int kStRetries = 12;
+static constexpr int kStNotPsd = 13;
+static constexpr int kStNonFinite = 14;
+// bits of a solve's status word (and of each batch problem's entry)
+static constexpr int kErrNotPsd = 1;
+static constexpr int kErrNonFinite = 2;
 static constexpr double kTauRel = 1e-10;   // relative Cholesky pivot that marks dependence
 static constexpr double kShiftRel = 1e-8;  // relative diagonal shift when dependence is met
 static constexpr double kJunkNorm2 = 1e-2; // squared column norm after a shifted pass

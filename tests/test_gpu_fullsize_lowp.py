@@ -4,24 +4,30 @@ for j <= 50, then 1e-3 exp(-(j - 51)/200)), k = 100, l = 120, its = 3.
 The float32 A is built on the device; its bfloat16 copy and its E4M3 copy
 with per-column scales (rpca_quantize) feed the range finder, the float32 A
 the Rayleigh-Ritz product.  The FP64 oracle runs the same algorithm on the
-host with the same Gaussian test matrix, the decoded low-precision matrix as
-the range matrix and the float32 A for B = Q* A:
-  * bfloat16: singular values within 1e-4 relative of the oracle's for the
-    well separated sigma_j = 1/j (j <= 50) and within 5e-4 on the tail, whose
-    Ritz values are not converged (sigma_k / sigma_{l+1} = 1.16) and move
-    with the bfloat16 rounding of the range finder's operand; U and V
-    orthonormal; the GPU's FP64 power estimate of the error within
-    1.1 sigma_{k+1} (sigma_{k+1} = 1e-3 e^-(50/200) exactly: A is not
-    centered);
-  * E4M3: singular values within 1e-4 relative for j <= 50 and 5e-3 on the
-    tail (its 2^-4 rounding moves the unconverged tail more; no error bound
-    is claimed for it, as at the smaller sizes).
+host with the same Gaussian test matrix and the same low-precision products
+(the stored values times the operand rounded to bfloat16,
+``oracle.precision.LowPrecisionA``), and the float32 A for B = Q* A.  The
+two then differ only by float32 accumulation and renormalization rounding,
+as the float32 path does:
+  * bfloat16: singular values within 1e-4 relative of the oracle's, the
+    unconverged tail (sigma_k / sigma_{l+1} = 1.16) included;
+    ||A - U S V^T||_2 (exact, float64) within 1.1 sigma_{k+1}
+    (sigma_{k+1} = 1e-3 e^-(50/200) exactly: A is not centered);
+  * E4M3: the converged singular values (sigma_j = 1/j, j <= 50) within 1e-4
+    of the oracle's.  The tail is parity unpinned: E4M3's 2^-4 rounding puts
+    a noise floor of about 1.4 sigma_{k+1} under A's tail, the Ritz values
+    there are 15-60% below the exact sigma_j and move with float32-level
+    differences of the sketch.  They must obey Cauchy interlacing against the
+    float32 A (sigma~_j <= sigma_j + u ||A||_F) and stay within a quarter of
+    the oracle's own distance below sigma_j; no error bound is claimed;
+  * U and V orthonormal.
 """
 
 import numpy as np
 import pytest
 import torch
 
+from bench import exact_residual_norm
 from oracle import philox, precision, rsvd
 from synth import dense
 
@@ -53,29 +59,31 @@ def test_fullsize_lowp(workload, kind):
     U, S, V = ctx.svd(q, K, L, ITS, SEED, sync=True, mat=mat)
     Sh = S.cpu().numpy()
     if kind == "bf16":
-        Al = precision.from_bf16_bits(q.view(torch.int16).cpu().numpy().view(np.uint16))
+        op = precision.LowPrecisionA(
+            precision.from_bf16_bits(q.view(torch.int16).cpu().numpy().view(np.uint16)))
     else:
-        Al = precision.from_e4m3(q.view(torch.uint8).cpu().numpy(), s.cpu().numpy())
-    _, S0, _ = rsvd.rsvd(w["Ah"], K, L, ITS, w["om"], A_range=Al)
-    del Al
+        op = precision.LowPrecisionA(precision.e4m3_decode(q.view(torch.uint8).cpu().numpy()),
+                                     s.cpu().numpy())
+    _, S0, _ = rsvd.rsvd(w["Ah"], K, L, ITS, w["om"], A_range=op)
+    del op
     rel = np.abs(Sh - S0) / S0
     lead = w["sig"][:K] > 1e-2  # sigma_j = 1/j, j <= 50: well separated, converged
     print("%s: max rel sigma diff %.2e (j <= 50), %.2e (tail; worst j = %s)"
           % (kind, rel[lead].max(), rel[~lead].max(), np.argsort(rel)[-3:] + 1), flush=True)
+    np.testing.assert_allclose(Sh[lead], S0[lead], rtol=1e-4)
     if kind == "bf16":
-        # sigma_k / sigma_{l+1} = 1.16: the tail of the Ritz values is not
-        # converged, and the bfloat16 rounding of the range finder's operand
-        # (which the oracle applies exactly) moves it by up to ~2e-4
-        np.testing.assert_allclose(Sh[lead], S0[lead], rtol=1e-4)
-        np.testing.assert_allclose(Sh[~lead], S0[~lead], rtol=5e-4)
-        assert _orth_err(U.cpu().numpy()) < 1e-4
-        assert _orth_err(V.cpu().numpy()) < 1e-4
-        err = ctx.spectral_err(q, U, S, V, iters=20, seed=9, mat=mat)
-        print("bf16: err / sigma_{k+1} = %.4f" % (err / w["sig"][K]), flush=True)
-        assert err <= 1.1 * w["sig"][K]
+        np.testing.assert_allclose(Sh, S0, rtol=1e-4)
     else:
-        # E4M3's 2^-4 rounding moves the unconverged tail further (~3e-3)
-        np.testing.assert_allclose(Sh[lead], S0[lead], rtol=1e-4)
-        np.testing.assert_allclose(Sh[~lead], S0[~lead], rtol=5e-3)
-        assert _orth_err(U.cpu().numpy()) < 1e-4
-        assert _orth_err(V.cpu().numpy()) < 1e-4
+        sig = w["sig"][:K]
+        assert np.all(Sh <= sig + 1e-7)  # interlacing; u ||A||_F < 8e-8 covers the rounding of A
+        gap = sig - S0
+        band = np.abs(Sh - S0)[~lead] / gap[~lead]
+        print("fp8 tail: |gpu - oracle| / (sigma_j - oracle) max %.3g" % band.max(), flush=True)
+        assert np.all(np.abs(Sh - S0)[~lead] <= 0.25 * gap[~lead] + 1e-4 * S0[~lead])
+    assert _orth_err(U.cpu().numpy()) < 1e-4
+    assert _orth_err(V.cpu().numpy()) < 1e-4
+    err = exact_residual_norm(w["A"], U, S, V)
+    print("%s: err / sigma_{k+1} = %.5f (exact)" % (kind, err / w["sig"][K]), flush=True)
+    assert err >= w["sig"][K] * (1 - 1e-4)  # Eckart-Young, less the float32 rounding of A
+    if kind == "bf16":
+        assert err <= 1.1 * w["sig"][K]

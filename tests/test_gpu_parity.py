@@ -263,7 +263,7 @@ def test_eig_psd(ctx, n, k, l, its):
     A = dense.psd(n, lam, seed=n + k)
     U, L = ctx.eig_psd(_dev(A), k, l, its, 99)
     U, L = U.cpu().numpy(), L.cpu().numpy()
-    U0, L0, nu, _ = nystrom.eig_psd(A, k, l, its, philox.omega(99, n, l))
+    U0, L0, nu, _ = nystrom.eig_psd(A, k, l, its, philox.omega(99, n, l), u_A=2.0 ** -16)
     np.testing.assert_allclose(L, L0, rtol=1e-4, atol=1e-6 * L0[0])
     err = spectral.spectral_err_exact(A, U, L)
     err0 = spectral.spectral_err_exact(A, U0, L0)

@@ -111,7 +111,7 @@ def test_persistent_matches_oracle(batch, i):
     print("case", CASES[i], flush=True)
     if kind == "psd":
         U, L = outs[i]
-        U0, L0, _, _ = nystrom.eig_psd(A, k, l, its, om)
+        U0, L0, _, _ = nystrom.eig_psd(A, k, l, its, om, u_A=2.0 ** -16)
         np.testing.assert_allclose(L, L0, rtol=1e-4, atol=1e-6 * L0[0])
         assert _orth_err(U) < 1e-5
         if n <= 1000:
@@ -181,7 +181,7 @@ def test_persistent_and_streams_in_one_call(ctx):
     for (kind, m, n, k, l), A, o in zip(shapes, host, outs):
         om = philox.omega(800 + shapes.index((kind, m, n, k, l)), n, l)
         if kind == "psd":
-            _, L0, _, _ = nystrom.eig_psd(A, k, l, 2, om)
+            _, L0, _, _ = nystrom.eig_psd(A, k, l, 2, om, u_A=2.0 ** -16)
             np.testing.assert_allclose(o[1].cpu().numpy(), L0, rtol=1e-4, atol=1e-6 * L0[0])
         else:
             _, S0, _ = rsvd.rsvd(A, k, l, 2, om)

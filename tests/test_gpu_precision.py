@@ -8,12 +8,14 @@
     float64 product of the same rounded operands (K terms accumulated in
     float32 after exact bfloat16 products).
   * Whole solves are compared with the oracle run with the same
-    low-precision range matrix (and the float32 A in the Rayleigh-Ritz
-    product): singular values within 1e-4 relative for bfloat16, 1e-3 for
-    E4M3, whose 2^-4 rounding moves the sketch more; the bfloat16 solve meets
+    low-precision products (stored values times the operand rounded to
+    bfloat16, ``oracle.precision.LowPrecisionA``) in the range finder and the
+    float32 A in the Rayleigh-Ritz product: the two differ by float32
+    rounding only, and singular values agree within 1e-4 relative for both
+    copies, as on the float32 path; the bfloat16 solve meets
     err <= 1.1 sigma_{k+1}, the bound of the float32 path.  E4M3 claims no
     bound (its rounding can exceed sigma_{k+1}); its error must stay within 5%
-    of the oracle's for the same E4M3 matrix.
+    of the oracle's for the same E4M3 products.
 """
 
 import numpy as np
@@ -67,6 +69,10 @@ def _lowp(ctx, gpu_lib, A, kind):
     return dA, q, s, mat, Al, sh
 
 
+def _op(Al, sh, kind):
+    return precision.LowPrecisionA(Al, None if kind == "bf16" else sh.astype(np.float32))
+
+
 @pytest.mark.parametrize("kind", ["bf16", "fp8"])
 # 70001 and 66000 rows: 256-row tiles (8 waves) for A X; 66000 rows leave each
 # workgroup a last tile of two rows.  40000 x 1040: 256-column tiles for A^T Q
@@ -106,17 +112,16 @@ def test_lowp_svd(ctx, gpu_lib, kind):
     Uh, Sh, Vh = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
     err = spectral.spectral_err_exact(A, Uh, Sh, Vh, center=True)
     om = philox.omega(seed, n, l)
-    U0, S0, V0 = rsvd.rsvd(A, k, l, its, om, center=True, A_range=Al * sh[None, :])
+    U0, S0, V0 = rsvd.rsvd(A, k, l, its, om, center=True, A_range=_op(Al, sh, kind))
     err0 = spectral.spectral_err_exact(A, U0, S0, V0, center=True)
+    np.testing.assert_allclose(Sh, S0, rtol=1e-4)
     if kind == "bf16":
-        # the bound the float32 path meets, and the oracle's singular values
+        # the bound the float32 path meets
         assert err <= 1.1 * csig[k]
-        np.testing.assert_allclose(Sh, S0, rtol=1e-4)
     else:
         # E4M3 rounding (2^-4) perturbs A by more than sigma_{k+1} here: no bound
-        # is claimed, the result must match the oracle run on the same E4M3 range
+        # is claimed, the result must match the oracle run on the same E4M3 products
         assert err <= 1.05 * err0
-        np.testing.assert_allclose(Sh, S0, rtol=1e-3)
     # the GPU error estimate reads the float32 copy
     est = ctx.spectral_err(q, U, S, V, iters=30, seed=3, center=True, mat=mat)
     assert 0.5 * err <= est <= err * (1 + 1e-9)
@@ -130,14 +135,14 @@ def test_lowp_eig_psd(ctx, gpu_lib):
     U, L = ctx.eig_psd(q, k, l, its, seed=seed, sync=True, mat=mat)
     Lh = L.cpu().numpy()
     om = philox.omega(seed, n, l)
-    U0, L0, _, _ = nystrom.eig_psd(A, k, l, its, om, A_range=Al)
+    # B1 = A Q reads the float32 A: the shift's unit roundoff is that of its
+    # split-bfloat16 products
+    U0, L0, _, _ = nystrom.eig_psd(A, k, l, its, om, A_range=precision.LowPrecisionA(Al),
+                                   u_A=2.0 ** -16)
     err = spectral.spectral_err_exact(A, U.cpu().numpy(), Lh, None)
     err0 = spectral.spectral_err_exact(A, U0, L0, None)
     assert err <= 1.05 * err0
-    # lambda_{l+1} / lambda_k = e^-0.6: the sketch is far from converged, and the
-    # bfloat16 rounding of the range finder's operand moves the Ritz values by
-    # ~2e-4 relative (the oracle applies the same bfloat16 A exactly)
-    np.testing.assert_allclose(Lh, L0, rtol=1e-3)
+    np.testing.assert_allclose(Lh, L0, rtol=1e-4)
 
 
 def test_lowp_shape_rules(ctx, gpu_lib):
