@@ -128,6 +128,25 @@ rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
                      uint64_t seed, unsigned flags, float* U, int64_t ldu, double* S,
                      float* V, int64_t ldv);
 
+/* rpca_svd for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, kernels and results as rpca_svd, with the working memory taken
+ * from a static device array of 64 MiB (the last 64 KiB hold the pivot
+ * tournament's counters) that each GPU the library runs on holds until the
+ * process ends, instead of the context's workspace.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the
+ * context must already exist.  Its first call on a device looks up the
+ * array's address there.  A problem whose working memory exceeds the array
+ * (rpca_workspace_size minus the second tall buffer, roughly
+ * 12 * max(m, n) * 32*ceil(l/32) bytes) returns RPCA_ERR_NO_MEMORY before
+ * anything is launched.  Every call on one GPU shares that array and leaves
+ * its contents behind: calls that overlap on one GPU (several streams or
+ * contexts at once) race and must be serialized by the caller.  Timing
+ * (rpca_set_timing) is not recorded for this call. */
+rpca_status rpca_svd_noalloc(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
+                             uint64_t seed, unsigned flags, float* U, int64_t ldu, double* S,
+                             float* V, int64_t ldv);
+
 /* Shift-stabilized Nystrom method for a symmetric positive semidefinite n x n
  * A (Section 3, formulas (start)-(finish), after the self-adjoint core loop of
  * Section 5): U (n x k) and lambda (k, descending) with A ~ U diag(lambda) U*.

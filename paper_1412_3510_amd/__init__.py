@@ -131,6 +131,8 @@ _SIGS = {
     "rpca_set_workspace_limit": [P, ctypes.c_size_t],
     "rpca_workspace_size": [P, ctypes.POINTER(Matrix), I32, I32, ctypes.POINTER(ctypes.c_size_t)],
     "rpca_svd": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P, P, I64],
+    "rpca_svd_noalloc": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P,
+                         P, I64],
     "rpca_eig_psd": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P],
     "rpca_spectral_err": [P, ctypes.POINTER(Matrix), I32, P, I64, P, P, I64, I32, U64,
                           ctypes.c_uint, ctypes.POINTER(D)],

@@ -15,6 +15,7 @@
 
 #include "../../include/rpca.h"
 #include "common.h"
+#include "internal.h"
 #include "kernels.h"
 #include "small_core.h"
 
@@ -597,6 +598,55 @@ rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
 
 }  // namespace
 
+namespace rpca {
+
+int ctx_device(rpca_ctx ctx) { return ctx->device; }
+
+rpca_status ctx_fail(rpca_ctx ctx, rpca_status s, const char* msg) { return fail(ctx, s, msg); }
+
+rpca_status svd_on_workspace(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
+                             uint64_t seed, unsigned flags, float* U, int64_t ldu, double* S,
+                             float* V, int64_t ldv, char* ws, size_t ws_bytes,
+                             unsigned* counters, size_t counters_n) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  rpca_status s = check_matrix(ctx, A);
+  if (s != RPCA_OK) return s;
+  s = check_kl(ctx, k, l, A->m, A->n);
+  if (s != RPCA_OK) return s;
+  // the sizes svd_impl's prepare() will ask for (independent of the tiles)
+  Work w;
+  Arena probe;
+  layout(probe, w, A->m, A->n, l, ctx->num_cus, false, layout_kind(A));
+  const size_t need = probe.off + 256, need_ctr = (size_t)w.lu_ctr + 16;
+  if (need > ws_bytes || need_ctr > counters_n)
+    return fail(ctx, RPCA_ERR_NO_MEMORY,
+                "rpca_svd_noalloc: this problem needs " + std::to_string(need) +
+                    " bytes of scratch and " + std::to_string(need_ctr) +
+                    " counters; the static scratch holds " + std::to_string(ws_bytes) +
+                    " bytes and " + std::to_string(counters_n) + " counters");
+  // the tournament's arrival counters start at zero (a kernel node, not a memset)
+  launch_fill_zero(ctx->stream, reinterpret_cast<float*>(counters),
+                   round_up((int64_t)need_ctr, 4));
+  char* const ws0 = ctx->ws;
+  const size_t wsb0 = ctx->ws_bytes;
+  unsigned* const ctr0 = ctx->counters;
+  const size_t ctrn0 = ctx->counters_n;
+  const bool timing0 = ctx->timing;
+  ctx->ws = ws;
+  ctx->ws_bytes = ws_bytes;
+  ctx->counters = counters;
+  ctx->counters_n = counters_n;
+  ctx->timing = false;  // event pairs could need creating
+  s = svd_impl(ctx, A, k, l, its, seed, flags, U, ldu, S, V, ldv, nullptr);
+  ctx->ws = ws0;
+  ctx->ws_bytes = wsb0;
+  ctx->counters = ctr0;
+  ctx->counters_n = ctrn0;
+  ctx->timing = timing0;
+  return s;
+}
+
+}  // namespace rpca
 
 // ============================================================================
 // C ABI
