@@ -57,8 +57,9 @@ def parse():
                    help="skip the autotuner (built-in tile configurations)")
     p.add_argument("--no-sparse", action="store_true",
                    help="skip the 10^6 x 10^6 sparse workload report")
-    p.add_argument("--renorm", choices=("lu", "orth"), default="lu",
-                   help="renormalization between applications: pivoted LU (the paper's) "
+    p.add_argument("--renorm", choices=("chol", "lu", "orth"), default="chol",
+                   help="renormalization between applications: one Cholesky QR pass (the "
+                        "library's default), pivoted LU (the paper's) "
                         "or Cholesky QR")
     p.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                    help="HBM bytes per launch measured by rocprofv3 counters")
@@ -241,7 +242,7 @@ def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
                       "NumPy + %s), median %.2f s" % (nsolves, A.shape[0], n, blas, med)}, rel
 
 
-def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="lu", center=True):
+def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="chol", center=True):
     """Warm up, then time ``steps`` solves on the stream with events; returns
     (ms per solve, library stats over the timed solves)."""
     import torch

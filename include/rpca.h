@@ -97,11 +97,30 @@ enum {
                        bit-identical results.  Without it the results are still
                        bit-identical run to run on one context whose autotune
                        table does not change.                                  */
-  RPCA_RENORM_ORTH = 8u /* renormalize by Cholesky QR after every application of
-                           A or A* instead of pivoted LU (Section 5 prefers LU
-                           for its cost; the span, and so the result in exact
-                           arithmetic, is the same)                           */
+  RPCA_RENORM_ORTH = 8u, /* renormalize by the two-pass orthonormalization
+                           (Cholesky QR twice) after every application of A
+                           or A*                                               */
+  RPCA_RENORM_LU = 16u, /* renormalize by pivoted LU (Q = P L, tournament
+                           pivoting) after every application but the last --
+                           the paper's choice (Section 5)                     */
+  RPCA_OMEGA_UNIFORM = 32u /* draw the test matrix Omega uniformly on (-1, 1)
+                           (rpca_uniform) instead of from N(0, 1): Section 5
+                           notes the method does not depend on the law, and
+                           each 32-bit word then gives one entry (no
+                           transcendental functions)                          */
 };
+/* Renormalization between applications of A and A* (Sections 2 and 5).
+ * Each is right-multiplication by an invertible l x l matrix, so the span and
+ * the result in exact arithmetic do not depend on it; only its cost and the
+ * conditioning of the basis it returns do.  By default one pass of Cholesky
+ * QR with a float64 Gram matrix (Q = Y R^-1, R^T R = Y^T Y): on this device
+ * it costs a third of the pivot tournament, whose l dependent elimination
+ * steps bound it by latency, where Section 5 chose LU because it costs less
+ * than QR on a CPU.  When that Cholesky factorization needs a shift (Y
+ * numerically rank deficient) the repair passes of the orthonormalizing form
+ * follow.  The last renormalization before B = Q* A is always the two-pass
+ * orthonormalization.  RPCA_RENORM_LU and RPCA_RENORM_ORTH select the
+ * others. */
 
 /* Create a context on the current HIP device, ordered on ``hip_stream``
  * (a hipStream_t; NULL = the null stream).  Owns its workspace. */
@@ -266,6 +285,13 @@ rpca_status rpca_quantize(rpca_ctx ctx, const float* A, int64_t m, int64_t n, in
  * of blocks 0 .. ceil(n*l/4)-1, four per block. */
 rpca_status rpca_gaussian(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
                           float* out, int64_t ldo, uint32_t* words_out);
+
+/* The uniform test matrix of RPCA_OMEGA_UNIFORM: out[i*ldo + j] = v[j*n + i],
+ * v[e] = (x + 1/2) 2^-31 - 1 for the 32-bit word x number e of Philox4x32-10
+ * stream ``stream`` under key ``seed`` (word e % 4 of block e / 4), formed
+ * exactly in float64 and rounded once to float32. */
+rpca_status rpca_uniform(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
+                         float* out, int64_t ldo);
 
 /* ---- single steps of the method, exposed for testing ------------------- */
 

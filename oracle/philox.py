@@ -26,7 +26,10 @@ Mapping to the test matrix (fixed by this project):
         (z_even, z_odd) = (r cos theta, r sin theta),
     evaluated in float64 and rounded once to float32;
   * the n-by-l test matrix is Omega[i, j] = z[j*n + i] (column-major order
-    of the stream).
+    of the stream);
+  * the uniform alternative of Section 5 maps each word on its own,
+    v = (x + 1/2) 2^-31 - 1, exact in float64 and rounded once to float32,
+    and Omega[i, j] = v[j*n + i] (``omega_uniform``).
 
 Pins (tests/test_oracle_philox.py): the Weyl constants against their closed
 forms (golden ratio and sqrt(3)), bijectivity of the round on a small word
@@ -118,3 +121,18 @@ def omega(seed, n, l, stream=STREAM_OMEGA):
     """The n-by-l Gaussian test matrix Omega[i, j] = z[j*n + i], float32."""
     z = normals(seed, stream, n * l)
     return z.reshape(l, n).T.copy()
+
+
+def uniforms(seed, stream, count):
+    """v[0 .. count-1]: word e of the stream (block e // 4, word e % 4) mapped
+    to (x + 1/2) 2^-31 - 1 in (-1, 1), exact in float64, rounded once to
+    float32 (Section 5: uniform draws on [-1, 1] serve as well as normal
+    ones, from the fastest generator at hand)."""
+    nb = (int(count) + 3) // 4
+    w = words(seed, stream, nb).reshape(-1)[:count]
+    return ((w.astype(np.float64) + 0.5) * 2.0 ** -31 - 1.0).astype(np.float32)
+
+
+def omega_uniform(seed, n, l, stream=STREAM_OMEGA):
+    """The n-by-l uniform test matrix Omega[i, j] = v[j*n + i], float32."""
+    return uniforms(seed, stream, n * l).reshape(l, n).T.copy()

@@ -21,7 +21,11 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rpca.h")
 
 F32, BF16, FP8_E4M3 = 0, 1, 2
 DENSE_ROWMAJOR, SPARSE_CSR = 0, 1
-CENTER, SYNC, DETERMINISTIC, RENORM_ORTH = 1, 2, 4, 8
+CENTER, SYNC, DETERMINISTIC, RENORM_ORTH, RENORM_LU, OMEGA_UNIFORM = 1, 2, 4, 8, 16, 32
+_OMEGA = {"gaussian": 0, None: 0, "uniform": OMEGA_UNIFORM}
+# renormalization between applications: "chol" (one Cholesky QR pass, the
+# default), "lu" (pivoted LU, the paper's choice), "orth" (Cholesky QR twice)
+_RENORM = {"chol": 0, None: 0, "lu": RENORM_LU, "orth": RENORM_ORTH}
 
 STATUS = {
     0: "RPCA_OK",
@@ -137,6 +141,7 @@ _SIGS = {
     "rpca_spectral_err": [P, ctypes.POINTER(Matrix), I32, P, I64, P, P, I64, I32, U64,
                           ctypes.c_uint, ctypes.POINTER(D)],
     "rpca_gaussian": [P, U64, U32, I64, I64, P, I64, P],
+    "rpca_uniform": [P, U64, U32, I64, I64, P, I64],
     "rpca_quantize": [P, P, I64, I64, I64, I32, P, I64, P],
     "rpca_svd_batched": [P, I32, P, ctypes.c_uint],
     "rpca_op_matmul": [P, ctypes.POINTER(Matrix), I32, I32, P, I64, P, I64, ctypes.c_uint],
@@ -305,11 +310,14 @@ class Context:
 
     # ---- solvers -------------------------------------------------------
     def svd(self, A, k, l=None, its=2, seed=0, center=False, sync=False, out=None, mat=None,
-            renorm="lu", deterministic=False):
+            renorm="chol", deterministic=False, omega="gaussian"):
         """U (m x k), S (k, float64), V (n x k) with U diag(S) V^T ~ A (or A - 1 c).
 
-        renorm: "lu" (pivoted LU between applications, the paper's choice) or
-        "orth" (Cholesky QR every time).  sync: wait for the device and raise
+        omega: the test matrix's law, "gaussian" or "uniform" (on (-1, 1)).
+
+        renorm: the renormalization between applications -- "chol" (one
+        Cholesky QR pass, default), "lu" (pivoted LU, the paper's choice) or
+        "orth" (Cholesky QR twice).  sync: wait for the device and raise
         on device-side failures (RpcaError with RPCA_ERR_NUMERICAL for
         non-finite values)."""
         torch = self._torch
@@ -321,15 +329,14 @@ class Context:
             V = torch.empty(n, k, device="cuda", dtype=torch.float32)
         else:
             U, S, V = out
-        flags = (CENTER if center else 0) | (SYNC if sync else 0)
-        flags |= RENORM_ORTH if renorm == "orth" else 0
-        flags |= DETERMINISTIC if deterministic else 0
+        flags = (CENTER if center else 0) | (SYNC if sync else 0) | _RENORM[renorm]
+        flags |= (DETERMINISTIC if deterministic else 0) | _OMEGA[omega]
         self._check(self.lib.rpca_svd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                       _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0)))
         return U, S, V
 
-    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="lu",
-                deterministic=False):
+    def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="chol",
+                deterministic=False, omega="gaussian"):
         """U (n x k), lambda (k, float64) with U diag(lambda) U^T ~ A (PSD A).
 
         sync: wait for the device and raise RpcaError(RPCA_ERR_NOT_PSD) when the
@@ -340,8 +347,8 @@ class Context:
         l = k + 2 if l is None else l
         U = torch.empty(n, k, device="cuda", dtype=torch.float32)
         lam = torch.empty(k, device="cuda", dtype=torch.float64)
-        flags = (SYNC if sync else 0) | (RENORM_ORTH if renorm == "orth" else 0)
-        flags |= DETERMINISTIC if deterministic else 0
+        flags = (SYNC if sync else 0) | _RENORM[renorm]
+        flags |= (DETERMINISTIC if deterministic else 0) | _OMEGA[omega]
         self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                           _ptr(U), U.stride(0), _ptr(lam)))
         return U, lam
@@ -405,8 +412,8 @@ class Context:
             q.kind = 1 if psd else 0
             q.k, q.l, q.its = k, l, int(pr.get("its", 2))
             q.seed = int(pr.get("seed", 0))
-            q.flags = (CENTER if pr.get("center") else 0) | \
-                (RENORM_ORTH if pr.get("renorm") == "orth" else 0)
+            q.flags = ((CENTER if pr.get("center") else 0) | _RENORM[pr.get("renorm")]
+                       | _OMEGA[pr.get("omega")])
             q.A = ctypes.cast(ctypes.pointer(mat), ctypes.c_void_p)
             q.U, q.ldu = U.data_ptr(), U.stride(0)
             q.S = S.data_ptr()
@@ -441,6 +448,13 @@ class Context:
         self._check(self.lib.rpca_gaussian(self.h, seed, stream, n, l, _ptr(out), out.stride(0),
                                            _ptr(w)))
         return (out, w) if words else out
+
+    def uniform(self, seed, n, l, stream=0):
+        """The uniform test matrix (n x l) of the ``omega="uniform"`` option."""
+        torch = self._torch
+        out = torch.zeros(n, l, device="cuda", dtype=torch.float32)
+        self._check(self.lib.rpca_uniform(self.h, seed, stream, n, l, _ptr(out), out.stride(0)))
+        return out
 
     def matmul(self, A, X, trans=False, center=False, mat=None):
         torch = self._torch

@@ -173,10 +173,12 @@ __device__ __forceinline__ unsigned long long abs_key(float v, int i) {
 
 // ---- Omega: X (n x LP), X[i][c] = Omega[i][c] for c < l, 0 beyond ------------
 template <int LP>
-__device__ __attribute__((noinline)) void p_omega(uint64_t seed, int n, int l, float* X_) {
+__device__ __attribute__((noinline)) void p_omega(uint64_t seed, int n, int l, float* X_,
+                                                  int uniform) {
   seed = uni(seed);
   n = uni(n);
   l = uni(l);
+  uniform = uni(uniform);
   auto X = as_global(uni(X_));
   const int tid = threadIdx.x;
   for (int e = tid; e < n * LP; e += NT)
@@ -187,8 +189,13 @@ __device__ __attribute__((noinline)) void p_omega(uint64_t seed, int n, int l, f
     uint32_t c[4] = {(uint32_t)t, (uint32_t)((uint64_t)t >> 32), 0u, 0u};
     philox_block(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     float z[4];
-    box_muller(c[0], c[1], z[0], z[1]);
-    box_muller(c[2], c[3], z[2], z[3]);
+    if (uniform) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) z[q] = word_uniform(c[q]);
+    } else {
+      box_muller(c[0], c[1], z[0], z[1]);
+      box_muller(c[2], c[3], z[2], z[3]);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t e = 4 * t + q;
@@ -875,8 +882,9 @@ __device__ __attribute__((noinline)) void p_complete(float* Q_, int rows, int l,
 // Cholesky QR, twice (and twice more when a pass was shifted or columns were
 // completed); with want_r, G = Q^T X_in afterwards (X_in kept in Bk).
 template <int LP>
+// single: one Cholesky QR pass unless it had to shift (then the repair passes)
 __device__ __attribute__((noinline)) void p_orth(float* X, int rows, int l, bool want_r, float* Bk, double* G,
-                       uint64_t seed) {
+                       uint64_t seed, bool single = false) {
   rows = uni(rows);
   l = uni(l);
   seed = uni(seed);
@@ -884,6 +892,7 @@ __device__ __attribute__((noinline)) void p_orth(float* X, int rows, int l, bool
   Bk = uni(Bk);
   G = uni(G);
   want_r = uni((int)want_r) != 0;
+  single = uni((int)single) != 0;
   PLds& S = g_S;
   if (want_r) {
     auto src = as_global(X);
@@ -893,6 +902,7 @@ __device__ __attribute__((noinline)) void p_orth(float* X, int rows, int l, bool
   }
   for (int pass = 1; pass <= 4; ++pass) {
     if (pass >= 3 && S.state[1] == 0) break;
+    if (pass == 2 && single && S.state[0] == 0) break;
     p_gram<LP>(X, nullptr, rows, G);
     p_chol_qr<LP>(G, l, pass);
     p_trsm<LP>(X, rows, l, nullptr, 0.f);
@@ -1088,8 +1098,8 @@ __device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b
   const int m = p.m, n = p.n, l = p.l;
   const bool center = p.center != 0;
   auto mid = [&](float* T, int rows) {
-    if (p.orth_all) p_orth<LP>(T, rows, l, false, b.T, b.G, p.seed);
-    else p_lu<LP>(T, rows, l);
+    if (p.mid == 1) p_lu<LP>(T, rows, l);
+    else p_orth<LP>(T, rows, l, false, b.T, b.G, p.seed, p.mid == 0);
   };
   auto apply_a = [&](const float* X) {  // Y = A X (centered when asked)
     p_pack<LP>(X, n, l, false, b.P);
@@ -1104,7 +1114,7 @@ __device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b
     p_pack<LP>(b.Y, m, l, center, b.P);
     p_atx<LP>(A, p.lda, m, n, b.P, b.Z);
   };
-  p_omega<LP>(p.seed, n, l, b.Z);
+  p_omega<LP>(p.seed, n, l, b.Z, p.uniform);
   apply_a(b.Z);
   if (p.its == 0) p_orth<LP>(b.Y, m, l, false, b.T, b.G, p.seed);
   else mid(b.Y, m);
@@ -1133,7 +1143,7 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
   const int n = p.n, l = p.l;
   float* Q = b.Y;
   float* Q2 = b.Z;
-  p_omega<LP>(p.seed, n, l, Q);
+  p_omega<LP>(p.seed, n, l, Q, p.uniform);
   if (p.its == 0) p_orth<LP>(Q, n, l, false, b.T, b.G, p.seed);
   for (int it = 1; it <= p.its; ++it) {
     p_pack<LP>(Q, n, l, false, b.P);
@@ -1141,8 +1151,8 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
     float* t = Q;
     Q = Q2;
     Q2 = t;
-    if (it < p.its && !p.orth_all) p_lu<LP>(Q, n, l);
-    else p_orth<LP>(Q, n, l, false, b.T, b.G, p.seed);
+    if (it < p.its && p.mid == 1) p_lu<LP>(Q, n, l);
+    else p_orth<LP>(Q, n, l, false, b.T, b.G, p.seed, it < p.its && p.mid == 0);
   }
   // B1 = A Q (start); B2 = Q^T B1 (second), shifted; C = chol (Cholesky)
   p_pack<LP>(Q, n, l, false, b.P);
@@ -1197,9 +1207,11 @@ __global__ void __launch_bounds__(NT) persistent_kernel(const PersProblem* __res
   }
 }
 
-// The problem table travels in kernel arguments (32 entries per launch) and
-// is written on the stream, so a captured graph replays its own table.
-constexpr int kTabChunk = 32;
+// The problem table travels in kernel arguments (16 entries per launch, well
+// inside the 4 KiB argument block) and is written on the stream, so a
+// captured graph replays its own table.
+constexpr int kTabChunk = 16;
+static_assert(sizeof(PersProblem) * kTabChunk + 16 <= 4096, "problem table chunk too large");
 struct TabChunk {
   PersProblem p[kTabChunk];
 };

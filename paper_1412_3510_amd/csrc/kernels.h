@@ -6,8 +6,9 @@
 namespace rpca {
 
 // ---- Philox Gaussian (philox.hip) -------------------------------------------
+// uniform: each word mapped to (x + 1/2) 2^-31 - 1 instead of Box-Muller
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
-                     float* out, int64_t ldo, uint32_t* words);
+                     float* out, int64_t ldo, uint32_t* words, bool uniform = false);
 
 // ---- dense products (gemm.hip) ----------------------------------------------
 // Fragment-ordered bfloat16 (hi, lo) copy of a tall float32 matrix, used as
@@ -145,11 +146,12 @@ void launch_lu_tree(hipStream_t st, const float* X, int64_t ldx, int64_t rows, i
 
 // ---- small dense float64 kernels (small.hip) ---------------------------------
 // One Cholesky-QR step on the Gram G (lp x lp): upper R as float32 ``Rf``
-// for the solve.  Passes 1 and 2 always run; passes 3 and 4 only when
+// for the solve.  Pass 1 always runs; pass 2 too unless ``cond2``, which
+// runs it only when pass 1 had to shift (state[0]); passes 3 and 4 only when
 // state[1] is set (a shifted factorization or dependent columns met).  See
-// small.hip for ``state``.
+// small_core.h for ``state``.
 void launch_chol_qr_step(hipStream_t st, const double* G, int l, int lp, int pass, float* Rf,
-                         int* state);
+                         int* state, bool cond2 = false);
 // Replace the dependent columns flagged in ``state`` by Gaussian columns.
 void launch_complete(hipStream_t st, float* Q, int64_t ldq, int64_t rows, int l, const int* state,
                      uint64_t seed);
@@ -194,8 +196,9 @@ size_t spectral_work_bytes(int64_t m, int64_t n, int k);
 // ---- persistent batched solver (batch.hip) --------------------------------------
 // One problem of the persistent launch (float32 A, row-major; all pointers
 // device memory).  kind 0: randomized SVD (center: of the column-centered A);
-// kind 1: Nystrom for a PSD A (m == n).  orth_all: Cholesky QR in place of
-// every LU renormalization.
+// kind 1: Nystrom for a PSD A (m == n).  mid: the renormalization between
+// applications -- 0 one Cholesky QR pass (repaired when it needs a shift),
+// 1 pivoted LU, 2 the two-pass orthonormalization.
 struct PersProblem {
   const float* A;
   int64_t lda;
@@ -205,7 +208,9 @@ struct PersProblem {
   float* V;
   int64_t ldv;
   uint64_t seed;
-  int32_t m, n, kind, k, l, its, center, orth_all;
+  int32_t m, n, kind, k, l, its, center, mid;
+  int32_t uniform;  // uniform test matrix (Section 5) instead of the Gaussian one
+  int32_t pad_;
   int* status;   // the problem's status entry (bits of small_core.h), nullable
   int* gstatus;  // the caller's status word: [0] OR of the bits, [1] Nystrom retries
 };

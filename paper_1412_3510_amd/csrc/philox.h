@@ -37,6 +37,12 @@ __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, float& z0, 
 }
 
 
+// The uniform alternative (Section 5: uniform draws on [-1, 1] serve as well):
+// word x -> (x + 1/2) 2^-31 - 1, exact in float64, rounded once to float32.
+__device__ __forceinline__ float word_uniform(uint32_t x) {
+  return (float)(((double)x + 0.5) * 4.656612873077393e-10 - 1.0);  // 2^-31
+}
+
 // Normal variate number e (e = 4t + q) of stream ``stream`` under ``seed``.
 __device__ __forceinline__ float philox_normal(uint64_t seed, uint32_t stream, uint64_t e) {
   const uint64_t t = e >> 2;

@@ -11,6 +11,8 @@
 //       u = (x + 1/2) 2^-32, r = sqrt(-2 ln u_a), theta = 2 pi u_b,
 //       (r cos theta, r sin theta), then rounded once to float32
 //   Omega[i, j] = z[j*n + i]
+// or, for the uniform test matrix, each word on its own:
+//   v = (x + 1/2) 2^-31 - 1 (float64, exact), rounded to float32
 #include "common.h"
 #include "kernels.h"
 #include "philox.h"
@@ -21,7 +23,8 @@ namespace rpca {
 // Omega[e % n, e / n].
 __global__ void __launch_bounds__(256) gaussian_kernel(uint64_t seed, uint32_t stream, int64_t n,
                                                        int64_t l, float* __restrict__ out,
-                                                       int64_t ldo, uint32_t* __restrict__ words) {
+                                                       int64_t ldo, uint32_t* __restrict__ words,
+                                                       int uniform) {
   const int64_t total = n * l;
   const int64_t nb = (total + 3) / 4;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -33,8 +36,13 @@ __global__ void __launch_bounds__(256) gaussian_kernel(uint64_t seed, uint32_t s
     for (int q = 0; q < 4; ++q) words[4 * t + q] = c[q];
   }
   float z[4];
-  box_muller(c[0], c[1], z[0], z[1]);
-  box_muller(c[2], c[3], z[2], z[3]);
+  if (uniform) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) z[q] = word_uniform(c[q]);
+  } else {
+    box_muller(c[0], c[1], z[0], z[1]);
+    box_muller(c[2], c[3], z[2], z[3]);
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t e = 4 * t + q;
@@ -46,12 +54,12 @@ __global__ void __launch_bounds__(256) gaussian_kernel(uint64_t seed, uint32_t s
 }
 
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
-                     float* out, int64_t ldo, uint32_t* words) {
+                     float* out, int64_t ldo, uint32_t* words, bool uniform) {
   const int64_t nb = (n * l + 3) / 4;
   if (nb == 0) return;
   const int64_t grid = (nb + 255) / 256;
   hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)grid), dim3(256), 0, st, seed, stream, n, l,
-                     out, ldo, words);
+                     out, ldo, words, uniform ? 1 : 0);
 }
 
 }  // namespace rpca

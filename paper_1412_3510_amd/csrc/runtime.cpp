@@ -433,19 +433,30 @@ void lu_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
 // shifted and completed when Y is numerically rank deficient).  With
 // ``want_r`` the l x l factor R = Q^T Y_in is formed in float64 into w.G
 // (the exact projection of the input onto the final basis; upper triangular
-// up to rounding).
-void orth_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows, bool want_r, uint64_t seed) {
+// up to rounding).  ``single``: one Cholesky QR pass when its factorization
+// needs no shift (the renormalization between applications of A, where only
+// the span and a well-conditioned basis matter); the repair passes run, as
+// in the orthonormalizing form, when it does.
+void orth_renorm(rpca_ctx ctx, Work& w, float* Y, int64_t rows, bool want_r, uint64_t seed,
+                 bool single = false) {
   hipStream_t st = ctx->stream;
   if (want_r)
     launch_copy(st, w.Bk, Y, rows * w.lp);
   for (int pass = 1; pass <= 4; ++pass) {
-    const int* skip = (pass >= 3) ? (w.state + 1) : nullptr;
+    const int* skip = (pass >= 3) ? (w.state + 1) : ((pass == 2 && single) ? w.state : nullptr);
     launch_gram(st, Y, w.lp, rows, w.lp, nullptr, 0, w.gpart, w.G, skip);
-    launch_chol_qr_step(st, w.G, w.l, w.lp, pass, w.Rf, w.state);
+    launch_chol_qr_step(st, w.G, w.l, w.lp, pass, w.Rf, w.state, single);
     launch_trsm(st, Y, w.lp, rows, w.l, w.lp, w.Rf, nullptr, skip, nullptr, nullptr, 0, ctx->num_cus);
     if (pass == 2) launch_complete(st, Y, w.lp, rows, w.l, w.state, seed ^ 0x5bd1e995u);
   }
   if (want_r) launch_gram(st, Y, w.lp, rows, w.lp, w.Bk, w.lp, w.gpart, w.G, nullptr);
+}
+
+// The renormalization between applications of A and A* selected by the flags.
+void renorm_mid(rpca_ctx ctx, Work& w, float* T, int64_t rows, unsigned kind, uint64_t seed) {
+  if (kind & RPCA_RENORM_LU) lu_renorm(ctx, w, T, rows);
+  else if (kind & RPCA_RENORM_ORTH) orth_renorm(ctx, w, T, rows, false, seed);
+  else orth_renorm(ctx, w, T, rows, false, seed, true);
 }
 
 void center_rows(rpca_ctx ctx, Work& w, float* Y, int64_t rows) {
@@ -546,7 +557,7 @@ rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   if (ldu < k || ldv < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu/ldv must be >= k");
   const int64_t m = A->m, n = A->n;
   const bool center = (flags & RPCA_CENTER) != 0;
-  const bool orth_all = (flags & RPCA_RENORM_ORTH) != 0;
+  const unsigned mid_kind = flags & (RPCA_RENORM_ORTH | RPCA_RENORM_LU);
   Work w;
   s = prepare(ctx, w, m, n, l, false, layout_kind(A),
               (flags & RPCA_DETERMINISTIC) ? &kBuiltin : nullptr);
@@ -557,15 +568,14 @@ rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   launch_fill_zero(st, reinterpret_cast<float*>(w.state + kStRetries), 4);
   const AView Av = native_view(A);  // range finder
   const AView Ar = rr_view(A);      // Rayleigh-Ritz product
-  // intermediate renormalization: pivoted LU (Section 5), or Cholesky QR
-  auto mid_renorm = [&](float* T, int64_t rows) {
-    if (orth_all) orth_renorm(ctx, w, T, rows, false, seed);
-    else lu_renorm(ctx, w, T, rows);
-  };
+  // renormalization between applications (Section 5: LU or QR both keep the
+  // span): one Cholesky QR pass by default, pivoted LU or the two-pass
+  // orthonormalization on request
+  auto mid_renorm = [&](float* T, int64_t rows) { renorm_mid(ctx, w, T, rows, mid_kind, seed); };
 
   // Omega (n x l, zero padded to lp) -> packed right operand
   launch_fill_zero(st, w.Z, n * w.lp);
-  launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr);
+  launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr, (flags & RPCA_OMEGA_UNIFORM) != 0);
   // Y = A Omega
   apply_A(ctx, A, Av, w, w.Z, w.Y);
   if (center) center_rows(ctx, w, w.Y, m);
@@ -790,6 +800,14 @@ rpca_status rpca_gaussian(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t 
   return RPCA_OK;
 }
 
+rpca_status rpca_uniform(rpca_ctx ctx, uint64_t seed, uint32_t stream, int64_t n, int64_t l,
+                         float* out, int64_t ldo) {
+  if (!ctx || !out || n < 0 || l < 0 || ldo < l) return fail(ctx, RPCA_ERR_INVALID_ARG, "bad arguments");
+  launch_gaussian(ctx->stream, seed, stream, n, l, out, ldo, nullptr, true);
+  HIP_OK(hipGetLastError());
+  return RPCA_OK;
+}
+
 rpca_status rpca_svd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
                      unsigned flags, float* U, int64_t ldu, double* S, float* V, int64_t ldv) {
   return svd_impl(ctx, A, k, l, its, seed, flags, U, ldu, S, V, ldv, nullptr);
@@ -827,12 +845,12 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
 
   // Q = Omega; its times Q = A Q renormalized (LU, QR after the last).
   launch_fill_zero(st, w.Y, n * w.lp);
-  launch_gaussian(st, seed, 0u, n, l, w.Y, w.lp, nullptr);
+  launch_gaussian(st, seed, 0u, n, l, w.Y, w.lp, nullptr, (flags & RPCA_OMEGA_UNIFORM) != 0);
   if (its == 0) orth_renorm(ctx, w, w.Y, n, false, seed);
   for (int it = 1; it <= its; ++it) {
     apply_A(ctx, A, Av, w, w.Y, w.Y2);
     launch_copy(st, w.Y, w.Y2, n * w.lp);
-    if (it < its && !(flags & RPCA_RENORM_ORTH)) lu_renorm(ctx, w, w.Y, n);
+    if (it < its) renorm_mid(ctx, w, w.Y, n, flags & (RPCA_RENORM_ORTH | RPCA_RENORM_LU), seed);
     else orth_renorm(ctx, w, w.Y, n, false, seed);
   }
   // B1 = A Q (start); B2 = Q* B1 (second), shifted; C = chol (Cholesky)
@@ -1080,7 +1098,8 @@ rpca_status pers_prepare(rpca_ctx ctx, const rpca_problem* problems, const std::
     e.l = q.l > 0 ? q.l : q.k + 2;
     e.its = q.its;
     e.center = (q.flags & RPCA_CENTER) ? 1 : 0;
-    e.orth_all = (q.flags & RPCA_RENORM_ORTH) ? 1 : 0;
+    e.mid = (q.flags & RPCA_RENORM_LU) ? 1 : ((q.flags & RPCA_RENORM_ORTH) ? 2 : 0);
+    e.uniform = (q.flags & RPCA_OMEGA_UNIFORM) ? 1 : 0;
     e.status = ctx->bstat + p;
     e.gstatus = ctx->dstat;
     tab.push_back(e);
@@ -1276,7 +1295,9 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     ctx->ws_bytes = sl.ws_bytes;
     ctx->counters = sl.counters;
     ctx->counters_n = sl.counters_n;
-    const unsigned f = (q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH)) | (flags & RPCA_DETERMINISTIC);
+    const unsigned f =
+        (q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH | RPCA_RENORM_LU | RPCA_OMEGA_UNIFORM)) |
+        (flags & RPCA_DETERMINISTIC);
     if (q.kind == 0)
       res = svd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, q.V, q.ldv,
                      ctx->bstat + p);

@@ -8,12 +8,15 @@
 
 namespace rpca {
 
+// cond2: pass 2 runs only when pass 1 had to shift (a single Cholesky QR pass
+// otherwise)
 template <int LP>
 __global__ void __launch_bounds__(kCholThreads) chol_qr_kernel(const double* __restrict__ G,
-                                                               int l, int pass,
+                                                               int l, int pass, int cond2,
                                                                float* __restrict__ Rf,
                                                                int* __restrict__ state) {
   if (pass >= 3 && state[1] == 0) return;
+  if (pass == 2 && cond2 && state[0] == 0) return;
   __shared__ double ubuf[2 * LP];
   __shared__ double diag[LP];
   __shared__ float Rs[LP * LP];
@@ -66,11 +69,12 @@ __global__ void __launch_bounds__(kCholThreads) chol_qr_kernel(const double* __r
 }
 
 void launch_chol_qr_step(hipStream_t st, const double* G, int l, int lp, int pass, float* Rf,
-                         int* state) {
+                         int* state, bool cond2) {
+  const int c2 = cond2 ? 1 : 0;
   switch (lp) {
-    case 32: hipLaunchKernelGGL(chol_qr_kernel<32>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, Rf, state); break;
-    case 64: hipLaunchKernelGGL(chol_qr_kernel<64>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, Rf, state); break;
-    case 128: hipLaunchKernelGGL(chol_qr_kernel<128>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, Rf, state); break;
+    case 32: hipLaunchKernelGGL(chol_qr_kernel<32>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, c2, Rf, state); break;
+    case 64: hipLaunchKernelGGL(chol_qr_kernel<64>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, c2, Rf, state); break;
+    case 128: hipLaunchKernelGGL(chol_qr_kernel<128>, dim3(1), dim3(kCholThreads), 0, st, G, l, pass, c2, Rf, state); break;
     default: break;
   }
 }

@@ -226,3 +226,38 @@ def batch_params(count_dense=256, count_psd=256, seed=5000):
             out.append(dict(kind="psd", m=n, n=n, k=k, l=k + 5, its=2, seed_A=10000 + p,
                             seed=20000 + p))
     return out
+
+
+# --------------------------------------------------------------------------
+# the rank-4 experiment of the paper's Section 7
+# --------------------------------------------------------------------------
+
+
+def noisy_gaussian(n, seed, dtype=np.float32):
+    """n x n matrix of i.i.d. N(sqrt(30/n), 1) entries with the sign of entry
+    (i, j) flipped when i*j is odd (1-based i, j), as in the paper's Section 7:
+    two singular values about twice as large as the rest."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) + np.sqrt(30.0 / n)
+    odd = (np.arange(1, n + 1) % 2 == 1)
+    A[np.ix_(odd, odd)] *= -1.0
+    return A.astype(dtype)
+
+
+def noisy_gaussian_torch(n, seed, device, chunk=4096):
+    """The same law on the device (torch's generator, float32, built in row
+    blocks): for n up to 10^5 (40 GB)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    A = torch.empty(n, n, device=device, dtype=torch.float32)
+    mu = float(np.sqrt(30.0 / n))
+    sgn_col = torch.ones(n, device=device, dtype=torch.float32)
+    sgn_col[0::2] = -1.0  # 1-based odd columns
+    for i in range(0, n, chunk):
+        r = min(chunk, n - i)
+        blk = torch.randn(r, n, generator=gen, device=device, dtype=torch.float32) + mu
+        rows_odd = torch.arange(i, i + r, device=device) % 2 == 0  # 1-based odd rows
+        blk[rows_odd] *= sgn_col
+        A[i:i + r] = blk
+    return A

@@ -169,7 +169,7 @@ def test_small_svd(ctx, l):
 
 # ---------------------------------------------------------------- end to end
 def _check_svd(ctx, A, k, l, its, seed, center=False, rel=1e-4, err_factor=1.1, sk1=None,
-               renorm="lu"):
+               renorm="chol"):
     m, n = A.shape
     U, S, V = ctx.svd(_dev(A), k, l, its, seed, center=center, renorm=renorm)
     torch.cuda.synchronize()
@@ -220,6 +220,16 @@ def test_svd_l120_vectors(ctx):
     U, S, V, U0, S0, V0 = _check_svd(ctx, A, k, l, 2, 99, sk1=sig[k])
     assert np.max(np.abs(U - U0)) < 1e-4
     assert np.max(np.abs(V - V0)) < 1e-4
+
+
+@pytest.mark.parametrize("m,n,k,l,its", [(3000, 200, 20, 30, 2), (200, 3000, 20, 30, 1),
+                                         (4000, 400, 50, 60, 3), (2000, 300, 90, 120, 2)])
+def test_svd_lu_renorm(ctx, m, n, k, l, its):
+    # pivoted LU (tournament) between applications, the paper's choice; the
+    # default renormalization (one Cholesky QR pass) spans the same space
+    sig = dense.spectrum_tall(min(m, n))
+    A = dense.dense(m, n, sig, seed=m + n + 2)
+    _check_svd(ctx, A, k, l, its, 27 + its, sk1=sig[k], err_factor=1.2, renorm="lu")
 
 
 @pytest.mark.parametrize("m,n,k,l,its", [(3000, 200, 20, 30, 2), (4000, 400, 50, 60, 3),

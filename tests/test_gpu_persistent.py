@@ -29,26 +29,29 @@ pytestmark = pytest.mark.gpu
 
 # (kind, m, n, k, l, its, center, renorm, special)
 CASES = [
-    ("svd", 1000, 500, 10, 12, 2, False, "lu", None),
+    ("svd", 1000, 500, 10, 12, 2, False, "chol", None),
     ("svd", 3000, 200, 20, 30, 2, False, "lu", None),
     ("svd", 200, 3000, 20, 30, 1, False, "lu", None),
-    ("svd", 4000, 400, 50, 60, 2, False, "lu", None),
+    ("svd", 4000, 400, 50, 60, 2, False, "chol", None),
+    ("svd", 777, 333, 40, 45, 2, True, "chol", None),
     ("svd", 777, 333, 40, 45, 2, True, "lu", None),
     ("svd", 500, 300, 5, 12, 0, False, "lu", None),
     ("svd", 3000, 200, 20, 30, 2, False, "orth", None),
-    ("svd", 300, 70, 8, 64, 3, False, "lu", None),
+    ("svd", 300, 70, 8, 64, 3, False, "chol", None),
     ("svd", 100, 64, 10, 64, 2, False, "lu", None),
-    ("svd", 257, 129, 12, 33, 2, True, "lu", "odd_ld"),
+    ("svd", 257, 129, 12, 33, 2, True, "chol", "odd_ld"),
     ("svd", 600, 400, 5, 20, 2, False, "lu", "rank5"),
+    ("svd", 600, 400, 5, 20, 2, False, "chol", "rank5"),
     ("svd", 300, 200, 5, 10, 1, False, "lu", "zero"),
-    ("svd", 8192, 2048, 40, 45, 2, False, "lu", None),
+    ("svd", 300, 200, 5, 10, 1, False, "chol", "zero"),
+    ("svd", 8192, 2048, 40, 45, 2, False, "chol", None),
     ("psd", 300, 300, 20, 25, 2, False, "lu", None),
-    ("psd", 1000, 1000, 10, 15, 1, False, "lu", None),
-    ("psd", 700, 700, 40, 45, 2, False, "lu", None),
+    ("psd", 1000, 1000, 10, 15, 1, False, "chol", None),
+    ("psd", 700, 700, 40, 45, 2, False, "chol", None),
     ("psd", 500, 500, 5, 10, 0, False, "lu", None),
     ("psd", 2500, 2500, 30, 35, 2, False, "orth", None),
-    ("psd", 200, 200, 3, 20, 0, False, "lu", None),
-    ("svd", 1, 300, 1, 1, 1, False, "lu", None),
+    ("psd", 200, 200, 3, 20, 0, False, "chol", None),
+    ("svd", 1, 300, 1, 1, 1, False, "chol", None),
     ("svd", 500, 1, 1, 1, 2, False, "lu", None),
 ]
 

@@ -115,3 +115,35 @@ def test_omega_layout(n, l):
     for i in range(n):
         for j in range(l):
             assert om[i, j] == z[j * n + i]
+
+
+def test_uniform_map_closed_form_and_law():
+    # the uniform test matrix of Section 5: v = (x + 1/2) 2^-31 - 1 per word
+    w = philox.words(11, 0, 1000).reshape(-1)
+    v = philox.uniforms(11, 0, 4000)
+    # closed form at the extremes and the midpoint, and exactness of the map
+    assert np.float32((0 + 0.5) * 2.0 ** -31 - 1.0) == np.float32(-1.0)
+    assert np.float32((2.0 ** 32 - 0.5) * 2.0 ** -31 - 1.0) == np.float32(1.0)
+    assert np.float32((2.0 ** 31 + 0.5) * 2.0 ** -31 - 1.0) == np.float32(2.0 ** -32)
+    np.testing.assert_array_equal(v, ((w.astype(np.float64) + 0.5) / 2.0 ** 31 - 1.0)
+                                  .astype(np.float32))
+    big = philox.uniforms(12, 0, 400000).astype(np.float64)
+    assert abs(big.mean()) < 5e-3
+    assert abs(big.var() - 1.0 / 3.0) < 5e-3
+    assert big.min() >= -1.0 and big.max() <= 1.0
+    from scipy import stats
+    assert stats.kstest(big, "uniform", args=(-1.0, 2.0)).pvalue > 1e-3
+    om = philox.omega_uniform(12, 100, 7)
+    np.testing.assert_array_equal(om[:, 2], philox.uniforms(12, 0, 700)[200:300])
+
+
+def test_uniform_omega_serves_the_range_finder():
+    # Section 5: the algorithm does not depend on the generator's law; with a
+    # uniform Omega the error stays near sigma_{k+1}, as with the Gaussian one
+    from oracle import rsvd, spectral
+    from synth import dense
+    m, n, k, l = 400, 200, 10, 12
+    sig = dense.spectrum_small(n)
+    A = dense.dense(m, n, sig, seed=5)
+    U, S, V = rsvd.rsvd(A, k, l, 2, philox.omega_uniform(3, n, l))
+    assert spectral.spectral_err_exact(A, U, S, V) <= 1.1 * sig[k]
