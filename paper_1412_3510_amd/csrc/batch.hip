@@ -110,7 +110,7 @@ struct PLds {
     float W[64 * 64];
   } u;
   float at[NWAVE][32 * 68] __attribute__((aligned(16)));  // A-pass row tiles (pitch 68)
-  double ubuf[2 * 64];
+  double ubuf[2 * 64] __attribute__((aligned(16)));
   double diag[64];
   double zero[64];
   float mu[64];

@@ -120,7 +120,7 @@ void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int
                  const float* addX, int64_t ldadd, int num_cus);
 // Y (rows x k) = X (rows x lp) W (lp x k, float64, row-major ld ldw)
 void launch_small_gemm(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,
-                       const double* W, int ldw, int k, float* Y, int64_t ldy);
+                       const double* W, int ldw, int k, float* Y, int64_t ldy, int num_cus);
 // Sign convention: flip columns of U (and V) so the largest-|.| entry of each
 // U column is positive.  ``work`` holds sign_work_bytes(m) bytes.
 size_t sign_work_bytes(int64_t m);

@@ -596,8 +596,8 @@ rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   orth_renorm(ctx, w, w.Z, n, true, seed + 1);
   launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
   // U = Q W, V = Q2 X, S = top k
-  launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu);
-  launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv);
+  launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu, ctx->num_cus);
+  launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv, ctx->num_cus);
   launch_finish_values(st, w.sv, k, nullptr, S, w.state, ctx->dstat, slot);
   launch_sign_fix(st, U, ldu, m, k, V, ldv, n, w.signwork);
   HIP_OK(hipGetLastError());
@@ -868,7 +868,7 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   launch_trsm(st, w.Y2, w.lp, n, l, w.lp, w.Rf, nullptr, nullptr, w.nu_f, w.Y, w.lp, ctx->num_cus);
   orth_renorm(ctx, w, w.Y2, n, true, seed + 1);
   launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
-  launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu);
+  launch_small_gemm(st, w.Y2, w.lp, n, l, w.Wacc, w.lp, k, U, ldu, ctx->num_cus);
   launch_finish_values(st, w.sv, k, w.scal + 1, lambda, w.state, ctx->dstat, slot);
   launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
   HIP_OK(hipGetLastError());

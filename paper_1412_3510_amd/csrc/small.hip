@@ -17,7 +17,7 @@ __global__ void __launch_bounds__(kCholThreads) chol_qr_kernel(const double* __r
                                                                int* __restrict__ state) {
   if (pass >= 3 && state[1] == 0) return;
   if (pass == 2 && cond2 && state[0] == 0) return;
-  __shared__ double ubuf[2 * LP];
+  __shared__ __attribute__((aligned(16))) double ubuf[2 * LP];
   __shared__ double diag[LP];
   __shared__ float Rs[LP * LP];
   __shared__ double s_maxd;
@@ -25,10 +25,12 @@ __global__ void __launch_bounds__(kCholThreads) chol_qr_kernel(const double* __r
   if (pass == 1 && tid < 12) state[tid] = 0;
   if (tid < LP) diag[tid] = (tid < l) ? G[tid * LP + tid] : 0.0;
   __syncthreads();
-  if (tid == 0) {
-    double maxd = 0.0;
-    for (int j = 0; j < l; ++j) maxd = fmax(maxd, diag[j]);
-    s_maxd = maxd;
+  if (tid < 64) {  // largest diagonal entry: one wave, shuffle reduction
+    double mx = 0.0;
+    for (int j = tid; j < l; j += 64) mx = fmax(mx, diag[j]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (tid == 0) s_maxd = mx;
   }
   __syncthreads();
   const double maxd = s_maxd;
@@ -114,7 +116,7 @@ __global__ void __launch_bounds__(kCholThreads) chol_nystrom_kernel(
     const double* __restrict__ G, int l, const double* __restrict__ fro2, double n_sqrt_u,
     float* __restrict__ Rf, double* __restrict__ nu_out, float* __restrict__ nu_f,
     int* __restrict__ state, int max_retries) {
-  __shared__ double ubuf[2 * LP];
+  __shared__ __attribute__((aligned(16))) double ubuf[2 * LP];
   __shared__ double zero[LP];
   __shared__ float Rs[LP * LP];
   const int tid = threadIdx.x;

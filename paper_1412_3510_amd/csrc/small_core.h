@@ -29,16 +29,18 @@ static constexpr double kShiftRel = 1e-8;  // relative diagonal shift when depen
 static constexpr double kJunkNorm2 = 1e-2; // squared column norm after a shifted pass
 
 // Cholesky G + shift = R^T R (R upper) of the leading l x l block by one
-// workgroup of NTH threads (1024 unless given).  Thread (g, c) -- g = tid / LP, c = tid % LP --
-// keeps the entries (i, c), i = g + RG q (RG = NTH / LP row groups), in
-// registers.  Step j: every thread reads the current row u = G[j][.] from a
-// double-buffered LDS row (published by its owners at the end of step j - 1)
-// and the pivot d = u[j]; row j of R, u[c] / sqrt(d), goes to the LDS factor
-// Rs (float32, row-major stride LP); the trailing entries are updated,
-// G[i][c] -= u[i] u[c] / d for j < i <= c; the owners of row j + 1 publish it;
-// one barrier.  1/sqrt(d) is v_rsq_f64 refined by two Newton steps, which
-// keeps division and square root off the step's critical path.  Nothing in
-// the loop touches global memory, so the barrier waits for LDS only.
+// workgroup of NTH threads (1024 unless given).  Thread (g, c) -- g = tid / LP,
+// c = tid % LP -- keeps the entries (i, c) of the RPT = LP RG / NTH
+// consecutive rows i = g RPT + q (RG = NTH / LP row groups) in registers.
+// Step j: every thread reads the current row u = G[j][.] from a
+// double-buffered LDS row (published by its owners at the end of step j - 1;
+// zero at the columns already factored) and the pivot d = u[j]; row j of R,
+// u[c] / sqrt(d), goes to the LDS factor Rs (float32, row-major stride LP);
+// every entry takes G[i][c] -= u[i] u[c] / d (its rows' u[i] read as 16-byte
+// pairs); the owners of row j + 1 publish it; one barrier.  1/sqrt(d) is
+// v_rsq_f64 refined by two Newton steps, which keeps division and square
+// root off the step's critical path.  Nothing in the loop touches global
+// memory, so the barrier waits for LDS only.
 // Returns false at the first pivot d <= tau * diag[j] (or not finite): all
 // threads read the same d, so all agree.
 static constexpr int kCholThreads = 1024;  // default workgroup size of chol_par
@@ -66,19 +68,19 @@ __device__ __forceinline__ double rcp_nr(double d) {
 template <int LP, int NTH = kCholThreads>
 __device__ bool chol_par(const double* __restrict__ G, bool sym, int l, double srel, double sabs,
                          const double* diag, double tau, float* Rs, double* ubuf) {
-  constexpr int RG = NTH / LP;  // row groups
-  constexpr int RPT = LP / RG;           // rows per thread
+  constexpr int RG = NTH / LP;   // row groups
+  constexpr int RPT = LP / RG;   // rows per thread, contiguous: i = g RPT + q
   const int tid = threadIdx.x, g = tid / LP, c = tid % LP;
   double v[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int i = g + RG * q;
+    const int i = g * RPT + q;
     double x = 0.0;
     if (i < l && c < l) x = sym ? 0.5 * (G[i * LP + c] + G[c * LP + i]) : G[i * LP + c];
     if (i == c && c < l) x += srel * diag[c] + sabs;
     v[q] = x;
   }
-  if (g == 0) ubuf[c] = v[0];  // row 0
+  if (g == 0) ubuf[c] = (c < l) ? v[0] : 0.0;  // row 0
   __syncthreads();
   for (int j = 0; j < l; ++j) {
     const double* u = ubuf + (j & 1) * LP;
@@ -88,14 +90,31 @@ __device__ bool chol_par(const double* __restrict__ G, bool sym, int l, double s
     const double y = rsqrt_nr(d);
     const double f = uc * (y * y);
     if (g == 0) Rs[j * LP + c] = (c < l && c >= j) ? (float)((c == j) ? d * y : uc * y) : 0.f;
-    double nxt = 0.0;
+    // every entry is updated: the published row is zero at the finished
+    // positions (c <= j), so rows above j and the lower triangle (never
+    // published) take harmless updates, and no lane is masked
+    double ui[RPT];
+    if constexpr (RPT % 2 == 0) {  // (ubuf is 16-byte aligned)
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int i = g + RG * q;
-      if (i > j && i <= c && c < l) v[q] -= u[i] * f;
-      if (i == j + 1) nxt = v[q];
+      for (int q = 0; q < RPT; q += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(u + g * RPT + q);
+        ui[q] = t.x;
+        ui[q + 1] = t.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) ui[q] = u[g * RPT + q];
     }
-    if (g == (j + 1) % RG) ubuf[((j + 1) & 1) * LP + c] = (c > j && c < l) ? nxt : 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) v[q] = fma(-ui[q], f, v[q]);
+    const int jn = j + 1;
+    if (g == jn / RPT) {  // the owners of row j + 1 publish it
+      const int oq = jn % RPT;
+      double nxt = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) nxt = (q == oq) ? v[q] : nxt;
+      ubuf[(jn & 1) * LP + c] = (c > j && c < l) ? nxt : 0.0;
+    }
     __syncthreads();
   }
   return true;
@@ -135,13 +154,14 @@ __device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
   return __hiloint2double(hi2, lo2);
 }
 
-// sum over the G (8 or 16) aligned lanes of a group (all G get the sum)
+// sum over the G (4, 8 or 16) aligned lanes of a group (all G get the sum)
 template <int G>
 __device__ __forceinline__ double sum_group(double v) {
+  static_assert(G == 4 || G == 8 || G == 16, "sum_group: G must be 4, 8 or 16");
   v += dpp_f64(v, 0);
   v += dpp_f64(v, 1);
-  v += dpp_f64(v, 2);
-  if (G == 16) v += dpp_f64(v, 3);
+  if constexpr (G >= 8) v += dpp_f64(v, 2);
+  if constexpr (G == 16) v += dpp_f64(v, 3);
   return v;
 }
 
@@ -170,7 +190,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
                                             double* __restrict__ Wacc, double* __restrict__ Xn,
                                             double* Mc, double* Vc, double* sig, int* perm,
                                             int& s_rot, int& s_big, int* flag = nullptr,
-                                            int kneed = 0) {
+                                            int kneed = 0, int* sweeps_out = nullptr) {
   constexpr int CS = jacobi_cs<LP, GLOBAL>();
   constexpr int RPT = LP / G;     // rows per lane
   constexpr int NT = G * LP / 2;  // G lanes for each of the LP/2 pair slots
@@ -194,7 +214,8 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
   // and the accumulated rotations within about 1e-12 of the converged ones;
   // the sweeps after it only confirm that, and are skipped
   const double quiet = 1e-6;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
     __syncthreads();
     if (tid == 0) {
       s_rot = 0;
@@ -273,6 +294,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
     }
     if (s_rot == 0 || s_big == 0) break;
   }
+  if (sweeps_out && tid == 0) *sweeps_out = sweep;
   __syncthreads();
   if (tid < LP) {
     double s = 0.0;

@@ -441,46 +441,110 @@ void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int
 
 // ------------------------------------------------------------------------
 // Y (rows x k) = X (rows x lp) W (lp x k), W float64 rounded to float32 in
-// LDS.  One thread per row.
+// LDS.  A workgroup walks tiles of 32 rows (grid-stride, about two
+// workgroups per CU, so W is converted once per workgroup): the tile of X
+// is loaded with coalesced 16-byte reads and kept transposed in LDS; thread
+// (row group, column group) accumulates a (32 / RG) x 4 block of Y over
+// i < l in order, and writes it back with 16-byte stores when the layout
+// allows.
 // ------------------------------------------------------------------------
+static constexpr int kGemmRows = 32;
+
 template <int LP>
 __global__ void __launch_bounds__(256) small_gemm_kernel(const float* __restrict__ X, int64_t ldx,
                                                          int64_t rows, int l,
                                                          const double* __restrict__ W, int ldw,
                                                          int k, float* __restrict__ Y,
-                                                         int64_t ldy) {
-  __shared__ float sW[LP * LP];
-  for (int e = threadIdx.x; e < LP * k; e += 256) {
-    const int i = e / k, c = e % k;
-    sW[i * LP + c] = (i < l) ? (float)W[i * ldw + c] : 0.f;
+                                                         int64_t ldy, int vec) {
+  constexpr int TR = kGemmRows;
+  constexpr int CG = LP / 4;        // column groups of 4
+  constexpr int RG = 256 / CG;      // row groups
+  constexpr int RPG = TR / RG;      // rows per thread
+  constexpr int WS = LP + 4;        // LDS row stride of W
+  constexpr int XS = TR + 4;        // LDS row stride of the transposed tile
+  constexpr int F4 = TR * LP / 4 / 256;  // float4 loads per thread per tile
+  __shared__ __attribute__((aligned(16))) float sW[LP * WS];
+  __shared__ __attribute__((aligned(16))) float sX[LP * XS];
+  for (int e = threadIdx.x; e < LP * LP; e += 256) {
+    const int i = e / LP, c = e % LP;
+    sW[i * WS + c] = (i < l && c < k) ? (float)W[i * ldw + c] : 0.f;
   }
-  __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (row >= rows) return;
-  float x[LP];
-  const float* src = X + row * ldx;
+  const int tc = threadIdx.x % CG, tr = threadIdx.x / CG;
+  const int64_t ntiles = ceil_div(rows, (int64_t)TR);
+  // the next tile's X is loaded into registers while the current one is used
+  float4 pre[F4];
+  auto load = [&](int64_t t) {
 #pragma unroll
-  for (int c = 0; c < LP; c += 4) {
-    const float4 v = *reinterpret_cast<const float4*>(src + c);
-    x[c] = v.x; x[c + 1] = v.y; x[c + 2] = v.z; x[c + 3] = v.w;
-  }
-  for (int c = 0; c < k; ++c) {
-    float s = 0.f;
+    for (int q = 0; q < F4; ++q) {
+      const int e = threadIdx.x + 256 * q, rr = e / (LP / 4), c4 = 4 * (e % (LP / 4));
+      const int64_t r = t * TR + rr;
+      pre[q] = (r < rows) ? *reinterpret_cast<const float4*>(X + r * ldx + c4)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  if ((int64_t)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t r0 = t * TR;
+    __syncthreads();  // the previous tile's reads are done (and W is in place)
 #pragma unroll
-    for (int i = 0; i < LP; ++i) s += x[i] * sW[i * LP + c];
-    Y[row * ldy + c] = s;
+    for (int q = 0; q < F4; ++q) {
+      const int e = threadIdx.x + 256 * q, rr = e / (LP / 4), c4 = 4 * (e % (LP / 4));
+      sX[(c4 + 0) * XS + rr] = pre[q].x;
+      sX[(c4 + 1) * XS + rr] = pre[q].y;
+      sX[(c4 + 2) * XS + rr] = pre[q].z;
+      sX[(c4 + 3) * XS + rr] = pre[q].w;
+    }
+    __syncthreads();
+    if (t + gridDim.x < ntiles) load(t + gridDim.x);
+    float acc[RPG][4];
+#pragma unroll
+    for (int a = 0; a < RPG; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+    for (int i = 0; i < l; ++i) {
+      const float4 w4 = *reinterpret_cast<const float4*>(sW + i * WS + 4 * tc);
+      float xa[RPG];
+#pragma unroll
+      for (int a = 0; a < RPG; ++a) xa[a] = sX[i * XS + tr * RPG + a];
+#pragma unroll
+      for (int a = 0; a < RPG; ++a) {
+        acc[a][0] = fmaf(xa[a], w4.x, acc[a][0]);
+        acc[a][1] = fmaf(xa[a], w4.y, acc[a][1]);
+        acc[a][2] = fmaf(xa[a], w4.z, acc[a][2]);
+        acc[a][3] = fmaf(xa[a], w4.w, acc[a][3]);
+      }
+    }
+    const int c0 = 4 * tc;
+    if (c0 < k) {
+#pragma unroll
+      for (int a = 0; a < RPG; ++a) {
+        const int64_t r = r0 + tr * RPG + a;
+        if (r >= rows) break;
+        float* dst = Y + r * ldy + c0;
+        if (vec && c0 + 4 <= k) {
+          *reinterpret_cast<float4*>(dst) = make_float4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
+        } else {
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (c0 + b < k) dst[b] = acc[a][b];
+        }
+      }
+    }
   }
 }
 
 void launch_small_gemm(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int l,
-                       const double* W, int ldw, int k, float* Y, int64_t ldy) {
+                       const double* W, int ldw, int k, float* Y, int64_t ldy, int num_cus) {
   if (rows == 0) return;
-  const dim3 grid((unsigned)ceil_div(rows, 256));
+  const int64_t tiles = ceil_div(rows, (int64_t)kGemmRows);
+  const int64_t cap = 2 * (int64_t)(num_cus > 0 ? num_cus : 256);
+  const dim3 grid((unsigned)(tiles < cap ? tiles : cap));
+  const int vec = (ldy % 4 == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0) ? 1 : 0;
   const int lp = (int)ldx;  // X is stored with ld = lp
   switch (lp) {
-    case 32: hipLaunchKernelGGL(small_gemm_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy); break;
-    case 64: hipLaunchKernelGGL(small_gemm_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy); break;
-    case 128: hipLaunchKernelGGL(small_gemm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy); break;
+    case 32: hipLaunchKernelGGL(small_gemm_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy, vec); break;
+    case 64: hipLaunchKernelGGL(small_gemm_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy, vec); break;
+    case 128: hipLaunchKernelGGL(small_gemm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, W, ldw, k, Y, ldy, vec); break;
     default: break;
   }
 }
