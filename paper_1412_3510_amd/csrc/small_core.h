@@ -136,20 +136,22 @@ __device__ bool chol_par(const double* __restrict__ G, bool sym, int l, double s
 // ------------------------------------------------------------------------
 __device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
   // ctrl_sel: 0 = quad_perm [1,0,3,2], 1 = quad_perm [2,3,0,1], 2 = row_half_mirror
+  // every lane reads a valid source lane (full row and bank masks), so the
+  // moves need no fill value
   int lo = __double2loint(v), hi = __double2hiint(v);
   int lo2, hi2;
   if (ctrl_sel == 0) {
-    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
-    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
   } else if (ctrl_sel == 1) {
-    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
-    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
   } else if (ctrl_sel == 2) {
-    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
-    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
   } else {  // row_mirror
-    lo2 = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
-    hi2 = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false);
   }
   return __hiloint2double(hi2, lo2);
 }
@@ -190,7 +192,8 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
                                             double* __restrict__ Wacc, double* __restrict__ Xn,
                                             double* Mc, double* Vc, double* sig, int* perm,
                                             int& s_rot, int& s_big, int* flag = nullptr,
-                                            int kneed = 0, int* sweeps_out = nullptr) {
+                                            int kneed = 0, int* sweeps_out = nullptr,
+                                            double quiet = 1e-6) {
   constexpr int CS = jacobi_cs<LP, GLOBAL>();
   constexpr int RPT = LP / G;     // rows per lane
   constexpr int NT = G * LP / 2;  // G lanes for each of the LP/2 pair slots
@@ -206,14 +209,18 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
   const int npairs = lp2 / 2;
   const int k = tid / G, gl = tid % G;  // pair slot, lane in the group of G
   const bool active = (k < npairs);
-  const int i0 = gl * RPT;  // this lane's first row
+  // rows of a lane: pairs (2 gl, 2 gl + 1) + 2 G v, v < RPT / 2, so that the
+  // G lanes of a pair read consecutive 16-byte words (no LDS bank conflicts)
+  const int i0 = 2 * gl;
   const double tol = 1e-13;
   // cyclic Jacobi converges quadratically: a sweep that starts with every
   // |cos of the pair angle| <= 1e-6 leaves them near 1e-12 or below, which
   // puts the column norms (the singular values) within about 1e-16 relative
   // and the accumulated rotations within about 1e-12 of the converged ones;
   // the sweeps after it only confirm that, and are skipped
-  const double quiet = 1e-6;
+  // round-robin pairs: slot k starts with (k, lp2 - 1 - k); every index but 0
+  // advances by one per round, cyclically through 1 .. lp2 - 1
+  const int P = lp2 - 1;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
     __syncthreads();
@@ -222,21 +229,17 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
       s_big = 0;
     }
     __syncthreads();
-    for (int r = 0; r < lp2 - 1; ++r) {
-      int p = 0, q = 0;
-      if (active) {
-        const int a = k, b = lp2 - 1 - k;
-        p = (a == 0) ? 0 : 1 + (a - 1 + r) % (lp2 - 1);
-        q = (b == 0) ? 0 : 1 + (b - 1 + r) % (lp2 - 1);
-      }
+    int p = active ? k : 0, q = active ? P - k : 0;
+    for (int r = 0; r < P; ++r, p = (p == 0) ? 0 : (p == P ? 1 : p + 1),
+             q = (q == 0) ? 0 : (q == P ? 1 : q + 1)) {
       const bool go = active && p < l && q < l;
       double mp[RPT], mq[RPT];
       double al = 0.0, be = 0.0, ga = 0.0;
       if (go) {
 #pragma unroll
         for (int u = 0; u < RPT; u += 2) {
-          const double2 x = *reinterpret_cast<const double2*>(Mc + p * CS + i0 + u);
-          const double2 y = *reinterpret_cast<const double2*>(Mc + q * CS + i0 + u);
+          const double2 x = *reinterpret_cast<const double2*>(Mc + p * CS + i0 + u * G);
+          const double2 y = *reinterpret_cast<const double2*>(Mc + q * CS + i0 + u * G);
           mp[u] = x.x; mp[u + 1] = x.y;
           mq[u] = y.x; mq[u + 1] = y.y;
         }
@@ -255,17 +258,19 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
       if (go && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
         // Rutishauser's rotation, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
         // with zeta = (be - al) / (2 ga), evaluated as
-        // t = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (one
-        // reciprocal fewer on the critical path); reciprocals and square
-        // roots from the hardware approximations refined by Newton steps
-        // (rcp_nr, rsqrt_nr)
+        // t = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al.  t needs
+        // only the hardware reciprocal and square-root approximations (about
+        // 22 bits: the rotation then removes all but ~1e-6 of ga, and the
+        // next sweep the rest); c = 1/sqrt(1 + t^2) is refined by Newton
+        // steps, so (c, s = c t) is orthogonal to rounding whatever t is and
+        // the column norms are preserved
         const double d = be - al;
         double t;
         if (fabs(d) < 1e150 && fabs(ga) < 1e150) {
           const double h2 = fma(d, d, 4.0 * ga * ga);
-          const double h = h2 * rsqrt_nr(h2);
+          const double h = h2 * __builtin_amdgcn_rsq(h2);
           // sign(zeta) = sign(d) sign(ga), with d = +0 counting as positive
-          t = copysign(2.0 * fabs(ga) * rcp_nr(fabs(d) + h), d >= 0.0 ? ga : -ga);
+          t = copysign(2.0 * fabs(ga) * __builtin_amdgcn_rcp(fabs(d) + h), d >= 0.0 ? ga : -ga);
         } else {  // huge entries: the zeta form, which cannot overflow in h2
           const double zeta = d * (0.5 * rcp_nr(ga));
           t = (fabs(zeta) < 1e150)
@@ -275,16 +280,16 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ M, int l,
         const double c = rsqrt_nr(fma(t, t, 1.0)), s = c * t;
 #pragma unroll
         for (int u = 0; u < RPT; u += 2) {
-          *reinterpret_cast<double2*>(Mc + p * CS + i0 + u) =
+          *reinterpret_cast<double2*>(Mc + p * CS + i0 + u * G) =
               make_double2(c * mp[u] - s * mq[u], c * mp[u + 1] - s * mq[u + 1]);
-          *reinterpret_cast<double2*>(Mc + q * CS + i0 + u) =
+          *reinterpret_cast<double2*>(Mc + q * CS + i0 + u * G) =
               make_double2(s * mp[u] + c * mq[u], s * mp[u + 1] + c * mq[u + 1]);
           if constexpr (ACC) {
-            const double2 vp = *reinterpret_cast<const double2*>(Vc + p * CS + i0 + u);
-            const double2 vq = *reinterpret_cast<const double2*>(Vc + q * CS + i0 + u);
-            *reinterpret_cast<double2*>(Vc + p * CS + i0 + u) =
+            const double2 vp = *reinterpret_cast<const double2*>(Vc + p * CS + i0 + u * G);
+            const double2 vq = *reinterpret_cast<const double2*>(Vc + q * CS + i0 + u * G);
+            *reinterpret_cast<double2*>(Vc + p * CS + i0 + u * G) =
                 make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
-            *reinterpret_cast<double2*>(Vc + q * CS + i0 + u) =
+            *reinterpret_cast<double2*>(Vc + q * CS + i0 + u * G) =
                 make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
           }
         }
