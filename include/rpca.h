@@ -103,11 +103,18 @@ enum {
   RPCA_RENORM_LU = 16u, /* renormalize by pivoted LU (Q = P L, tournament
                            pivoting) after every application but the last --
                            the paper's choice (Section 5)                     */
-  RPCA_OMEGA_UNIFORM = 32u /* draw the test matrix Omega uniformly on (-1, 1)
+  RPCA_OMEGA_UNIFORM = 32u, /* draw the test matrix Omega uniformly on (-1, 1)
                            (rpca_uniform) instead of from N(0, 1): Section 5
                            notes the method does not depend on the law, and
                            each 32-bit word then gives one entry (no
                            transcendental functions)                          */
+  RPCA_NYSTROM_SQRT = 64u /* rpca_eig_psd: stabilize by the self-adjoint square
+                           root of B2 and a regularized pseudoinverse (Section
+                           3's first remedy) instead of the shifted Cholesky
+                           factor: B2 = W diag(w) W^T, F = B1 W diag(w)^-1/2
+                           over the w above sqrt(n) u ||B1||_F (the shift's
+                           scale), lambda = the squared singular values of F.
+                           Never reports RPCA_ERR_NOT_PSD.                    */
 };
 /* Renormalization between applications of A and A* (Sections 2 and 5).
  * Each is right-multiplication by an invertible l x l matrix, so the span and
@@ -180,6 +187,17 @@ rpca_status rpca_svd_noalloc(rpca_ctx ctx, const rpca_matrix* A, int k, int l, i
 rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
                          uint64_t seed, unsigned flags, float* U, int64_t ldu,
                          double* lambda);
+
+/* Rayleigh-Ritz eigenpairs of a general self-adjoint n x n A (positive,
+ * negative or indefinite), after the self-adjoint core loop of Section 5
+ * (A applied ``its`` times to Omega with renormalization, the last an
+ * orthonormalization): B2 = Q* A Q = W diag(lambda) W*, U = Q W.  Returns the
+ * k eigenpairs largest in magnitude: U (n x k) and lambda (k, signed,
+ * ordered by |lambda| descending) with A ~ U diag(lambda) U*.  Flags as for
+ * rpca_eig_psd (not RPCA_NYSTROM_SQRT).  With eigenvalues of equal magnitude
+ * and opposite signs among the k, the pair's vectors are not separated. */
+rpca_status rpca_eig_sym(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
+                         uint64_t seed, unsigned flags, float* U, int64_t ldu, double* lambda);
 
 /* One problem of a batch (rpca_svd_batched).  kind 0: rpca_svd of A with
  * outputs U, S, V; kind 1: rpca_eig_psd of A with outputs U and S (the

@@ -27,6 +27,9 @@ Readings of the paper taken here:
 The alternative of the paper (a self-adjoint square root of B2 from its
 eigendecomposition, with a regularized pseudoinverse) is ``eig_psd_sqrt``;
 in exact arithmetic both give the same approximation A_hat = B1 B2^+ B1*.
+For a self-adjoint A that is not definite, ``eig_sym`` gives the
+Rayleigh-Ritz eigenpairs Q W diag(lambda) (Q W)* with B2 = Q* A Q =
+W diag(lambda) W*, Q from the same core loop.
 
 Pins (tests/test_oracle_nystrom.py): exactness when rank(A) <= l; the
 eigenvalue bounds lambda_hat_j <= lambda_j and A - A_hat >= 0 (Loewner order)
@@ -99,11 +102,14 @@ def eig_psd(A, k, l, its, omega, u_A=2.0 ** -24, max_retries=10, A_range=None):
     return U, lam[:k], nu, retry
 
 
-def eig_psd_sqrt(A, k, l, its, omega, rcond=1e-13):
+def eig_psd_sqrt(A, k, l, its, omega, rcond=1e-13, u_A=None):
     """The self-adjoint square-root form of Section 3 (no shift).
 
     C = B2^(1/2) from the eigendecomposition of B2, F = B1 C^+ with the
-    pseudoinverse regularized by discarding eigenvalues below rcond * max.
+    pseudoinverse regularized by discarding the eigenvalues below
+    rcond * max, or, when ``u_A`` is given, below the shift's scale
+    sqrt(n) u_A ||B1||_F (the size of the rounding B2 carries when B1 = A Q is
+    computed with unit roundoff u_A).
     """
     A = np.asarray(A, dtype=np.float64)
     Q = range_psd(A, l, its, omega)
@@ -111,9 +117,30 @@ def eig_psd_sqrt(A, k, l, its, omega, rcond=1e-13):
     B2 = Q.T @ B1
     B2 = 0.5 * (B2 + B2.T)
     w, X = np.linalg.eigh(B2)
-    keep = w > rcond * max(w.max(), 0.0)
+    if u_A is None:
+        keep = w > rcond * max(w.max(), 0.0)
+    else:
+        keep = w > shift0(B1, A.shape[0], u_A)
     Cpinv = (X[:, keep] / np.sqrt(w[keep])) @ X[:, keep].T
     F = B1 @ Cpinv
     U, S, _ = np.linalg.svd(F, full_matrices=False)
     U = sign_fix(U[:, :k])
     return U, (S ** 2)[:k]
+
+
+def eig_sym(A, k, l, its, omega, A_range=None):
+    """Rayleigh-Ritz eigenpairs of a general self-adjoint A.
+
+    Q from the self-adjoint core loop of Section 5, B2 = Q* A Q (symmetrized)
+    = W diag(lambda) W*, U = Q W; the k eigenvalues largest in magnitude
+    (signed, ordered by |lambda| descending), each eigenvector signed so that
+    its largest-magnitude entry is positive.  Returns (U n x k, lambda k).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    Q = range_psd(A if A_range is None else A_range, l, its, omega)
+    B2 = Q.T @ (A @ Q)
+    B2 = 0.5 * (B2 + B2.T)
+    lam, W = np.linalg.eigh(B2)
+    order = np.argsort(-np.abs(lam), kind="stable")[:k]
+    U = sign_fix(Q @ W[:, order])
+    return U, lam[order]

@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rpca.h")
 F32, BF16, FP8_E4M3 = 0, 1, 2
 DENSE_ROWMAJOR, SPARSE_CSR = 0, 1
 CENTER, SYNC, DETERMINISTIC, RENORM_ORTH, RENORM_LU, OMEGA_UNIFORM = 1, 2, 4, 8, 16, 32
+NYSTROM_SQRT = 64
+_STAB = {"shift": 0, None: 0, "sqrt": NYSTROM_SQRT}
 _OMEGA = {"gaussian": 0, None: 0, "uniform": OMEGA_UNIFORM}
 # renormalization between applications: "chol" (one Cholesky QR pass, the
 # default), "lu" (pivoted LU, the paper's choice), "orth" (Cholesky QR twice)
@@ -138,6 +140,7 @@ _SIGS = {
     "rpca_svd_noalloc": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P,
                          P, I64],
     "rpca_eig_psd": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P],
+    "rpca_eig_sym": [P, ctypes.POINTER(Matrix), I32, I32, I32, U64, ctypes.c_uint, P, I64, P],
     "rpca_spectral_err": [P, ctypes.POINTER(Matrix), I32, P, I64, P, P, I64, I32, U64,
                           ctypes.c_uint, ctypes.POINTER(D)],
     "rpca_gaussian": [P, U64, U32, I64, I64, P, I64, P],
@@ -336,20 +339,37 @@ class Context:
         return U, S, V
 
     def eig_psd(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="chol",
-                deterministic=False, omega="gaussian"):
+                deterministic=False, omega="gaussian", stabilize="shift"):
         """U (n x k), lambda (k, float64) with U diag(lambda) U^T ~ A (PSD A).
 
-        sync: wait for the device and raise RpcaError(RPCA_ERR_NOT_PSD) when the
-        shifted Cholesky factor was never found (else that surfaces at the next
-        synchronizing call, see ``sync``)."""
+        stabilize: "shift" (shifted Cholesky factor) or "sqrt" (self-adjoint
+        square root with a regularized pseudoinverse).  sync: wait for the
+        device and raise RpcaError(RPCA_ERR_NOT_PSD) when the shifted Cholesky
+        factor was never found (else that surfaces at the next synchronizing
+        call, see ``sync``)."""
         torch = self._torch
         mat, n, _ = _as_mat(A, mat)
         l = k + 2 if l is None else l
         U = torch.empty(n, k, device="cuda", dtype=torch.float32)
         lam = torch.empty(k, device="cuda", dtype=torch.float64)
-        flags = (SYNC if sync else 0) | _RENORM[renorm]
+        flags = (SYNC if sync else 0) | _RENORM[renorm] | _STAB[stabilize]
         flags |= (DETERMINISTIC if deterministic else 0) | _OMEGA[omega]
         self._check(self.lib.rpca_eig_psd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
+                                          _ptr(U), U.stride(0), _ptr(lam)))
+        return U, lam
+
+    def eig_sym(self, A, k, l=None, its=2, seed=0, sync=False, mat=None, renorm="chol",
+                deterministic=False, omega="gaussian"):
+        """U (n x k), lambda (k, float64, signed, by |lambda| descending) with
+        U diag(lambda) U^T ~ A for a general symmetric A."""
+        torch = self._torch
+        mat, n, _ = _as_mat(A, mat)
+        l = k + 2 if l is None else l
+        U = torch.empty(n, k, device="cuda", dtype=torch.float32)
+        lam = torch.empty(k, device="cuda", dtype=torch.float64)
+        flags = (SYNC if sync else 0) | _RENORM[renorm] | _OMEGA[omega]
+        flags |= DETERMINISTIC if deterministic else 0
+        self._check(self.lib.rpca_eig_sym(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                           _ptr(U), U.stride(0), _ptr(lam)))
         return U, lam
 
@@ -413,7 +433,7 @@ class Context:
             q.k, q.l, q.its = k, l, int(pr.get("its", 2))
             q.seed = int(pr.get("seed", 0))
             q.flags = ((CENTER if pr.get("center") else 0) | _RENORM[pr.get("renorm")]
-                       | _OMEGA[pr.get("omega")])
+                       | _OMEGA[pr.get("omega")] | _STAB[pr.get("stabilize")])
             q.A = ctypes.cast(ctypes.pointer(mat), ctypes.c_void_p)
             q.U, q.ldu = U.data_ptr(), U.stride(0)
             q.S = S.data_ptr()

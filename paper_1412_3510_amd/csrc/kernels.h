@@ -177,6 +177,16 @@ void launch_jacobi_svd(hipStream_t st, const double* M, int l, int lp, int trans
 void launch_finish_values(hipStream_t st, const double* s, int k, const double* nu, double* out,
                           const int* state, int* status, int* slot);
 
+// Self-adjoint variants: G <- (G + G^T)/2; the pseudoinverse factor
+// M = W diag(s^-1/2) over the s_j above n_sqrt_u * sqrt(fro2[0]) (Section 3,
+// square-root stabilization); eigenvalues lambda_j = s_j sign(w_j . x_j) of a
+// symmetric matrix from its SVD (out[j], j < k), with the solve's status.
+void launch_symmetrize(hipStream_t st, double* G, int l, int lp);
+void launch_sqrt_pinv(hipStream_t st, const double* W, const double* s, int l, int lp,
+                      const double* fro2, double n_sqrt_u, double* M);
+void launch_sym_eig_finish(hipStream_t st, const double* s, const double* W, const double* X, int l,
+                           int k, int lp, double* out, const int* state, int* status, int* slot);
+
 // ---- spectral-norm estimate (spectral.hip) -------------------------------------
 // a sparse A for the error estimate: CSR (ptr, idx, val) and CSC (ptr_t, ...)
 struct SpecSparse {

@@ -819,13 +819,15 @@ namespace {
 // slot (nullable, device): the problem's status entry in a batch.  Whether
 // the shifted factor was found is known on the device only: it reaches the
 // caller at the next synchronizing call (RPCA_SYNC here, rpca_sync, ...).
+// sym: the Rayleigh-Ritz eigenpairs of a general self-adjoint A (rpca_eig_sym)
+// instead of the Nystrom method
 rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its,
                          uint64_t seed, unsigned flags, float* U, int64_t ldu, double* lambda,
-                         int* slot) {
+                         int* slot, bool sym = false) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
   rpca_status s = check_matrix(ctx, A, false);
   if (s != RPCA_OK) return s;
-  if (A->m != A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "eig_psd needs a square matrix");
+  if (A->m != A->n) return fail(ctx, RPCA_ERR_INVALID_ARG, "eig_psd / eig_sym need a square matrix");
   s = check_kl(ctx, k, l, A->m, A->n);
   if (s != RPCA_OK) return s;
   if (its < 0) return fail(ctx, RPCA_ERR_INVALID_ARG, "its must be >= 0");
@@ -853,15 +855,51 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
     if (it < its) renorm_mid(ctx, w, w.Y, n, flags & (RPCA_RENORM_ORTH | RPCA_RENORM_LU), seed);
     else orth_renorm(ctx, w, w.Y, n, false, seed);
   }
-  // B1 = A Q (start); B2 = Q* B1 (second), shifted; C = chol (Cholesky)
+  // B1 = A Q (start); B2 = Q* B1 (second)
   apply_A(ctx, A, Ar, w, w.Y, w.Y2);
   launch_fro2_d(st, w.Y2, w.lp, n, l, w.colpart, w.colpart2, w.scal);
   launch_gram(st, w.Y, w.lp, n, w.lp, w.Y2, w.lp, w.gpart, w.G, nullptr);
+  if (sym) {
+    // Rayleigh-Ritz for a self-adjoint A: B2 = W diag(lambda) W^T (Jacobi SVD
+    // of the symmetrized B2, signs from W^T X), U = Q W, the k eigenvalues
+    // largest in magnitude
+    launch_symmetrize(st, w.G, l, w.lp);
+    launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
+    launch_small_gemm(st, w.Y, w.lp, n, l, w.Wacc, w.lp, k, U, ldu, ctx->num_cus);
+    launch_sym_eig_finish(st, w.sv, w.Wacc, w.Xn, l, k, w.lp, lambda, w.state, ctx->dstat, slot);
+    launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
+    HIP_OK(hipGetLastError());
+    if (flags & RPCA_SYNC) return sync_status(ctx);
+    return RPCA_OK;
+  }
   // unit roundoff of the product B1 = A Q: a float32 A is multiplied as three
   // bfloat16 products of split operands (about 16 significant bits), a
   // bfloat16 / E4M3 copy with the operand rounded to bfloat16 (8 bits; 4 for
   // the E4M3 values themselves)
   const double u = std::ldexp(1.0, Ar.dtype == RPCA_F32 ? -16 : (Ar.dtype == RPCA_BF16 ? -8 : -4));
+  if (flags & RPCA_NYSTROM_SQRT) {
+    // Section 3's square-root stabilization: C = W diag(w)^1/2 W^T from the
+    // eigendecomposition B2 = W diag(w) W^T (Jacobi SVD of the symmetrized
+    // B2), F = B1 C^+ with the eigenvalues below the shift's scale
+    // sqrt(n) u ||B1||_F discarded.  F = (B1 W diag(w)^-1/2) W^T shares its
+    // left singular pairs with F' = B1 W diag(w)^-1/2: F' = QF R, R^T's
+    // Jacobi SVD, U = QF X, lambda = s^2.
+    launch_symmetrize(st, w.G, l, w.lp);
+    launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, l);
+    launch_sqrt_pinv(st, w.Wacc, w.sv, l, w.lp, w.scal, std::sqrt((double)n) * u, w.jwork);
+    launch_fill_zero(st, w.Y, n * w.lp);
+    launch_small_gemm(st, w.Y2, w.lp, n, l, w.jwork, w.lp, l, w.Y, w.lp, ctx->num_cus);
+    launch_fill_zero(st, reinterpret_cast<float*>(w.scal + 2), 4);  // no shift to remove
+    orth_renorm(ctx, w, w.Y, n, true, seed + 1);
+    launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
+    launch_small_gemm(st, w.Y, w.lp, n, l, w.Wacc, w.lp, k, U, ldu, ctx->num_cus);
+    launch_finish_values(st, w.sv, k, w.scal + 2, lambda, w.state, ctx->dstat, slot);
+    launch_sign_fix(st, U, ldu, n, k, nullptr, 0, 0, w.signwork);
+    HIP_OK(hipGetLastError());
+    if (flags & RPCA_SYNC) return sync_status(ctx);
+    return RPCA_OK;
+  }
+  // the shift nu; C = chol(B2 + nu I) (Cholesky)
   launch_chol_nystrom(st, w.G, l, w.lp, w.scal, std::sqrt((double)n) * u, w.Rf, w.scal + 1,
                       w.nu_f, w.state, ctx->nys_retries);
   // F = (B1 + nu Q) C^-1 (pseudo), then its SVD: F = QF RF, RF^T = ...
@@ -882,6 +920,13 @@ extern "C" {
 rpca_status rpca_eig_psd(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
                          unsigned flags, float* U, int64_t ldu, double* lambda) {
   return eig_psd_impl(ctx, A, k, l, its, seed, flags, U, ldu, lambda, nullptr);
+}
+
+rpca_status rpca_eig_sym(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, uint64_t seed,
+                         unsigned flags, float* U, int64_t ldu, double* lambda) {
+  if (flags & RPCA_NYSTROM_SQRT)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "eig_sym: RPCA_NYSTROM_SQRT applies to eig_psd");
+  return eig_psd_impl(ctx, A, k, l, its, seed, flags, U, ldu, lambda, nullptr, true);
 }
 
 rpca_status rpca_spectral_err(rpca_ctx ctx, const rpca_matrix* A, int k, const float* U,
@@ -1187,7 +1232,8 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     const rpca_problem& q = problems[p];
     const int l = q.l > 0 ? q.l : q.k + 2;
     const bool ok = ctx->batch_mode == 0 && !is_sparse(q.A) && q.A->dtype == RPCA_F32 &&
-                    l <= kPersMaxL && q.A->m <= kPersMaxDim && q.A->n <= kPersMaxDim;
+                    l <= kPersMaxL && q.A->m <= kPersMaxDim && q.A->n <= kPersMaxDim &&
+                    !(q.flags & RPCA_NYSTROM_SQRT);
     (ok ? pers : rest).push_back(p);
   }
   const int ns = std::min(kSlots, (int)rest.size());
@@ -1296,7 +1342,8 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     ctx->counters = sl.counters;
     ctx->counters_n = sl.counters_n;
     const unsigned f =
-        (q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH | RPCA_RENORM_LU | RPCA_OMEGA_UNIFORM)) |
+        (q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH | RPCA_RENORM_LU | RPCA_OMEGA_UNIFORM |
+                    RPCA_NYSTROM_SQRT)) |
         (flags & RPCA_DETERMINISTIC);
     if (q.kind == 0)
       res = svd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, q.V, q.ldv,

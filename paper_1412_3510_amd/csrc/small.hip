@@ -243,4 +243,79 @@ void launch_finish_values(hipStream_t st, const double* s, int k, const double* 
                      status, slot);
 }
 
+// ------------------------------------------------------------------------
+// Self-adjoint variants (Section 3's square-root stabilization; the
+// Rayleigh-Ritz eigenpairs of a general self-adjoint A).
+// ------------------------------------------------------------------------
+// G (l x l, stride lp) <- (G + G^T) / 2
+__global__ void __launch_bounds__(256) symmetrize_kernel(double* __restrict__ G, int l, int lp) {
+  for (int e = threadIdx.x; e < l * l; e += 256) {
+    const int i = e / l, j = e % l;
+    if (i < j) {
+      const double a = 0.5 * (G[i * lp + j] + G[j * lp + i]);
+      G[i * lp + j] = a;
+      G[j * lp + i] = a;
+    }
+  }
+}
+
+void launch_symmetrize(hipStream_t st, double* G, int l, int lp) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(1), dim3(256), 0, st, G, l, lp);
+}
+
+// M = W diag(w_j^-1/2) over the eigenvalues w_j = s[j] above the cut
+// n_sqrt_u * sqrt(fro2[0]) (zero columns for the others): the regularized
+// pseudoinverse of the self-adjoint square root C = W diag(w^1/2) W^T of
+// B2, applied as B1 C^+ = (B1 M) W^T.  W, M: lp x lp, row-major.
+__global__ void __launch_bounds__(256) sqrt_pinv_kernel(const double* __restrict__ W,
+                                                        const double* __restrict__ s, int l, int lp,
+                                                        const double* __restrict__ fro2,
+                                                        double n_sqrt_u, double* __restrict__ M) {
+  const double cut = n_sqrt_u * sqrt(fro2[0]);
+  for (int e = threadIdx.x; e < lp * lp; e += 256) {
+    const int i = e / lp, j = e % lp;
+    double v = 0.0;
+    if (i < l && j < l && s[j] > cut) v = W[i * lp + j] * rsqrt_nr(s[j]);
+    M[e] = v;
+  }
+}
+
+void launch_sqrt_pinv(hipStream_t st, const double* W, const double* s, int l, int lp,
+                      const double* fro2, double n_sqrt_u, double* M) {
+  hipLaunchKernelGGL(sqrt_pinv_kernel, dim3(1), dim3(256), 0, st, W, s, l, lp, fro2, n_sqrt_u, M);
+}
+
+// Eigenvalues of a symmetric M from its SVD M W = X diag(s): for an
+// eigenvector w_j, M w_j = lambda_j w_j, so x_j = sign(lambda_j) w_j and
+// lambda_j = s_j sign(w_j . x_j); out[j] for j < k (ordered by |lambda|).
+// The status of the solve goes to status / slot as in finish_values_kernel.
+__global__ void __launch_bounds__(128) sym_eig_finish_kernel(
+    const double* __restrict__ s, const double* __restrict__ W, const double* __restrict__ X,
+    int l, int k, int lp, double* __restrict__ out, const int* __restrict__ state,
+    int* __restrict__ status, int* __restrict__ slot) {
+  __shared__ int bad;
+  const int j = threadIdx.x;
+  if (j == 0) bad = 0;
+  __syncthreads();
+  if (j < k) {
+    double d = 0.0;
+    for (int i = 0; i < l; ++i) d += W[i * lp + j] * X[i * lp + j];
+    out[j] = (d < 0.0) ? -s[j] : s[j];
+    if (!isfinite(s[j])) bad = 1;
+  }
+  __syncthreads();
+  if (j == 0) {
+    int bits = bad ? kErrNonFinite : 0;
+    if (state && state[kStNonFinite]) bits |= kErrNonFinite;
+    if (status && bits) atomicOr(status, bits);
+    if (slot) *slot = bits;
+  }
+}
+
+void launch_sym_eig_finish(hipStream_t st, const double* s, const double* W, const double* X, int l,
+                           int k, int lp, double* out, const int* state, int* status, int* slot) {
+  hipLaunchKernelGGL(sym_eig_finish_kernel, dim3(1), dim3(128), 0, st, s, W, X, l, k, lp, out, state,
+                     status, slot);
+}
+
 }  // namespace rpca

@@ -103,3 +103,68 @@ def test_range_matrix_enters_only_through_its_span():
     U1, L1, _, _ = nystrom.eig_psd(A, k, l, 2, om, A_range=0.25 * A)
     np.testing.assert_allclose(L1, L0, rtol=1e-10)
     np.testing.assert_allclose(np.abs(U1.T @ U0), np.eye(k), atol=1e-8)
+
+
+# ---- the self-adjoint (not necessarily definite) Rayleigh-Ritz eigenpairs
+
+def _sym(n, lam, seed):
+    return dense.psd(n, lam, seed, dtype=np.float64)  # V diag(lam) V^T for any signs
+
+
+def test_eig_sym_exact_when_rank_at_most_l():
+    # an indefinite matrix of rank 8 <= l: the sketch spans its range exactly
+    n, k, l = 90, 6, 12
+    lam = np.zeros(n)
+    lam[:8] = [5.0, -4.0, 3.0, -2.5, 2.0, -1.0, 0.5, -0.25]
+    A = _sym(n, lam, 31)
+    U, L = nystrom.eig_sym(A, k, l, 2, philox.omega(3, n, l))
+    want = lam[np.argsort(-np.abs(lam), kind="stable")][:k]
+    np.testing.assert_allclose(L, want, rtol=1e-10)
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-12)
+    np.testing.assert_allclose(A @ U, U * L, atol=1e-10)
+
+
+def test_eig_sym_full_width_and_interlacing():
+    rng = np.random.default_rng(8)
+    n = 50
+    G = rng.standard_normal((n, n))
+    A = 0.5 * (G + G.T)
+    w = np.linalg.eigvalsh(A)
+    # l = n: every eigenpair exactly
+    U, L = nystrom.eig_sym(A, n, n, 1, philox.omega(4, n, n))
+    np.testing.assert_allclose(np.sort(L), w, atol=1e-10)
+    # l < n: the Ritz values lie inside the spectrum (Cauchy interlacing for
+    # Q* A Q): the j-th largest Ritz value is at most the j-th largest
+    # eigenvalue, the j-th smallest at least the j-th smallest
+    l = 12
+    Q = nystrom.range_psd(A, l, 2, philox.omega(5, n, l))
+    th = np.linalg.eigvalsh(Q.T @ A @ Q)
+    assert np.all(th[::-1] <= w[::-1][:l] + 1e-12)
+    assert np.all(th >= w[:l] - 1e-12)
+    _, L2 = nystrom.eig_sym(A, 5, l, 2, philox.omega(5, n, l))
+    th_by_mag = th[np.argsort(-np.abs(th), kind="stable")][:5]
+    np.testing.assert_allclose(L2, th_by_mag, rtol=1e-12)
+
+
+def test_eig_sym_on_psd_matches_rayleigh_ritz_bound():
+    # on a PSD matrix the Rayleigh-Ritz values never exceed the Nystrom ones
+    # (Nystrom's A_hat dominates Q Q* A Q Q* in the Loewner order)
+    n, k, l = 150, 8, 12
+    lam = dense.spectrum_exp(n)
+    A = dense.psd(n, lam, seed=12, dtype=np.float64)
+    om = philox.omega(6, n, l)
+    _, Lrr = nystrom.eig_sym(A, k, l, 1, om)
+    _, Lny = nystrom.eig_psd_sqrt(A, k, l, 1, om)
+    assert np.all(Lrr <= Lny + 1e-12)
+    assert np.all(Lny <= lam[:k] + 1e-12)
+
+
+def test_sqrt_form_with_rounding_cut():
+    # the cut sqrt(n) u ||B1||_F drops the null directions of a rank-10 A
+    # (l = 20) and keeps the result exact
+    n, r, k, l = 200, 10, 8, 20
+    lam = np.zeros(n)
+    lam[:r] = np.exp(-np.arange(1, r + 1) / 3.0)
+    A = dense.psd(n, lam, seed=13, dtype=np.float64)
+    U, L = nystrom.eig_psd_sqrt(A, k, l, 1, philox.omega(7, n, l), u_A=2.0 ** -16)
+    np.testing.assert_allclose(L, lam[:k], rtol=1e-9)
