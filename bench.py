@@ -57,6 +57,12 @@ def parse():
                    help="skip the autotuner (built-in tile configurations)")
     p.add_argument("--no-sparse", action="store_true",
                    help="skip the 10^6 x 10^6 sparse workload report")
+    p.add_argument("--sparse-only", action="store_true",
+                   help="run only the 10^6 x 10^6 sparse workload (for profiling it) and print "
+                        "its report")
+    p.add_argument("--no-noisy", action="store_true",
+                   help="skip the rank-4 noisy Gaussian workload (n = 10^5, its = 0, 2, 4)")
+    p.add_argument("--noisy-n", type=int, default=100000)
     p.add_argument("--renorm", choices=("chol", "lu", "orth"), default="chol",
                    help="renormalization between applications: one Cholesky QR pass (the "
                         "library's default), pivoted LU (the paper's) "
@@ -386,12 +392,64 @@ def sparse_workload(ctx, steps, renorm):
     except (OSError, ValueError, KeyError):
         sk1 = None
     err = ctx.spectral_err(S, U, Sv, V, iters=20, seed=7)
-    return {"workload": "CSR %dx%d, 10 distinct uniform columns per row, N(0,1) i^-1/2 values; "
-                        "k=%d l=%d its=%d" % (m, n, k, l, its),
-            "solves_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 4),
-            "passes": pass_rates(st), "err_estimate": err,
-            "err_over_sigma_k1": round(err / sk1, 5) if sk1 else None,
-            "generation_s": round(gen_s, 1)}
+    out = {"workload": "CSR %dx%d, 10 distinct uniform columns per row, N(0,1) i^-1/2 values; "
+                       "k=%d l=%d its=%d" % (m, n, k, l, its),
+           "solves_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 4),
+           "passes": pass_rates(st), "err_estimate": err,
+           "err_over_sigma_k1": round(err / sk1, 5) if sk1 else None,
+           "err_note": "FP64 power estimate (20 iterations, a lower bound) over sigma_{k+1} "
+                       "of the oracle run at l=60, its=8",
+           "generation_s": round(gen_s, 1)}
+    # the same matrix with bfloat16 values (half the value bytes per pass)
+    Sb = rp.csr(m, n, dev[0], dev[1], dev[2].to(torch.bfloat16), dev[3], dev[4],
+                dev[5].to(torch.bfloat16))
+    msb, stb = time_solves(ctx, Sb, k, l, its, seed, (U, Sv, V), None, steps, 2, renorm,
+                           center=False)
+    errb = ctx.spectral_err(Sb, U, Sv, V, iters=20, seed=7)
+    out["bf16_values"] = {"solves_per_s": round(1e3 / msb, 3), "ms_per_step": round(msb, 4),
+                          "speedup_vs_f32_values": round(ms / msb, 3),
+                          "passes": pass_rates(stb), "err_estimate": errb,
+                          "err_over_sigma_k1": round(errb / sk1, 5) if sk1 else None}
+    return out
+
+
+def noisy_workload(ctx, n, steps):
+    """The paper's second dense experiment (Section 7) at its largest size: an
+    n x n matrix of i.i.d. N(sqrt(30/n), 1) entries with signs flipped where
+    i*j is odd, rank-4 approximations with l = k + 2 and its = 0, 2, 4.  The
+    best rank-4 error is about ||A|| / 2; the library's FP64 power estimate
+    (a lower bound) of each error is reported over the largest computed
+    singular value."""
+    import torch
+    from synth import dense
+    t0 = time.perf_counter()
+    A = dense.noisy_gaussian_torch(n, seed=7000 + n, device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    k, l = 4, 6
+    U = torch.empty(n, k, device="cuda", dtype=torch.float32)
+    S = torch.empty(k, device="cuda", dtype=torch.float64)
+    V = torch.empty(n, k, device="cuda", dtype=torch.float32)
+    res = {"workload": "%dx%d N(sqrt(30/n),1), signs flipped where i*j is odd; k=4 l=6" % (n, n),
+           "generation_s": round(gen_s, 1)}
+    runs = {}
+    for its in (4, 2, 0):
+        ms, _ = time_solves(ctx, A, k, l, its, 100 + its, (U, S, V), None, steps, 1,
+                            center=False)
+        err = ctx.spectral_err(A, U, S, V, iters=20, seed=7)
+        runs[its] = (ms, err, float(S[0].item()), float(S[3].item()))
+    s1 = runs[4][2]
+    for its in (0, 2, 4):
+        ms, err, _, s4 = runs[its]
+        res["its=%d" % its] = {"ms_per_step": round(ms, 3), "err_estimate": round(err, 4),
+                               "err_over_sigma1": round(err / s1, 4),
+                               "err_over_its4": round(err / runs[4][1], 4),
+                               "sigma4": round(s4, 4)}
+    res["note"] = ("err_estimate: FP64 power method, 20 iterations (a lower bound); sigma1 "
+                   "from the its=4 solve; the best possible error is sigma_5, about sigma1/2")
+    del A, U, S, V
+    torch.cuda.empty_cache()
+    return res
 
 
 def batched_workload(ctx, steps):
@@ -502,6 +560,9 @@ def main():
     if args.precision_only:
         print(json.dumps(precision_form_full(rp.Context(), args.steps, args.renorm)), flush=True)
         return
+    if args.sparse_only:
+        print(json.dumps(sparse_workload(rp.Context(), args.steps, args.renorm)), flush=True)
+        return
     m, n, k, l, its = args.m, args.n, args.k, args.l, args.its
     sigma = dense.spectrum_tall(min(m, n))
     t0 = time.perf_counter()
@@ -611,6 +672,8 @@ def main():
         out["precision_form_on_timed_workload"] = prec
     if not args.no_sparse:
         out["sparse"] = sparse_workload(ctx, args.precision_steps, args.renorm)
+    if not args.no_noisy:
+        out["noisy_gaussian"] = noisy_workload(ctx, args.noisy_n, 3)
     bprobs = None
     if not args.no_batched:
         out["batched"], bprobs = batched_workload(ctx, 5)

@@ -8,7 +8,8 @@
     at l = 60, its = 8 (the sparse workload has no closed-form spectrum);
   * the GPU power estimate equals the oracle's from the same start block.
 The largest case is the 10^6 x 10^6 matrix with 10 entries per row
-(k = 20, l = 30, its = 4).
+(k = 20, l = 30, its = 4), with float32 and with bfloat16 values (the
+oracle then runs on the rounded values).
 """
 
 import numpy as np
@@ -104,6 +105,27 @@ def test_sparse_svd_full_size(ctx, gpu_lib):
     A, S = _make(gpu_lib, m, n, 10, seed=1004)
     ratio = _check(ctx, A, S, 20, 30, 4, seed=2004, iters=10, sk1=ref["sigma_k_plus_1"])
     print("err / sigma_{k+1} = %.4f" % ratio)
+
+
+@pytest.mark.parametrize("m,n,k,l,its", [(20000, 15000, 20, 30, 4), (8000, 30000, 10, 16, 2)])
+def test_sparse_svd_bf16_values(ctx, gpu_lib, m, n, k, l, its):
+    # bfloat16 values (widened exactly to float32 in the gather): the oracle
+    # runs on the same rounded values, so the float32 tolerance holds
+    A, S = _make(gpu_lib, m, n, 10, seed=m + n, bf16=True)
+    _check(ctx, A, S, k, l, its, seed=23)
+
+
+def test_sparse_svd_full_size_bf16_values(ctx, gpu_lib):
+    import json
+    import os
+    m = n = 1000000
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "sparse_1e6_sigma.json")))
+    A, S = _make(gpu_lib, m, n, 10, seed=1004, bf16=True)
+    # sigma_{k+1} of the float32-valued matrix; bfloat16 rounding of the values
+    # (2^-9 relative each) moves it by far less than the 10% margin
+    ratio = _check(ctx, A, S, 20, 30, 4, seed=2004, iters=10, sk1=ref["sigma_k_plus_1"])
+    print("bf16 values: err / sigma_{k+1} = %.4f" % ratio)
 
 
 def test_sparse_rejects_missing_transpose(ctx, gpu_lib):
