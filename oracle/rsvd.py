@@ -30,7 +30,11 @@ rank(A) <= l (brute force with numpy.linalg.svd, including the paper's
 diag(1,1,1,.999 x 17, 0, ...) matrices from Section 6); the closed-form
 spectrum of a centered construction; Cauchy interlacing and Eckart-Young
 bounds; orthonormality; equality of the LU and Householder variants (span
-invariance); near-optimal error on the six spectra of Section 7.
+invariance); near-optimal error on the six spectra of Section 7.  The
+schedule that renormalizes only after every second application (``fused``):
+exact at full width, the same range as the standard schedule where float64
+loses nothing by squaring, and the accuracy Section 5 says it gives up where
+the squared spectrum passes float64's resolution.
 """
 
 import numpy as np
@@ -65,7 +69,7 @@ def sign_fix(U, V=None):
     return U, V * s
 
 
-def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
+def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None, fused=False):
     """Rank-k approximation U diag(S) V^T of A (or of its column-centered form).
 
     A       -- m x n array (the exact values the device sees; upcast to float64),
@@ -78,6 +82,13 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
                ``matmul(X)`` = A X and ``rmatmul(Q)`` = A* Q (the precision
                form's low-precision copy, ``oracle.precision.LowPrecisionA``);
                the Rayleigh-Ritz product B = Q* A always uses A
+    fused   -- renormalize only after every second application (the
+               acceleration Section 5 describes and does not adopt): starting
+               from Q = omega, ``its`` times Z = A* (A Q) with no
+               renormalization between the two products, then Z renormalized;
+               then Y = A Q, orthonormalized by QR, and Rayleigh-Ritz as
+               usual.  The range is (A A*)^its A omega as without ``fused``;
+               its = 0 is the plain sketch either way
 
     Returns (U m x k, S length k, V n x k), all float64.
     """
@@ -115,6 +126,16 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
             return np.asarray(Q.T @ R).T
         return R.rmatmul(Q - Q.mean(axis=0, keepdims=True) if center else Q)
 
+    if fused and its > 0:
+        Q = omega
+        for it in range(1, its + 1):
+            # A* A Q with no renormalization in between (Section 5, last
+            # paragraph: renormalizing only in the odd-numbered iterations)
+            Q = mid(apply_t(apply(Q)))
+        # the last application is followed by the orthonormalizing QR
+        Q = qr_renorm(apply(Q))
+        return _rayleigh_ritz(A, Q, k)
+
     # Apply A to l random vectors (Section 2, range finder).
     Y = apply(omega)
     Q = qr_renorm(Y) if its == 0 else mid(Y)
@@ -126,6 +147,11 @@ def rsvd(A, k, l, its, omega, center=False, renorm="lu", A_range=None):
         # LU in all but the last iteration, QR in the last (Section 5).
         Q = mid(Y) if it < its else qr_renorm(Y)
 
+    return _rayleigh_ritz(A, Q, k)
+
+
+def _rayleigh_ritz(A, Q, k):
+    """Top k of B = Q* A and U = Q W (formulas (i2)-(i4)), signs fixed."""
     # B = Q* A, formula (i2); its SVD W Sigma V* = B, formula (i3).
     B = np.asarray(Q.T @ A)
     W, S, Vt = np.linalg.svd(B, full_matrices=False)

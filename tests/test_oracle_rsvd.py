@@ -192,3 +192,69 @@ def test_sparse_input_equals_dense_definition():
     with pytest.raises(ValueError):
         rsvd.rsvd(A, 10, 16, 3, om, center=True)
     assert sps.issparse(A)
+
+
+# ---- renormalizing only after every second application (Section 5) ----------
+
+
+@pytest.mark.parametrize("m,n,its", [(60, 40, 1), (40, 60, 2), (80, 30, 3)])
+def test_fused_full_width_sketch_is_exact_svd(m, n, its):
+    # l = min(m, n): whatever the renormalization schedule, the sketch spans
+    # the whole range and the result is the exact truncated SVD
+    rng = np.random.default_rng(m + n + its)
+    A = rng.standard_normal((m, n))
+    l = min(m, n)
+    k = l - 3
+    U, S, V = rsvd.rsvd(A, k, l, its, philox.omega(4, n, l), fused=True)
+    U0, S0, V0t = np.linalg.svd(A)
+    np.testing.assert_allclose(S, S0[:k], rtol=1e-11)
+    assert _proj_diff(U, U0[:, :k]) < 1e-9
+    assert _proj_diff(V, V0t[:k].T) < 1e-9
+
+
+@pytest.mark.parametrize("center", [False, True])
+@pytest.mark.parametrize("its", [1, 2, 3])
+@pytest.mark.parametrize("m,n", [(300, 120), (120, 300)])
+def test_fused_spans_the_same_krylov_range(m, n, its, center):
+    # A (A* A)^its Omega = (A A*)^its A Omega: in exact arithmetic the fused
+    # schedule sketches the same range as renormalizing after every
+    # application, so on a moderately graded spectrum (where float64 loses
+    # nothing by squaring) the results agree with the standard path's, for
+    # centered A too (a centering dropped from either product of A* A would
+    # change the range)
+    k, l = 8, 12
+    sig = dense.spectrum_small(min(m, n))
+    A = dense.dense(m, n, sig, seed=41, dtype=np.float64) + 0.05
+    om = philox.omega(6, n, l)
+    for renorm in ("lu", "qr"):
+        U0, S0, V0 = rsvd.rsvd(A, k, l, its, om, center=center, renorm=renorm)
+        U1, S1, V1 = rsvd.rsvd(A, k, l, its, om, center=center, renorm=renorm, fused=True)
+        np.testing.assert_allclose(S1, S0, rtol=1e-9)
+        np.testing.assert_allclose(U1, U0, atol=1e-7)
+        np.testing.assert_allclose(V1, V0, atol=1e-7)
+    # its = 0 is the plain sketch, identical either way
+    a = rsvd.rsvd(A, k, l, 0, om, center=center)
+    b = rsvd.rsvd(A, k, l, 0, om, center=center, fused=True)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_fused_schedule_costs_accuracy_on_a_wide_spectrum():
+    # Section 5 says the fused schedule gives up some accuracy.  Singular
+    # values 1, 0.1, ..., 1e-9 over a flat tail at 1e-10: after A* A the
+    # tenth direction sits at 1e-18 of the first, below float64's rounding of
+    # the product, so the unrenormalized product loses it, while
+    # renormalizing after every application keeps it (ratios of 1e-9 at most).
+    m, n, r, k, l = 200, 150, 10, 10, 12
+    sig = np.full(n, 1e-10)
+    sig[:r] = 10.0 ** (-np.arange(r))
+    A = dense.dense(m, n, sig, seed=17, dtype=np.float64)
+    om = philox.omega(7, n, l)
+    U0, S0, V0 = rsvd.rsvd(A, k, l, 2, om)
+    U1, S1, V1 = rsvd.rsvd(A, k, l, 2, om, fused=True)
+    assert spectral.spectral_err_exact(A, U0, S0, V0) < 1.01 * sig[k]
+    np.testing.assert_allclose(S0, sig[:k], rtol=1e-6)
+    assert spectral.spectral_err_exact(A, U1, S1, V1) > 3.0 * sig[k]
+    assert abs(S1[-1] - sig[k - 1]) > 0.05 * sig[k - 1]
+    # the leading values are still right
+    np.testing.assert_allclose(S1[:5], sig[:5], rtol=1e-8)
