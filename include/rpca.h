@@ -108,13 +108,27 @@ enum {
                            notes the method does not depend on the law, and
                            each 32-bit word then gives one entry (no
                            transcendental functions)                          */
-  RPCA_NYSTROM_SQRT = 64u /* rpca_eig_psd: stabilize by the self-adjoint square
+  RPCA_NYSTROM_SQRT = 64u, /* rpca_eig_psd: stabilize by the self-adjoint square
                            root of B2 and a regularized pseudoinverse (Section
                            3's first remedy) instead of the shifted Cholesky
                            factor: B2 = W diag(w) W^T, F = B1 W diag(w)^-1/2
                            over the w above sqrt(n) u ||B1||_F (the shift's
                            scale), lambda = the squared singular values of F.
                            Never reports RPCA_ERR_NOT_PSD.                    */
+  RPCA_FUSED_ATA = 128u /* rpca_svd: renormalize only after every second
+                           application (the acceleration Section 5 describes
+                           and the paper does not adopt): starting from Omega,
+                           its times Z = A_c^T (A_c Z) with no renormalization
+                           between the two products, then Z renormalized;
+                           then Y = A_c Z orthonormalized and Rayleigh-Ritz
+                           as usual.  The sketched range is the same in exact
+                           arithmetic; the squared spectrum of A^T A costs
+                           accuracy where sigma_j^2 / sigma_1^2 falls below
+                           the products' resolution (2^-16 for float32 A,
+                           2^-8 for a bfloat16 copy).  Where the shape allows,
+                           A^T A Z is formed in one read of A (row panels:
+                           Y_p = A_p Z, then Z += A_p^T Y_p).  Not for the
+                           self-adjoint entry points (RPCA_ERR_INVALID_ARG). */
 };
 /* Renormalization between applications of A and A* (Sections 2 and 5).
  * Each is right-multiplication by an invertible l x l matrix, so the span and

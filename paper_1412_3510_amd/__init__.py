@@ -23,6 +23,7 @@ F32, BF16, FP8_E4M3 = 0, 1, 2
 DENSE_ROWMAJOR, SPARSE_CSR = 0, 1
 CENTER, SYNC, DETERMINISTIC, RENORM_ORTH, RENORM_LU, OMEGA_UNIFORM = 1, 2, 4, 8, 16, 32
 NYSTROM_SQRT = 64
+FUSED_ATA = 128
 _STAB = {"shift": 0, None: 0, "sqrt": NYSTROM_SQRT}
 _OMEGA = {"gaussian": 0, None: 0, "uniform": OMEGA_UNIFORM}
 # renormalization between applications: "chol" (one Cholesky QR pass, the
@@ -313,10 +314,13 @@ class Context:
 
     # ---- solvers -------------------------------------------------------
     def svd(self, A, k, l=None, its=2, seed=0, center=False, sync=False, out=None, mat=None,
-            renorm="chol", deterministic=False, omega="gaussian"):
+            renorm="chol", deterministic=False, omega="gaussian", fused=False):
         """U (m x k), S (k, float64), V (n x k) with U diag(S) V^T ~ A (or A - 1 c).
 
         omega: the test matrix's law, "gaussian" or "uniform" (on (-1, 1)).
+
+        fused: renormalize only after every second application, so that each
+        power step is Z = A^T (A Z) (Section 5's optional acceleration).
 
         renorm: the renormalization between applications -- "chol" (one
         Cholesky QR pass, default), "lu" (pivoted LU, the paper's choice) or
@@ -334,6 +338,7 @@ class Context:
             U, S, V = out
         flags = (CENTER if center else 0) | (SYNC if sync else 0) | _RENORM[renorm]
         flags |= (DETERMINISTIC if deterministic else 0) | _OMEGA[omega]
+        flags |= FUSED_ATA if fused else 0
         self._check(self.lib.rpca_svd(self.h, ctypes.byref(mat), k, l, its, seed, flags,
                                       _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0)))
         return U, S, V
@@ -433,7 +438,8 @@ class Context:
             q.k, q.l, q.its = k, l, int(pr.get("its", 2))
             q.seed = int(pr.get("seed", 0))
             q.flags = ((CENTER if pr.get("center") else 0) | _RENORM[pr.get("renorm")]
-                       | _OMEGA[pr.get("omega")] | _STAB[pr.get("stabilize")])
+                       | _OMEGA[pr.get("omega")] | _STAB[pr.get("stabilize")]
+                       | (FUSED_ATA if pr.get("fused") else 0))
             q.A = ctypes.cast(ctypes.pointer(mat), ctypes.c_void_p)
             q.U, q.ldu = U.data_ptr(), U.stride(0)
             q.S = S.data_ptr()

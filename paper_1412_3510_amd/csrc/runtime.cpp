@@ -534,6 +534,14 @@ void apply_At(rpca_ctx ctx, const rpca_matrix* A, const AView& Av, Work& w, cons
   apply_at(ctx, Av, w, Z);
 }
 
+// Z (n x lp) <- A_c^T A_c Z: both products of a power step, with no
+// renormalization between them (RPCA_FUSED_ATA); w.Y holds A_c Z
+void apply_AtA(rpca_ctx ctx, const rpca_matrix* A, const AView& Av, Work& w, bool center) {
+  apply_A(ctx, A, Av, w, w.Z, w.Y);
+  if (center) center_rows(ctx, w, w.Y, A->m);
+  apply_At(ctx, A, Av, w, w.Y, w.Z, center);
+}
+
 rpca_status check_kl(rpca_ctx ctx, int k, int& l, int64_t m, int64_t n) {
   if (l <= 0) l = k + 2;
   if (k < 1) return fail(ctx, RPCA_ERR_INVALID_ARG, "k must be >= 1");
@@ -576,20 +584,33 @@ rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
   // Omega (n x l, zero padded to lp) -> packed right operand
   launch_fill_zero(st, w.Z, n * w.lp);
   launch_gaussian(st, seed, 0u, n, l, w.Z, w.lp, nullptr, (flags & RPCA_OMEGA_UNIFORM) != 0);
-  // Y = A Omega
-  apply_A(ctx, A, Av, w, w.Z, w.Y);
-  if (center) center_rows(ctx, w, w.Y, m);
-  if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
-  else mid_renorm(w.Y, m);
-  for (int it = 1; it <= its; ++it) {
-    // Z = A^T Q, renormalized by LU
-    apply_At(ctx, A, Av, w, w.Y, w.Z, center);
-    mid_renorm(w.Z, n);
-    // Y = A Q; LU except after the last application, which is orthonormalized
+  if ((flags & RPCA_FUSED_ATA) && its > 0) {
+    // Z = A_c^T A_c Z its times, renormalized after each; then Y = A_c Z,
+    // orthonormalized (Section 5, renormalizing every second application)
+    for (int it = 1; it <= its; ++it) {
+      apply_AtA(ctx, A, Av, w, center);
+      mid_renorm(w.Z, n);
+    }
     apply_A(ctx, A, Av, w, w.Z, w.Y);
     if (center) center_rows(ctx, w, w.Y, m);
-    if (it < its) mid_renorm(w.Y, m);
-    else orth_renorm(ctx, w, w.Y, m, false, seed);
+    orth_renorm(ctx, w, w.Y, m, false, seed);
+  } else {
+    // Y = A Omega
+    apply_A(ctx, A, Av, w, w.Z, w.Y);
+    if (center) center_rows(ctx, w, w.Y, m);
+    if (its == 0) orth_renorm(ctx, w, w.Y, m, false, seed);
+    else mid_renorm(w.Y, m);
+    for (int it = 1; it <= its; ++it) {
+      // Z = A^T Q, renormalized
+      apply_At(ctx, A, Av, w, w.Y, w.Z, center);
+      mid_renorm(w.Z, n);
+      // Y = A Q; renormalized except after the last application, which is
+      // orthonormalized
+      apply_A(ctx, A, Av, w, w.Z, w.Y);
+      if (center) center_rows(ctx, w, w.Y, m);
+      if (it < its) mid_renorm(w.Y, m);
+      else orth_renorm(ctx, w, w.Y, m, false, seed);
+    }
   }
   // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
   apply_At(ctx, A, Ar, w, w.Y, w.Z, center);
@@ -834,6 +855,8 @@ rpca_status eig_psd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int i
   if (!U || !lambda) return fail(ctx, RPCA_ERR_INVALID_ARG, "null output");
   if (ldu < k) return fail(ctx, RPCA_ERR_INVALID_ARG, "ldu must be >= k");
   if (flags & RPCA_CENTER) return fail(ctx, RPCA_ERR_INVALID_ARG, "centering does not apply to eig_psd");
+  if (flags & RPCA_FUSED_ATA)
+    return fail(ctx, RPCA_ERR_INVALID_ARG, "RPCA_FUSED_ATA applies to rpca_svd only");
   const int64_t n = A->n;
   Work w;
   s = prepare(ctx, w, n, n, l, true, layout_kind(A),
@@ -1233,7 +1256,7 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     const int l = q.l > 0 ? q.l : q.k + 2;
     const bool ok = ctx->batch_mode == 0 && !is_sparse(q.A) && q.A->dtype == RPCA_F32 &&
                     l <= kPersMaxL && q.A->m <= kPersMaxDim && q.A->n <= kPersMaxDim &&
-                    !(q.flags & RPCA_NYSTROM_SQRT);
+                    !(q.flags & (RPCA_NYSTROM_SQRT | RPCA_FUSED_ATA));
     (ok ? pers : rest).push_back(p);
   }
   const int ns = std::min(kSlots, (int)rest.size());
@@ -1343,7 +1366,7 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
     ctx->counters_n = sl.counters_n;
     const unsigned f =
         (q.flags & (RPCA_CENTER | RPCA_RENORM_ORTH | RPCA_RENORM_LU | RPCA_OMEGA_UNIFORM |
-                    RPCA_NYSTROM_SQRT)) |
+                    RPCA_NYSTROM_SQRT | RPCA_FUSED_ATA)) |
         (flags & RPCA_DETERMINISTIC);
     if (q.kind == 0)
       res = svd_impl(ctx, q.A, q.k, q.l, q.its, q.seed, f, q.U, q.ldu, q.S, q.V, q.ldv,

@@ -34,3 +34,18 @@ def test_null_context_rejected():
     assert lib.rpca_destroy(None) == 1
     assert lib.rpca_set_timing(None, 1) == 1
     assert lib.rpca_svd(None, None, 1, 1, 0, 0, 0, None, 1, None, None, 1) == 1
+
+
+def test_flag_values_match_the_header():
+    import re
+    text = open(rp.HEADER).read()
+    enum = text[text.index("/* flags */"):]
+    enum = enum[:enum.index("};")]
+    vals = {name: int(v) for name, v in re.findall(r"RPCA_(\w+)\s*=\s*(\d+)u", enum)}
+    want = {"CENTER": rp.CENTER, "SYNC": rp.SYNC, "DETERMINISTIC": rp.DETERMINISTIC,
+            "RENORM_ORTH": rp.RENORM_ORTH, "RENORM_LU": rp.RENORM_LU,
+            "OMEGA_UNIFORM": rp.OMEGA_UNIFORM, "NYSTROM_SQRT": rp.NYSTROM_SQRT,
+            "FUSED_ATA": rp.FUSED_ATA}
+    assert vals == want
+    # one bit each
+    assert all(v & (v - 1) == 0 for v in vals.values()) and len(set(vals.values())) == len(vals)
