@@ -63,6 +63,11 @@ def parse():
     p.add_argument("--no-noisy", action="store_true",
                    help="skip the rank-4 noisy Gaussian workload (n = 10^5, its = 0, 2, 4)")
     p.add_argument("--noisy-n", type=int, default=100000)
+    p.add_argument("--no-fused", action="store_true",
+                   help="skip the schedule that renormalizes every second application")
+    p.add_argument("--no-fused-bf16-oracle", action="store_true",
+                   help="skip the oracle's bfloat16-copy solve of the fused schedule "
+                        "(about 20 s of host time)")
     p.add_argument("--renorm", choices=("chol", "lu", "orth"), default="chol",
                    help="renormalization between applications: one Cholesky QR pass (the "
                         "library's default), pivoted LU (the paper's) "
@@ -248,12 +253,13 @@ def cpu_baseline(A_gpu, k, l, its, seed, center, nsolves, S_gpu):
                       "NumPy + %s), median %.2f s" % (nsolves, A.shape[0], n, blas, med)}, rel
 
 
-def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="chol", center=True):
+def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="chol", center=True,
+                fused=False):
     """Warm up, then time ``steps`` solves on the stream with events; returns
     (ms per solve, library stats over the timed solves)."""
     import torch
     for _ in range(warmup):
-        ctx.svd(A, k, l, its, seed, center=center, out=out, mat=mat, renorm=renorm)
+        ctx.svd(A, k, l, its, seed, center=center, out=out, mat=mat, renorm=renorm, fused=fused)
     torch.cuda.synchronize()
     ctx.reset_stats()
     ctx.set_timing(True)
@@ -263,11 +269,68 @@ def time_solves(ctx, A, k, l, its, seed, out, mat, steps, warmup, renorm="chol",
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        ctx.svd(A, k, l, its, seed, center=center, out=out, mat=mat, renorm=renorm)
+        ctx.svd(A, k, l, its, seed, center=center, out=out, mat=mat, renorm=renorm, fused=fused)
     e1.record(stream)
     torch.cuda.synchronize()
     ctx.set_timing(False)
     return e0.elapsed_time(e1) / steps, ctx.stats()
+
+
+def fused_schedule(ctx, A, k, l, its, seed, sk1, ms_std, steps, renorm):
+    """The schedule that renormalizes only after every second application
+    (RPCA_FUSED_ATA) on the timed workload, with the float32 A and with a
+    bfloat16 copy in the range finder: ms per solve, the exact err /
+    sigma_{k+1}, A-passes per solve.  The oracle's errors for the same
+    schedule are added by the cpu_baseline leg."""
+    import torch
+    import paper_1412_3510_amd as rp
+    m, n = A.shape
+    U = torch.empty(m, k, device=A.device, dtype=torch.float32)
+    S = torch.empty(k, device=A.device, dtype=torch.float64)
+    V = torch.empty(n, k, device=A.device, dtype=torch.float32)
+    res = {"schedule": "its x (Z = A_c^T (A_c Z), renormalized), then Y = A_c Z "
+                       "orthonormalized; A^T A Z as two reads of A"}
+    for kind in ("f32", "bf16"):
+        if kind == "f32":
+            X, mat = A, rp.dense(A)
+        else:
+            X, sc = ctx.quantize(A, "bf16")
+            mat = rp.dense(X, col_scale=sc, A_f32=A)
+        ms, st = time_solves(ctx, X, k, l, its, seed, (U, S, V), mat, steps, 2, renorm,
+                             fused=True)
+        err = exact_residual_norm(A, U, S, V, center=True)
+        res[kind] = {"ms_per_step": round(ms, 4), "solves_per_s": round(1e3 / ms, 3),
+                     "speedup_vs_standard_f32": round(ms_std / ms, 3),
+                     "err_over_sigma_k1": round(err / sk1, 7),
+                     "a_passes_per_solve": round(st["a_passes"] / max(1, steps), 2)}
+    return res
+
+
+def oracle_fused(A_gpu, k, l, its, seed, sk1, with_bf16):
+    """The oracle's own error for the fused schedule on the timed workload (one
+    float64 solve each for the float32 A and, with ``with_bf16``, for the
+    bfloat16 copy as the precision form defines it), measured with the same
+    exact residual norm as the device's results."""
+    import torch
+    from oracle import philox, precision, rsvd
+    A = A_gpu.cpu().numpy()
+    n = A.shape[1]
+    om = philox.omega(seed, n, l)
+    out = {}
+    runs = [("f32", None)]
+    if with_bf16:
+        runs.append(("bf16", precision.LowPrecisionA(precision.to_bf16(A), None)))
+    for kind, op in runs:
+        t0 = time.perf_counter()
+        U0, S0, V0 = rsvd.rsvd(A, k, l, its, om, center=True, A_range=op, fused=True)
+        dt = time.perf_counter() - t0
+        dev = A_gpu.device
+        err = exact_residual_norm(A_gpu, torch.from_numpy(U0).to(dev),
+                                  torch.from_numpy(S0).to(dev), torch.from_numpy(V0).to(dev),
+                                  center=True)
+        out[kind] = {"err_over_sigma_k1": round(float(err) / sk1, 7), "seconds": round(dt, 1)}
+        del op
+    return out
 
 
 def pass_rates(st, suffix=""):
@@ -361,8 +424,23 @@ def precision_form_full(ctx, steps, renorm):
                      "sigma_rel_diff_vs_f32": round(float(np.max(np.abs(Sk - S32) / S32)), 7),
                      "passes_low_precision": pass_rates(st, "_lp"),
                      "passes_f32_rayleigh_ritz": pass_rates(st)}
+        if kind == "bf16":
+            msf, stf = time_solves(ctx, q, k, l, its, seed, (U, S, V), mat, steps, 1, renorm,
+                                   center=False, fused=True)
+            errf = exact_residual_norm(A, U, S, V)
+            res["bf16_fused"] = {"ms_per_step": round(msf, 4),
+                                 "speedup_vs_f32": round(ms32 / msf, 3),
+                                 "err_over_sigma_k1": round(errf / sk1, 5),
+                                 "sigma_rel_err": sigma_errors(S.cpu().numpy(), sig[:k])}
         del q, sc, mat
-    del A, U, S, V
+    mat = rp.dense(A)
+    msf, stf = time_solves(ctx, A, k, l, its, seed, (U, S, V), mat, steps, 1, renorm,
+                           center=False, fused=True)
+    errf = exact_residual_norm(A, U, S, V)
+    res["f32_fused"] = {"ms_per_step": round(msf, 4), "speedup_vs_f32": round(ms32 / msf, 3),
+                        "err_over_sigma_k1": round(errf / sk1, 5),
+                        "sigma_rel_err": sigma_errors(S.cpu().numpy(), sig[:k])}
+    del A, U, S, V, mat
     torch.cuda.empty_cache()
     return res
 
@@ -637,6 +715,10 @@ def main():
     sk1 = float(csig[k])
     err_f32 = exact_residual_norm(A, U, S, V, center=True)
     est_f32 = ctx.spectral_err(A, U, S, V, iters=30, seed=7, center=True)
+    fused = None
+    if not args.no_fused:
+        fused = fused_schedule(ctx, A, k, l, its, args.seed, sk1, ms_per_step,
+                               args.precision_steps, args.renorm)
     prec = None
     if not args.no_precision:
         prec = precision_form(ctx, A, k, l, its, args.seed, sk1, ms_per_step, err_f32,
@@ -667,6 +749,8 @@ def main():
                     "FP64 power estimate (30 iterations, a lower bound) gives %.6f"
                     % (est_f32 / sk1),
     }
+    if fused is not None:
+        out["fused_ata"] = fused
     if prec is not None:
         out["precision_form"] = precision_form_full(ctx, args.precision_steps, args.renorm)
         out["precision_form_on_timed_workload"] = prec
@@ -684,6 +768,9 @@ def main():
         if bprobs is not None:
             # the oracle on the batch's worst problems: its own error, for comparison
             out["batched"]["oracle_on_worst"] = cpu_oracle_worst(out["batched"], bprobs)
+        if fused is not None:
+            out["fused_ata"]["oracle"] = oracle_fused(A, k, l, its, args.seed, sk1,
+                                                      not args.no_fused_bf16_oracle)
     print(json.dumps(out), flush=True)
 
 
