@@ -43,7 +43,10 @@ typedef enum {
   RPCA_ERR_NO_MEMORY = 3,   /* workspace allocation failed or over the limit */
   RPCA_ERR_HIP = 4,         /* a HIP runtime call failed                     */
   RPCA_ERR_NOT_PSD = 5,     /* Nystrom: shifted B2 never positive definite   */
-  RPCA_ERR_NUMERICAL = 6    /* non-finite values met on the device           */
+  RPCA_ERR_NUMERICAL = 6,   /* non-finite values met on the device           */
+  RPCA_ERR_TIMEOUT = 7      /* a bounded device wait gave up: the workgroups
+                               sharing one batched problem were not on the
+                               device together (see rpca_set_batch_split)   */
 } rpca_status;
 
 typedef enum { RPCA_F32 = 0, RPCA_BF16 = 1, RPCA_FP8_E4M3 = 2 } rpca_dtype;
@@ -234,8 +237,8 @@ typedef struct {
  * anything is launched; device-side failures of single problems (a Nystrom
  * factor never found, non-finite values) are reported per problem by
  * rpca_batch_status and for the whole batch by the next synchronizing call
- * (RPCA_SYNC, rpca_sync), which returns RPCA_ERR_NOT_PSD or
- * RPCA_ERR_NUMERICAL; the other problems' outputs are valid.
+ * (RPCA_SYNC, rpca_sync), which returns RPCA_ERR_NOT_PSD, RPCA_ERR_NUMERICAL
+ * or RPCA_ERR_TIMEOUT (below); the other problems' outputs are valid.
  *
  * Problems with a dense float32 A, m, n <= 8192 and l <= 64 are solved by one
  * persistent launch on the context stream: each workgroup of 512 threads
@@ -250,6 +253,17 @@ typedef struct {
  * them (memory a larger buffer replaces is kept until rpca_destroy, for the
  * graphs that use it).  Calls that overlap on several streams share these
  * buffers and must not run at the same time.
+ *
+ * A problem whose single-workgroup time would set the batch's end (cost
+ * model below) is split over up to 8 workgroups
+ * (rpca_set_batch_split) that share its passes over A, its Gram matrices and
+ * triangular solves by row ranges and meet at a device counter between the
+ * steps; the split problems come first in the table and the launch has a
+ * workgroup for each of their shares, so they run together.  A share that
+ * waits too long (another kernel holding the device's compute units, e.g. a
+ * second batched call on another stream) gives up, and the problem reports
+ * RPCA_ERR_TIMEOUT.  Problems with the pivoted-LU renormalization are not
+ * split.
  *
  * The other problems (sparse, bfloat16/E4M3 storage, larger sizes), and every
  * problem after rpca_set_batch_mode(ctx, 1), run the single-problem kernels
@@ -269,9 +283,10 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
 
 /* Per-problem outcome of the last rpca_svd_batched call on the context
  * (synchronizes): status_host[i] (host, count <= that call's count) is
- * RPCA_OK, RPCA_ERR_NUMERICAL (non-finite values) or RPCA_ERR_NOT_PSD
- * (Nystrom factor never found) for problem i, in the order of the
- * problems array.  Does not clear what rpca_sync reports. */
+ * RPCA_OK, RPCA_ERR_NUMERICAL (non-finite values), RPCA_ERR_NOT_PSD
+ * (Nystrom factor never found) or RPCA_ERR_TIMEOUT (a problem split over
+ * workgroups whose shares did not run together) for problem i, in the order
+ * of the problems array.  Does not clear what rpca_sync reports. */
 rpca_status rpca_batch_status(rpca_ctx ctx, int32_t count, int32_t* status_host);
 
 /* Synchronize the context stream and report the device-side failures of the
@@ -374,6 +389,23 @@ rpca_status rpca_reset_stats(rpca_ctx ctx);
 /* Batched mode: 0 (default) solves the problems the persistent launch takes
  * there and the others on streams; 1 runs every problem on streams. */
 rpca_status rpca_set_batch_mode(rpca_ctx ctx, int32_t mode);
+/* Splitting of problems in the persistent launch: at most max_parts
+ * workgroups per problem (1 .. 16; 1 splits nothing; default 8); at least
+ * min_parts (1 .. max_parts; default 1, the cost model decides) for every
+ * problem that can be split (not LU-renormalized, 64 rows of its smaller side
+ * per share) as long as all shares fit in one round of the grid; and the
+ * polls of a share waiting for the others before it gives up (spin_limit >
+ * 0; 0 keeps the default of 2^22, about a second).  RPCA_ERR_INVALID_ARG
+ * outside those ranges.
+ *
+ * The cost model: a problem takes about 0.45 ms + 0.167 ns x passes x m x n
+ * + 1.21 ns x steps x (m + n) x lp on one workgroup (lp = 32 or 64; fitted
+ * on this device), and 0.9 ms + the variable part / g as one of g shares.
+ * Among a few split targets the host keeps the one whose simulated list
+ * schedule (the shares first, then the rest by decreasing cost, each to the
+ * first free workgroup) ends first. */
+rpca_status rpca_set_batch_split(rpca_ctx ctx, int32_t max_parts, int32_t min_parts,
+                                 int32_t spin_limit);
 
 /* Number of HIP streams rpca_svd_batched spreads a batch over (1..64,
  * default 8; each has its own workspace).  How many of them run at once is

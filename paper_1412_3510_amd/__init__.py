@@ -156,6 +156,7 @@ _SIGS = {
     "rpca_reset_stats": [P],
     "rpca_set_batch_streams": [P, I32],
     "rpca_set_batch_mode": [P, I32],
+    "rpca_set_batch_split": [P, I32, I32, I32],
     "rpca_batch_status": [P, I32, ctypes.POINTER(I32)],
     "rpca_sync": [P],
     "rpca_set_nystrom_retries": [P, I32],
@@ -517,6 +518,13 @@ class Context:
     def set_batch_mode(self, mode):
         """0: persistent launch for the problems it takes (default); 1: streams only."""
         self._check(self.lib.rpca_set_batch_mode(self.h, mode))
+
+    def set_batch_split(self, max_parts=8, min_parts=1, spin_limit=0):
+        """Problems of the persistent launch: at most ``max_parts`` workgroups
+        each (1: no splitting), at least ``min_parts`` for every problem that
+        can be split (1: the cost model decides); ``spin_limit`` polls before
+        a share stops waiting for the others (0: the default)."""
+        self._check(self.lib.rpca_set_batch_split(self.h, max_parts, min_parts, spin_limit))
 
     def set_batch_streams(self, n):
         """Streams svd_batched spreads a batch over (default 8)."""

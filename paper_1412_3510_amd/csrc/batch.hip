@@ -172,16 +172,19 @@ __device__ __forceinline__ unsigned long long abs_key(float v, int i) {
 }
 
 // ---- Omega: X (n x LP), X[i][c] = Omega[i][c] for c < l, 0 beyond ------------
+// (rows r0 .. r1 - 1 only: a workgroup of a team writes its own rows)
 template <int LP>
 __device__ __attribute__((noinline)) void p_omega(uint64_t seed, int n, int l, float* X_,
-                                                  int uniform) {
+                                                  int uniform, int r0, int r1) {
   seed = uni(seed);
   n = uni(n);
   l = uni(l);
   uniform = uni(uniform);
+  r0 = uni(r0);
+  r1 = uni(r1);
   auto X = as_global(uni(X_));
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * LP; e += NT)
+  for (int e = r0 * LP + tid; e < r1 * LP; e += NT)
     if ((e % LP) >= l) X[e] = 0.f;
   // element e = 4 t + q of the stream is Omega[e % n][e / n]
   const int64_t total = (int64_t)n * l, nb = (total + 3) / 4;
@@ -201,7 +204,7 @@ __device__ __attribute__((noinline)) void p_omega(uint64_t seed, int n, int l, f
       const int64_t e = 4 * t + q;
       if (e < total) {
         const int64_t j = e / n, i = e - j * n;
-        X[i * LP + j] = z[q];
+        if (i >= r0 && i < r1) X[i * LP + j] = z[q];
       }
     }
   }
@@ -862,19 +865,22 @@ __device__ __attribute__((noinline)) void p_trsm(float* X_, int rows, int l, con
   __syncthreads();
 }
 
-// Q (rows x LP): dependent columns (S.state mask) replaced by Gaussian ones
+// Q (rows x LP): dependent columns (S.state mask) replaced by Gaussian ones;
+// row r of Q is row r0 + r of the whole matrix (the counter of its entries)
 template <int LP>
-__device__ __attribute__((noinline)) void p_complete(float* Q_, int rows, int l, uint64_t seed) {
+__device__ __attribute__((noinline)) void p_complete(float* Q_, int rows, int l, uint64_t seed,
+                                                     int r0 = 0) {
   rows = uni(rows);
   l = uni(l);
   seed = uni(seed);
+  r0 = uni(r0);
   auto Q = as_global(uni(Q_));
   PLds& S = g_S;
   if (S.state[2] == 0) return;
   for (int e = threadIdx.x; e < rows * l; e += NT) {
     const int r = e / l, j = e % l;
     if ((((unsigned)S.state[8 + (j >> 5)]) >> (j & 31)) & 1u)
-      Q[(int64_t)r * LP + j] = philox_normal(seed, 3u, (uint64_t)r * 128u + (uint64_t)j);
+      Q[(int64_t)r * LP + j] = philox_normal(seed, 3u, (uint64_t)(r0 + r) * 128u + (uint64_t)j);
   }
   __syncthreads();
 }
@@ -1079,15 +1085,17 @@ __device__ __attribute__((noinline)) void p_status(const PersProblem& p, const d
   __syncthreads();
   if (threadIdx.x == 0) {
     int bits = S.state[kStNonFinite] ? kErrNonFinite : 0;
+    if (S.state[kStTeam]) bits |= kErrTimeout;
     if (!isfinite(nu)) bits |= kErrNonFinite;
     for (int j = 0; j < p.k; ++j)
       if (!isfinite(sv[j])) bits |= kErrNonFinite;
     if (p.kind == 1) {
       if (S.state[kStNotPsd]) bits |= kErrNotPsd;
-      if (p.gstatus) p.gstatus[1] = S.state[kStRetries];
+      if (p.gstatus && p.part == 0) p.gstatus[1] = S.state[kStRetries];
     }
     if (bits && p.gstatus) atomicOr(p.gstatus, bits);
-    if (p.status) *p.status = bits;
+    // the entry is zero when the batch starts; every workgroup of a team adds its bits
+    if (bits && p.status) atomicOr(p.status, bits);
   }
   __syncthreads();
 }
@@ -1114,7 +1122,7 @@ __device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b
     p_pack<LP>(b.Y, m, l, center, b.P);
     p_atx<LP>(A, p.lda, m, n, b.P, b.Z);
   };
-  p_omega<LP>(p.seed, n, l, b.Z, p.uniform);
+  p_omega<LP>(p.seed, n, l, b.Z, p.uniform, 0, n);
   apply_a(b.Z);
   if (p.its == 0) p_orth<LP>(b.Y, m, l, false, b.T, b.G, p.seed);
   else mid(b.Y, m);
@@ -1143,7 +1151,7 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
   const int n = p.n, l = p.l;
   float* Q = b.Y;
   float* Q2 = b.Z;
-  p_omega<LP>(p.seed, n, l, Q, p.uniform);
+  p_omega<LP>(p.seed, n, l, Q, p.uniform, 0, n);
   if (p.its == 0) p_orth<LP>(Q, n, l, false, b.T, b.G, p.seed);
   for (int it = 1; it <= p.its; ++it) {
     p_pack<LP>(Q, n, l, false, b.P);
@@ -1175,6 +1183,430 @@ __device__ __attribute__((noinline)) void solve_psd(const PersProblem& p, Buf& b
   p_sign(p.U, p.ldu, n, p.k, nullptr, 0, 0);
 }
 
+// ---- one problem over several workgroups (a team) ---------------------------
+// A problem that costs more than the batch's average share of a workgroup is
+// split by the host over ``parts`` workgroups.  Every team's entries come
+// first in the table and the grid holds all of them, so the workgroups of a
+// team are on the device together.  Each workgroup takes a range of rows (a
+// multiple of 64, never empty) on the m side and on the n side: its share of
+// Omega and of the packed operands, of the passes over A (A X over its m
+// rows; A^T X over its m rows into a partial that the team then sums by n
+// rows, in a fixed order), of the Gram matrices, the triangular solves,
+// U = Q W, V = Q2 X and the sign convention.  The l x l steps (Cholesky,
+// Jacobi) run in every workgroup of the team on the same summed Gram matrix,
+// so every workgroup takes the same branches.  The workgroups meet at an
+// arrival counter (team_sync); a wait is bounded, and a workgroup that gives
+// up marks the problem kErrTimeout and waits no more.
+
+struct TeamBufs {
+  float* Y;
+  float* Z;
+  float* T;
+  __bf16* P;
+  float* zpart;               // parts x np x 64
+  double* gpart;              // 2 x parts x 4096
+  double* vpart;              // 2 x parts x 64
+  unsigned long long* kpart;  // parts x 128 (keys, then signs)
+};
+
+// the layout team_floats (kernels.h) sizes
+__device__ __forceinline__ TeamBufs team_carve(float* sh, int parts, int64_t R, int64_t np) {
+  TeamBufs t;
+  t.Y = sh;
+  t.Z = sh + R * 64;
+  t.T = sh + 2 * R * 64;
+  t.P = reinterpret_cast<__bf16*>(sh + 3 * R * 64);
+  t.zpart = sh + 4 * R * 64;
+  double* d = reinterpret_cast<double*>(t.zpart + (int64_t)parts * np * 64);
+  t.gpart = d;
+  t.vpart = d + 2 * (int64_t)parts * 4096;
+  t.kpart = reinterpret_cast<unsigned long long*>(t.vpart + 2 * (int64_t)parts * 64);
+  return t;
+}
+
+// first row of part g of ``rows`` rows over ``parts`` (multiples of 64; with
+// parts <= rows / 64 every part is non-empty)
+__device__ __forceinline__ int part_row(int rows, int parts, int g) {
+  const int64_t r = ((int64_t)rows * g + parts - 1) / parts;
+  const int64_t a = (r + 63) / 64 * 64;
+  return (int)(a < rows ? a : rows);
+}
+
+__device__ __attribute__((noinline)) int p_state(int i) { return g_S.state[uni(i)]; }
+
+// Every workgroup of the team arrives (the k-th call of a solve waits for
+// k * parts arrivals); the writes of every workgroup before it are visible to
+// all after it.  At most spin_limit polls.
+__device__ __attribute__((noinline)) void team_sync(int* bar_, int target, int spin_limit) {
+  int* bar = uni(bar_);
+  target = uni(target);
+  spin_limit = uni(spin_limit);
+  PLds& S = g_S;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(bar, 1);
+    if (S.state[kStTeam] == 0) {
+      int spins = 0;
+      while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++spins >= spin_limit) {
+          S.state[kStTeam] = 1;
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// column sums (float64) of X (rows x LP) -> out[0 .. LP)
+template <int LP>
+__device__ __attribute__((noinline)) void p_colsum_part(const float* X_, int rows, int l,
+                                                        double* out_) {
+  rows = uni(rows);
+  l = uni(l);
+  auto X = as_global(uni(X_));
+  auto out = as_global(uni(out_));
+  PLds& S = g_S;
+  constexpr int NG = NT / LP;
+  const int tid = threadIdx.x, c = tid % LP, gi = tid / LP;
+  double s = 0.0;
+  if (c < l)
+    for (int r0 = gi; r0 < rows; r0 += 8 * NG) {  // eight loads in flight
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = X[(int64_t)min(r0 + j * NG, rows - 1) * LP + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (r0 + j * NG < rows) s += (double)v[j];
+    }
+  S.u.red[gi * LP + c] = s;
+  __syncthreads();
+  if (tid < LP) {
+    double t = 0.0;
+    for (int h = 0; h < NG; ++h) t += S.u.red[h * LP + tid];
+    out[tid] = t;
+  }
+  __syncthreads();
+}
+
+// S.mu = (the column sums of the parts, added in order) / rows
+template <int LP>
+__device__ __attribute__((noinline)) void p_mu_parts(const double* vp_, int parts, int rows,
+                                                     int l) {
+  auto vp = as_global(uni(vp_));
+  parts = uni(parts);
+  rows = uni(rows);
+  l = uni(l);
+  PLds& S = g_S;
+  if (threadIdx.x < LP) {
+    double t = 0.0;
+    for (int q = 0; q < parts; ++q) t += vp[q * 64 + threadIdx.x];
+    S.mu[threadIdx.x] = ((int)threadIdx.x < l && rows > 0) ? (float)(t / rows) : 0.f;
+  }
+  __syncthreads();
+}
+
+// G (LP x LP) = the partial Gram matrices of the parts (stride 4096), added in order
+template <int LP>
+__device__ __attribute__((noinline)) void p_sum_parts(const double* gp_, int parts, double* G_) {
+  auto gp = as_global(uni(gp_));
+  auto G = as_global(uni(G_));
+  parts = uni(parts);
+  for (int e = threadIdx.x; e < LP * LP; e += NT) {
+    double t = 0.0;
+    for (int q = 0; q < parts; ++q) t += gp[(int64_t)q * 4096 + e];
+    G[e] = t;
+  }
+  __syncthreads();
+}
+
+// one float64 value per part: write this part's (thread 0), or add all in order
+__device__ __attribute__((noinline)) void p_put_scalar(double* dst_, double v) {
+  auto dst = as_global(uni(dst_));
+  if (threadIdx.x == 0) *dst = v;
+  __syncthreads();
+}
+__device__ __attribute__((noinline)) double p_sum_scalars(const double* vp_, int parts) {
+  auto vp = as_global(uni(vp_));
+  parts = uni(parts);
+  double t = 0.0;
+  for (int q = 0; q < parts; ++q) t += vp[q * 64];
+  return t;
+}
+
+// Z rows r0 .. r1 - 1 = the A^T X partials of the parts (slot stride ``slot``
+// floats, row stride LP) added in order
+template <int LP>
+__device__ __attribute__((noinline)) void p_reduce_parts(const float* zp_, int parts, int64_t slot,
+                                                         int r0, int r1, float* Z_) {
+  auto zp = as_global(uni(zp_));
+  auto Z = as_global(uni(Z_));
+  parts = uni(parts);
+  slot = uni(slot);
+  r0 = uni(r0);
+  r1 = uni(r1);
+  const int64_t e1 = (int64_t)r1 * LP;
+  for (int64_t e = (int64_t)r0 * LP + 4 * threadIdx.x; e < e1; e += 4 * NT) {
+    f32x4 a = *reinterpret_cast<const GAS f32x4*>(zp + e);
+    for (int q = 1; q < parts; ++q) {
+      const f32x4 v = *reinterpret_cast<const GAS f32x4*>(zp + (int64_t)q * slot + e);
+      a.x += v.x;
+      a.y += v.y;
+      a.z += v.z;
+      a.w += v.w;
+    }
+    *reinterpret_cast<GAS f32x4*>(Z + e) = a;
+  }
+  __syncthreads();
+}
+
+// rows (x LP) of X copied to Y
+template <int LP>
+__device__ __attribute__((noinline)) void p_copy_rows(const float* X_, float* Y_, int rows) {
+  auto X = as_global(uni(X_));
+  auto Y = as_global(uni(Y_));
+  rows = uni(rows);
+  for (int e = threadIdx.x; e < rows * LP; e += NT) Y[e] = X[e];
+  __syncthreads();
+}
+
+// Sign convention over a team, first half: per column q < k the key of the
+// largest-magnitude entry among rows r0 .. r1 - 1 of U (ties to the smaller
+// row) -> kp[q], and that entry's sign -> kp[64 + q] (1 when negative)
+__device__ __attribute__((noinline)) void p_sign_key(const float* U_, int64_t ldu, int r0, int r1,
+                                                     int k, unsigned long long* kp_) {
+  auto U = as_global(uni(U_));
+  auto kp = as_global(uni(kp_));
+  ldu = uni(ldu);
+  r0 = uni(r0);
+  r1 = uni(r1);
+  k = uni(k);
+  PLds& S = g_S;
+  const int tid = threadIdx.x, q = tid & 63, gi = tid >> 6;
+  unsigned long long best = 0ull;
+  if (q < k)
+    for (int r = r0 + gi; r < r1; r += NWAVE) {
+      const unsigned long long key = abs_key(U[(int64_t)r * ldu + q], r);
+      best = key > best ? key : best;
+    }
+  S.u.kred[gi * 64 + q] = best;
+  __syncthreads();
+  if (tid < 64) {
+    unsigned long long bb = 0ull;
+    for (int h = 0; h < NWAVE; ++h) bb = S.u.kred[h * 64 + tid] > bb ? S.u.kred[h * 64 + tid] : bb;
+    kp[tid] = bb;
+    kp[64 + tid] = (tid < k && bb != 0ull && U[(int64_t)(int)(~(unsigned)bb) * ldu + tid] < 0.f)
+                       ? 1ull : 0ull;
+  }
+  __syncthreads();
+}
+
+// second half: the winning part's sign per column; this part's rows of U and V flipped
+__device__ __attribute__((noinline)) void p_sign_apply(const unsigned long long* kp_, int parts,
+                                                       float* U_, int64_t ldu, int k, int ur0,
+                                                       int ur1, float* V_, int64_t ldv, int vr0,
+                                                       int vr1) {
+  auto kp = as_global(uni(kp_));
+  auto U = as_global(uni(U_));
+  auto V = as_global(uni(V_));
+  parts = uni(parts);
+  ldu = uni(ldu);
+  k = uni(k);
+  ur0 = uni(ur0);
+  ur1 = uni(ur1);
+  ldv = uni(ldv);
+  vr0 = uni(vr0);
+  vr1 = uni(vr1);
+  PLds& S = g_S;
+  const int tid = threadIdx.x;
+  if (tid < k) {
+    unsigned long long bb = 0ull, neg = 0ull;
+    for (int q = 0; q < parts; ++q) {
+      const unsigned long long key = kp[q * 128 + tid];
+      if (key > bb) {
+        bb = key;
+        neg = kp[q * 128 + 64 + tid];
+      }
+    }
+    S.sgn[tid] = neg ? -1.f : 1.f;
+  }
+  __syncthreads();
+  for (int e = tid; e < (ur1 - ur0) * k; e += NT) {
+    const int r = ur0 + e / k, c = e % k;
+    if (S.sgn[c] < 0.f) U[(int64_t)r * ldu + c] = -U[(int64_t)r * ldu + c];
+  }
+  if (V)
+    for (int e = tid; e < (vr1 - vr0) * k; e += NT) {
+      const int r = vr0 + e / k, c = e % k;
+      if (S.sgn[c] < 0.f) V[(int64_t)r * ldv + c] = -V[(int64_t)r * ldv + c];
+    }
+  __syncthreads();
+}
+
+// The steps a team shares: the row ranges, the synchronization and the
+// partial sums of one solve.
+template <int LP>
+struct TeamRun {
+  const PersProblem& p;
+  Buf& b;
+  TeamBufs t;
+  int parts, g, spin, target, gsel, vsel;
+  int64_t np;
+  __device__ TeamRun(const PersProblem& p_, Buf& b_, int spin_limit) : p(p_), b(b_) {
+    parts = p.parts;
+    g = p.part;
+    spin = spin_limit;
+    target = gsel = vsel = 0;
+    np = round_up(p.n, 64);
+    t = team_carve(p.sh, parts, round_up(max(p.m, p.n), 64), np);
+  }
+  __device__ void sync() {
+    target += parts;
+    team_sync(p.bar, target, spin);
+  }
+  __device__ __bf16* packed(int r0) { return t.P + (int64_t)(r0 / 16) * (LP / 32) * 2 * 512; }
+  // S.mu = the column means of X (``rows`` rows; this part holds r0 .. r1 - 1)
+  __device__ void colmean(const float* X, int rows, int r0, int r1) {
+    double* vp = t.vpart + (int64_t)vsel * parts * 64;
+    vsel ^= 1;
+    p_colsum_part<LP>(X + (int64_t)r0 * LP, r1 - r0, p.l, vp + (int64_t)g * 64);
+    sync();
+    p_mu_parts<LP>(vp, parts, rows, p.l);
+  }
+  // a sum over all rows of a per-part float64 value
+  __device__ double scalar_sum(double v) {
+    double* vp = t.vpart + (int64_t)vsel * parts * 64;
+    vsel ^= 1;
+    p_put_scalar(vp + (int64_t)g * 64, v);
+    sync();
+    return p_sum_scalars(vp, parts);
+  }
+  // b.G = X^T X2 (X^T X when X2 is null) over all rows
+  __device__ void gram(const float* X, const float* X2, int r0, int r1) {
+    double* gp = t.gpart + (int64_t)gsel * parts * 4096;
+    gsel ^= 1;
+    p_gram<LP>(X + (int64_t)r0 * LP, X2 ? X2 + (int64_t)r0 * LP : nullptr, r1 - r0,
+               gp + (int64_t)g * 4096);
+    sync();
+    p_sum_parts<LP>(gp, parts, b.G);
+  }
+  // p_orth over the team (Cholesky QR; with want_r, b.G = Q^T X_in after)
+  __device__ void orth(float* X, int r0, int r1, bool want_r, uint64_t seed, bool single) {
+    if (want_r) p_copy_rows<LP>(X + (int64_t)r0 * LP, t.T + (int64_t)r0 * LP, r1 - r0);
+    for (int pass = 1; pass <= 4; ++pass) {
+      if (pass >= 3 && p_state(1) == 0) break;
+      if (pass == 2 && single && p_state(0) == 0) break;
+      gram(X, nullptr, r0, r1);
+      p_chol_qr<LP>(b.G, p.l, pass);
+      p_trsm<LP>(X + (int64_t)r0 * LP, r1 - r0, p.l, nullptr, 0.f);
+      if (pass == 2) p_complete<LP>(X + (int64_t)r0 * LP, r1 - r0, p.l, seed ^ 0x5bd1e995u, r0);
+    }
+    if (want_r) gram(X, t.T, r0, r1);
+  }
+  // out = A X for this part's rows r0 .. r1 of A, X (the n side, this part
+  // holding rows x0 .. x1) packed first
+  __device__ void ax(const float* X, int x0, int x1, float* out, int r0, int r1) {
+    p_pack<LP>(X + (int64_t)x0 * LP, x1 - x0, p.l, false, packed(x0));
+    sync();
+    p_ax<LP>(p.A + (int64_t)r0 * p.lda, p.lda, r1 - r0, p.n, t.P, out + (int64_t)r0 * LP);
+  }
+  // sign convention for U (rows ur0 .. ur1 of this part) and V
+  __device__ void sign(int ur0, int ur1, float* V, int vr0, int vr1) {
+    p_sign_key(p.U, p.ldu, ur0, ur1, p.k, t.kpart + (int64_t)g * 128);
+    sync();
+    p_sign_apply(t.kpart, parts, p.U, p.ldu, p.k, ur0, ur1, V, p.ldv, vr0, vr1);
+  }
+};
+
+template <int LP>
+__device__ __attribute__((noinline)) void team_svd(const PersProblem& p, Buf& b, int spin_limit) {
+  TeamRun<LP> T(p, b, spin_limit);
+  const int m = p.m, n = p.n, l = p.l, parts = p.parts, g = p.part;
+  const bool center = p.center != 0;
+  const int mr0 = part_row(m, parts, g), mr1 = part_row(m, parts, g + 1);
+  const int nr0 = part_row(n, parts, g), nr1 = part_row(n, parts, g + 1);
+  float* Y = T.t.Y;
+  float* Z = T.t.Z;
+  auto apply_a = [&]() {  // Y = A_c Z
+    T.ax(Z, nr0, nr1, Y, mr0, mr1);
+    if (center) {
+      T.colmean(Y, m, mr0, mr1);
+      p_sub_mu<LP>(Y + (int64_t)mr0 * LP, mr1 - mr0, l);
+    }
+  };
+  auto apply_at = [&]() {  // Z = A_c^T Y: partials over this part's m rows, summed by n rows
+    if (center) T.colmean(Y, m, mr0, mr1);
+    p_pack<LP>(Y + (int64_t)mr0 * LP, mr1 - mr0, l, center, T.packed(mr0));
+    T.sync();
+    float* zp = T.t.zpart + (int64_t)g * T.np * 64;
+    p_atx<LP>(p.A + (int64_t)mr0 * p.lda, p.lda, mr1 - mr0, n, T.packed(mr0), zp);
+    T.sync();
+    p_reduce_parts<LP>(T.t.zpart, parts, T.np * 64, nr0, nr1, Z);
+  };
+  // LU problems are not split: the renormalization is Cholesky QR
+  auto mid = [&](float* X, int r0, int r1) { T.orth(X, r0, r1, false, p.seed, p.mid == 0); };
+  p_omega<LP>(p.seed, n, l, Z, p.uniform, nr0, nr1);
+  apply_a();
+  if (p.its == 0) T.orth(Y, mr0, mr1, false, p.seed, false);
+  else mid(Y, mr0, mr1);
+  for (int it = 1; it <= p.its; ++it) {
+    apply_at();
+    mid(Z, nr0, nr1);
+    apply_a();
+    if (it < p.its) mid(Y, mr0, mr1);
+    else T.orth(Y, mr0, mr1, false, p.seed, false);
+  }
+  apply_at();
+  T.orth(Z, nr0, nr1, true, p.seed + 1, false);
+  jacobi_wg<LP>(b.G, l, 0, b);
+  p_small_gemm<LP>(Y + (int64_t)mr0 * LP, mr1 - mr0, l, b.Wacc, p.k, p.U + (int64_t)mr0 * p.ldu,
+                   p.ldu);
+  p_small_gemm<LP>(Z + (int64_t)nr0 * LP, nr1 - nr0, l, b.Xn, p.k, p.V + (int64_t)nr0 * p.ldv,
+                   p.ldv);
+  if (g == 0 && threadIdx.x < p.k) p.S[threadIdx.x] = b.sv[threadIdx.x];
+  T.sign(mr0, mr1, p.V, nr0, nr1);
+  p_status(p, b.sv, 0.0);
+}
+
+template <int LP>
+__device__ __attribute__((noinline)) void team_psd(const PersProblem& p, Buf& b, int max_retries,
+                                                   int spin_limit) {
+  TeamRun<LP> T(p, b, spin_limit);
+  const int n = p.n, l = p.l, parts = p.parts, g = p.part;
+  const int r0 = part_row(n, parts, g), r1 = part_row(n, parts, g + 1);
+  float* Q = T.t.Y;
+  float* Q2 = T.t.Z;
+  p_omega<LP>(p.seed, n, l, Q, p.uniform, r0, r1);
+  if (p.its == 0) T.orth(Q, r0, r1, false, p.seed, false);
+  for (int it = 1; it <= p.its; ++it) {
+    T.ax(Q, r0, r1, Q2, r0, r1);
+    float* t = Q;
+    Q = Q2;
+    Q2 = t;
+    T.orth(Q, r0, r1, false, p.seed, it < p.its && p.mid == 0);
+  }
+  // B1 = A Q (start); B2 = Q^T B1 (second), shifted; C = chol (Cholesky)
+  T.ax(Q, r0, r1, Q2, r0, r1);
+  const double fro2 = T.scalar_sum(p_fro2<LP>(Q2 + (int64_t)r0 * LP, r1 - r0, l));
+  T.gram(Q, Q2, r0, r1);
+  const double nu = p_chol_nystrom<LP>(b.G, l, fro2, sqrt((double)n) * 0x1p-16, max_retries);
+  // F = (B1 + nu Q) C^-1 (pseudo); U from the Jacobi SVD of F's R factor
+  p_trsm<LP>(Q2 + (int64_t)r0 * LP, r1 - r0, l, Q + (int64_t)r0 * LP, (float)nu);
+  T.orth(Q2, r0, r1, true, p.seed + 1, false);
+  jacobi_wg<LP>(b.G, l, 1, b);
+  p_small_gemm<LP>(Q2 + (int64_t)r0 * LP, r1 - r0, l, b.Wacc, p.k, p.U + (int64_t)r0 * p.ldu,
+                   p.ldu);
+  if (g == 0 && threadIdx.x < p.k) {
+    const double s = b.sv[threadIdx.x];
+    p.S[threadIdx.x] = fmax(s * s - nu, 0.0);
+  }
+  T.sign(r0, r1, nullptr, 0, 0);
+  p_status(p, b.sv, nu);
+}
+
 // The next problem index for the workgroup (the LDS block is only touched from
 // non-inlined routines: LDS used both by a kernel and by the functions it
 // calls would be allocated twice).
@@ -1191,13 +1623,21 @@ __device__ __attribute__((noinline)) int next_problem(int* counter) {
 __global__ void __launch_bounds__(NT) persistent_kernel(const PersProblem* __restrict__ probs,
                                                         int count, int* counter, float* ws,
                                                         int64_t slot_floats, int64_t R,
-                                                        int max_retries) {
+                                                        int max_retries, int spin_limit) {
   Buf b = carve(ws + (int64_t)blockIdx.x * slot_floats, R);
   for (;;) {
     const int idx = next_problem(counter);
     if (idx >= count) break;
     const PersProblem p = probs[idx];
-    if (p.l <= 32) {
+    if (p.parts > 1) {
+      if (p.l <= 32) {
+        if (p.kind == 0) team_svd<32>(p, b, spin_limit);
+        else team_psd<32>(p, b, max_retries, spin_limit);
+      } else {
+        if (p.kind == 0) team_svd<64>(p, b, spin_limit);
+        else team_psd<64>(p, b, max_retries, spin_limit);
+      }
+    } else if (p.l <= 32) {
       if (p.kind == 0) solve_svd<32>(p, b);
       else solve_psd<32>(p, b, max_retries);
     } else {
@@ -1238,10 +1678,10 @@ int64_t pers_slot_floats(int64_t maxdim) {
 }
 
 void launch_persistent(hipStream_t st, const PersProblem* probs, int count, int* counter,
-                       float* ws, int64_t maxdim, int grid, int max_retries) {
+                       float* ws, int64_t maxdim, int grid, int max_retries, int spin_limit) {
   if (count <= 0 || grid <= 0) return;
   hipLaunchKernelGGL(persistent_kernel, dim3(grid), dim3(NT), 0, st, probs, count, counter, ws,
-                     pers_slot_floats(maxdim), pers_rows(maxdim), max_retries);
+                     pers_slot_floats(maxdim), pers_rows(maxdim), max_retries, spin_limit);
 }
 
 }  // namespace rpca

@@ -220,12 +220,27 @@ struct PersProblem {
   uint64_t seed;
   int32_t m, n, kind, k, l, its, center, mid;
   int32_t uniform;  // uniform test matrix (Section 5) instead of the Gaussian one
+  int32_t parts;    // workgroups that share the problem (1: one workgroup solves it)
+  int32_t part;     // this entry's share, 0 .. parts - 1
   int32_t pad_;
   int* status;   // the problem's status entry (bits of small_core.h), nullable
   int* gstatus;  // the caller's status word: [0] OR of the bits, [1] Nystrom retries
+  float* sh;     // parts > 1: the problem's shared buffers (team_floats floats)
+  int* bar;      // parts > 1: the team's arrival counter, zero at launch
 };
 static constexpr int kPersMaxDim = 8192;  // largest m, n
 static constexpr int kPersMaxL = 64;      // largest l
+static constexpr int kPersMaxParts = 16;  // most workgroups on one problem
+// Floats of the shared buffers of a problem split over ``parts`` workgroups
+// (rows: pers_rows of its larger dimension; np: n rounded up to 64): Y, Z, T
+// and the packed operand (rows x 64 each), the A^T X partials (parts x np x
+// 64), two sets of Gram partials (parts x 64 x 64 doubles) and of vector
+// partials (parts x 64 doubles), and the sign keys and signs (parts x 128 x
+// 8 bytes).
+inline int64_t team_floats(int parts, int64_t rows, int64_t np) {
+  return 4 * rows * 64 + (int64_t)parts * np * 64 + 2 * 2 * (int64_t)parts * (4096 + 64) +
+         4 * (int64_t)parts * 64;
+}
 // rows of each slot buffer and floats per workgroup slot for problems up to maxdim
 int64_t pers_rows(int64_t maxdim);
 int64_t pers_slot_floats(int64_t maxdim);
@@ -235,7 +250,9 @@ void launch_pers_table(hipStream_t st, const PersProblem* host, int count, PersP
 // ``count`` problems (device table) over ``grid`` workgroups; ``counter`` (device int,
 // zero at launch) hands out the problems; ``ws`` holds grid * pers_slot_floats floats.
 // max_retries: Nystrom shift retries before a problem is reported not PSD
+// spin_limit: polls of a team's arrival counter before a workgroup gives up
+// waiting (the problem then reports kErrTimeout)
 void launch_persistent(hipStream_t st, const PersProblem* probs, int count, int* counter,
-                       float* ws, int64_t maxdim, int grid, int max_retries);
+                       float* ws, int64_t maxdim, int grid, int max_retries, int spin_limit);
 
 }  // namespace rpca

@@ -7,6 +7,7 @@
 #include <array>
 #include <list>
 #include <map>
+#include <queue>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -79,6 +80,14 @@ struct rpca_ctx_s {
   int* pers_counter = nullptr;
   float* pers_ws = nullptr;
   int64_t pers_ws_floats = 0;
+  // shared buffers and arrival counters of the problems split over workgroups
+  float* pers_sh = nullptr;
+  int64_t pers_sh_floats = 0;
+  int* pers_bar = nullptr;
+  int pers_bar_cap = 0;
+  int split_max_parts = 8;
+  int split_min_parts = 1;
+  int team_spins = 1 << 22;
   std::vector<void*> pers_retired;
 };
 
@@ -166,6 +175,10 @@ rpca_status sync_status(rpca_ctx ctx) {
   HIP_OK(hipStreamSynchronize(ctx->stream));
   // non-finite values are the cause when both are set (a NaN also defeats
   // every shifted Cholesky factorization)
+  // a share that stopped waiting computed from incomplete data: that is the cause
+  if (bits & kErrTimeout)
+    return fail(ctx, RPCA_ERR_TIMEOUT,
+                "a batched problem split over workgroups gave up waiting for its other shares");
   if (bits & kErrNonFinite)
     return fail(ctx, RPCA_ERR_NUMERICAL, "non-finite values met on the device (is A finite?)");
   return fail(ctx, RPCA_ERR_NOT_PSD,
@@ -693,6 +706,7 @@ const char* rpca_status_str(rpca_status s) {
     case RPCA_ERR_HIP: return "HIP error";
     case RPCA_ERR_NOT_PSD: return "matrix not positive semidefinite";
     case RPCA_ERR_NUMERICAL: return "non-finite values";
+    case RPCA_ERR_TIMEOUT: return "device wait timed out";
   }
   return "unknown status";
 }
@@ -760,6 +774,8 @@ rpca_status rpca_destroy(rpca_ctx ctx) {
   if (ctx->pers_tab) (void)hipFree(ctx->pers_tab);
   if (ctx->pers_counter) (void)hipFree(ctx->pers_counter);
   if (ctx->pers_ws) (void)hipFree(ctx->pers_ws);
+  if (ctx->pers_sh) (void)hipFree(ctx->pers_sh);
+  if (ctx->pers_bar) (void)hipFree(ctx->pers_bar);
   for (void* q : ctx->pers_retired) (void)hipFree(q);
   delete ctx;
   return RPCA_OK;
@@ -1122,9 +1138,10 @@ rpca_status rpca_reset_stats(rpca_ctx ctx) {
 
 namespace {
 struct ctx_s_pers_plan {
-  std::vector<PersProblem> table;  // largest problems first
+  std::vector<PersProblem> table;  // the split problems' shares, then the rest, largest first
   int64_t maxdim = 0;
   int grid = 0;
+  int teams = 0;  // problems split over workgroups (their arrival counters)
 };
 
 // grow a device buffer outside capture; the old one is kept for graphs that use it
@@ -1170,22 +1187,131 @@ rpca_status pers_prepare(rpca_ctx ctx, const rpca_problem* problems, const std::
     e.uniform = (q.flags & RPCA_OMEGA_UNIFORM) ? 1 : 0;
     e.status = ctx->bstat + p;
     e.gstatus = ctx->dstat;
+    e.parts = 1;
+    e.part = 0;
     tab.push_back(e);
+    // the work of the problem on one workgroup (ns): passes over A, and the
+    // steps on the tall m x lp and n x lp matrices (renormalizations, packs,
+    // Gram matrices) -- a fit to single-problem times on MI355X (median error
+    // 10% on the 512-problem workload)
+    const double lpf = e.l <= 32 ? 32.0 : 64.0;
     const double passes = q.kind == 0 ? 2.0 * q.its + 2.0 : q.its + 1.0;
-    cost.push_back(passes * (double)A->m * (double)A->n * (e.l <= 32 ? 32 : 64) +
-                   4096.0 * (double)(A->m + A->n) * e.l);
+    const double steps = q.kind == 0 ? 2.0 * q.its + 2.0 : q.its + 2.0;
+    const double side = q.kind == 0 ? (double)(A->m + A->n) : 2.0 * (double)A->n;
+    cost.push_back(0.1667 * passes * (double)A->m * (double)A->n * lpf / 64.0 +
+                   1.213 * steps * side * lpf);
     maxdim = std::max<int64_t>(maxdim, std::max(A->m, A->n));
   }
-  std::vector<int> ord(tab.size());
-  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  for (int i : ord) plan.table.push_back(tab[i]);
-  const int cnt = (int)plan.table.size();
+  // Teams.  A problem takes about kFixed + work on one workgroup and
+  // kTeamFixed + work / g as a share of a team of g (the waits and the l x l
+  // steps every share repeats).  For a few targets T, every problem whose
+  // single-workgroup time exceeds T gets the g that brings its shares under
+  // T (at most split_max_parts, one per 64 rows of its smaller side, and all
+  // shares within one round of the grid); the launch's list scheduling --
+  // the shares first, then the other problems by decreasing cost, each to the
+  // first free workgroup -- is simulated and the T with the shortest
+  // simulated makespan is kept.
+  const double kFixed = 450e3, kTeamFixed = 900e3;
+  const int nprob = (int)tab.size();
+  const int slots = std::max(1, ctx->num_cus);
+  double total = 0.0;
+  for (double c : cost) total += c + kFixed;
+  auto split_for = [&](double T, std::vector<int>& parts) {
+    int shares = 0;
+    for (int i = 0; i < nprob; ++i) {
+      const PersProblem& e = tab[i];
+      int g = 1;
+      if (ctx->split_max_parts > 1 && e.mid != 1 && cost[i] + kFixed > T && T > kTeamFixed) {
+        const int64_t cap = std::min<int64_t>(ctx->split_max_parts, std::min(e.m, e.n) / 64);
+        g = (int)std::min<double>(std::ceil(cost[i] / (T - kTeamFixed)), (double)cap);
+      }
+      parts[i] = g < 2 ? 1 : g;
+      if (parts[i] > 1) shares += parts[i];
+    }
+    return shares;
+  };
+  auto simulate = [&](const std::vector<int>& parts) {
+    std::vector<double> items;
+    for (int i = 0; i < nprob; ++i)
+      if (parts[i] > 1)
+        for (int g = 0; g < parts[i]; ++g) items.push_back(kTeamFixed + cost[i] / parts[i]);
+    std::vector<double> rest;
+    for (int i = 0; i < nprob; ++i)
+      if (parts[i] < 2) rest.push_back(kFixed + cost[i]);
+    std::sort(rest.begin(), rest.end(), std::greater<double>());
+    items.insert(items.end(), rest.begin(), rest.end());
+    std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+    for (int w = 0; w < std::min<int>(slots, (int)items.size()); ++w) free_at.push(0.0);
+    double span = 0.0;
+    for (double t : items) {
+      const double s0 = free_at.top();
+      free_at.pop();
+      free_at.push(s0 + t);
+      span = std::max(span, s0 + t);
+    }
+    return span;
+  };
+  std::vector<int> parts(nprob, 1), trial(nprob, 1);
+  double best = simulate(parts);
+  // targets: multiples of the average load, the times that cut the largest
+  // problem into 2 .. split_max_parts shares, and short ones that split every
+  // problem worth splitting (a small batch leaves workgroups idle)
+  std::vector<double> targets;
+  const double avg = total / slots;
+  for (double f : {0.5, 0.65, 0.8, 1.0, 1.25, 1.6, 2.0}) targets.push_back(f * avg);
+  const double cmax = nprob ? *std::max_element(cost.begin(), cost.end()) : 0.0;
+  for (int g = 2; g <= ctx->split_max_parts; ++g) targets.push_back(kTeamFixed + cmax / g + 1.0);
+  for (double f : {1.25, 1.5, 2.0, 3.0}) targets.push_back(f * kTeamFixed);
+  for (double T : targets) {
+    if (split_for(T, trial) > slots) continue;
+    const double span = simulate(trial);
+    if (span < best) {
+      best = span;
+      parts = trial;
+    }
+  }
+  // the caller's minimum number of shares for every problem that can be split
+  if (ctx->split_min_parts > 1) {
+    trial = parts;
+    int shares = 0;
+    for (int i = 0; i < nprob; ++i) {
+      const PersProblem& e = tab[i];
+      const int64_t cap = std::min<int64_t>(ctx->split_max_parts, std::min(e.m, e.n) / 64);
+      if (e.mid != 1 && cap >= 2)
+        trial[i] = (int)std::max<int64_t>(trial[i], std::min<int64_t>(ctx->split_min_parts, cap));
+      if (trial[i] > 1) shares += trial[i];
+    }
+    if (shares <= slots) parts = trial;
+  }
+  std::vector<int> ord(nprob);
+  for (int i = 0; i < nprob; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if ((parts[a] > 1) != (parts[b] > 1)) return parts[a] > 1;
+    return cost[a] > cost[b];
+  });
+  int64_t sh_need = 0;
+  int teams = 0;
+  std::vector<int64_t> sh_off(nprob, -1);
+  for (int i : ord) {
+    if (parts[i] < 2) continue;
+    const PersProblem& e = tab[i];
+    sh_off[i] = sh_need;
+    sh_need += round_up(team_floats(parts[i], round_up(std::max(e.m, e.n), 64),
+                                    round_up(e.n, 64)), 64);
+    ++teams;
+  }
+  const int cnt_items = [&] {
+    int c = 0;
+    for (int i = 0; i < nprob; ++i) c += parts[i];
+    return c;
+  }();
+  const int cnt = cnt_items;
   const int grid = (int)std::min<int64_t>(cnt, ctx->num_cus);
   const int64_t need = (int64_t)grid * pers_slot_floats(maxdim);
-  if (ctx->pers_ws_floats < need || ctx->pers_tab_cap < cnt || !ctx->pers_counter) {
+  if (ctx->pers_ws_floats < need || ctx->pers_tab_cap < cnt || !ctx->pers_counter ||
+      ctx->pers_sh_floats < sh_need || ctx->pers_bar_cap < teams) {
     if (capturing) return fail(ctx, RPCA_ERR_UNSUPPORTED, "run the batch once before capturing it");
-    if (ctx->ws_limit && (size_t)need * sizeof(float) > ctx->ws_limit)
+    if (ctx->ws_limit && (size_t)(need + sh_need) * sizeof(float) > ctx->ws_limit)
       return fail(ctx, RPCA_ERR_NO_MEMORY, "batch workspace exceeds the limit");
     HIP_OK(hipStreamSynchronize(ctx->stream));
     rpca_status s = RPCA_OK;
@@ -1203,14 +1329,54 @@ rpca_status pers_prepare(rpca_ctx ctx, const rpca_problem* problems, const std::
       s = pers_grow(ctx, ctx->pers_counter, 256, "work counter");
       if (s != RPCA_OK) return s;
     }
+    if (ctx->pers_sh_floats < sh_need) {
+      s = pers_grow(ctx, ctx->pers_sh, (size_t)sh_need * sizeof(float), "shared team buffers");
+      if (s != RPCA_OK) return s;
+      ctx->pers_sh_floats = sh_need;
+    }
+    if (ctx->pers_bar_cap < teams) {
+      const int cap = (int)round_up(teams, 64);
+      s = pers_grow(ctx, ctx->pers_bar, (size_t)cap * sizeof(int), "team counters");
+      if (s != RPCA_OK) return s;
+      ctx->pers_bar_cap = cap;
+    }
+  }
+  int team = 0;
+  for (int i : ord) {
+    PersProblem e = tab[i];
+    if (parts[i] < 2) {
+      plan.table.push_back(e);
+      continue;
+    }
+    e.parts = parts[i];
+    e.sh = ctx->pers_sh + sh_off[i];
+    e.bar = ctx->pers_bar + team++;
+    for (int g = 0; g < parts[i]; ++g) {
+      e.part = g;
+      plan.table.push_back(e);
+    }
   }
   plan.maxdim = maxdim;
   plan.grid = grid;
+  plan.teams = teams;
   return RPCA_OK;
 }
 }  // namespace
 
 extern "C" {
+
+rpca_status rpca_set_batch_split(rpca_ctx ctx, int32_t max_parts, int32_t min_parts,
+                                 int32_t spin_limit) {
+  if (!ctx) return RPCA_ERR_INVALID_ARG;
+  if (max_parts < 1 || max_parts > kPersMaxParts || min_parts < 1 || min_parts > max_parts ||
+      spin_limit < 0)
+    return fail(ctx, RPCA_ERR_INVALID_ARG,
+                "batch split: 1 <= min_parts <= max_parts <= 16, spin_limit >= 0");
+  ctx->split_max_parts = max_parts;
+  ctx->split_min_parts = min_parts;
+  ctx->team_spins = spin_limit ? spin_limit : (1 << 22);
+  return RPCA_OK;
+}
 
 rpca_status rpca_set_batch_mode(rpca_ctx ctx, int32_t mode) {
   if (!ctx) return RPCA_ERR_INVALID_ARG;
@@ -1343,8 +1509,11 @@ rpca_status rpca_svd_batched(rpca_ctx ctx, int count, const rpca_problem* proble
   if (!pers.empty()) {
     launch_pers_table(ctx->stream, plan.table.data(), (int)plan.table.size(), ctx->pers_tab);
     launch_fill_zero(ctx->stream, reinterpret_cast<float*>(ctx->pers_counter), 4);
-    launch_persistent(ctx->stream, ctx->pers_tab, (int)pers.size(), ctx->pers_counter,
-                      ctx->pers_ws, plan.maxdim, plan.grid, ctx->nys_retries);
+    if (plan.teams)
+      launch_fill_zero(ctx->stream, reinterpret_cast<float*>(ctx->pers_bar),
+                       round_up(plan.teams, 4));
+    launch_persistent(ctx->stream, ctx->pers_tab, (int)plan.table.size(), ctx->pers_counter,
+                      ctx->pers_ws, plan.maxdim, plan.grid, ctx->nys_retries, ctx->team_spins);
     HIP_OK(hipGetLastError());
     ctx->stats.calls += pers.size();
   }
@@ -1400,7 +1569,8 @@ rpca_status rpca_batch_status(rpca_ctx ctx, int32_t count, int32_t* status_host)
                         ctx->stream));
   HIP_OK(hipStreamSynchronize(ctx->stream));
   for (int i = 0; i < count; ++i)
-    status_host[i] = (bits[i] & kErrNonFinite) ? RPCA_ERR_NUMERICAL
+    status_host[i] = (bits[i] & kErrTimeout) ? RPCA_ERR_TIMEOUT
+                     : (bits[i] & kErrNonFinite) ? RPCA_ERR_NUMERICAL
                      : (bits[i] & kErrNotPsd) ? RPCA_ERR_NOT_PSD : RPCA_OK;
   return RPCA_OK;
 }

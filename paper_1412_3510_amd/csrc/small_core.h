@@ -17,13 +17,16 @@ namespace rpca {
 // Slots 0 .. 11 belong to one orthonormalization (its first pass clears
 // them); slots 12 .. 15 belong to the whole solve (cleared when it starts):
 //   12 Nystrom shift retries, 13 Nystrom: no positive definite shifted B2
-//   found, 14 non-finite values met in any step.
+//   found, 14 non-finite values met in any step, 15 a batched problem split
+//   over several workgroups gave up waiting for the others (bounded wait).
 static constexpr int kStRetries = 12;
 static constexpr int kStNotPsd = 13;
 static constexpr int kStNonFinite = 14;
+static constexpr int kStTeam = 15;
 // bits of a solve's status word (and of each batch problem's entry)
 static constexpr int kErrNotPsd = 1;
 static constexpr int kErrNonFinite = 2;
+static constexpr int kErrTimeout = 4;
 static constexpr double kTauRel = 1e-10;   // relative Cholesky pivot that marks dependence
 static constexpr double kShiftRel = 1e-8;  // relative diagonal shift when dependence is met
 static constexpr double kJunkNorm2 = 1e-2; // squared column norm after a shifted pass

@@ -6,8 +6,10 @@ Each problem is checked against the FP64 oracle on the same Omega:
   * U and V orthonormal to 1e-5;
   * where the exact residual is affordable, an error within 0.1% of the
     oracle's own rank-k error.
-The batch mixes shapes that exercise every edge of the single-workgroup
-routines: l <= 32 and 32 < l <= 64 (one or two MFMA column blocks), row
+The batch is solved twice: every problem on one workgroup, and with the
+problems above the batch's average load split over teams of workgroups
+(shared passes, Gram matrices and solves by row ranges).  It mixes shapes
+that exercise every edge of the single-workgroup routines: l <= 32 and 32 < l <= 64 (one or two MFMA column blocks), row
 counts and column counts that are not multiples of the tiles (64 for the
 K chunks, 256 for the row and column tiles), wide and tall A, its = 0, the
 centered form, Cholesky QR in place of LU, an A whose row stride is odd (the
@@ -87,8 +89,7 @@ def _device(A, special):
     return t
 
 
-@pytest.fixture(scope="module")
-def batch(ctx):
+def _problems():
     host, probs = [], []
     for i, case in enumerate(CASES):
         kind, m, n, k, l, its, center, renorm, special = case
@@ -96,8 +97,25 @@ def batch(ctx):
         host.append(A)
         probs.append(dict(A=_device(A, special), k=k, l=l, its=its, seed=900 + i,
                           center=center, renorm=renorm, kind=kind))
-    outs = ctx.svd_batched(probs, sync=True)
-    return host, probs, [[t.cpu().numpy() for t in o] for o in outs]
+    return host, probs
+
+
+# (max_parts, min_parts): (1, 1) every problem on one workgroup; (8, 4)
+# every problem that can be split (min(m, n) >= 128, no LU renormalization)
+# over a team of 2 to 8 workgroups
+SPLITS = {"whole": (1, 1), "split": (8, 4)}
+
+
+@pytest.fixture(scope="module", params=["whole", "split"])
+def batch(ctx, request):
+    host, probs = _problems()
+    ctx.set_batch_split(*SPLITS[request.param])
+    try:
+        outs = ctx.svd_batched(probs, sync=True)
+        assert ctx.batch_status(len(probs)) == [0] * len(probs)
+    finally:
+        ctx.set_batch_split()
+    return host, probs, [[t.cpu().numpy() for t in o] for o in outs], request.param
 
 
 def _orth_err(X):
@@ -107,7 +125,7 @@ def _orth_err(X):
 
 @pytest.mark.parametrize("i", range(len(CASES)))
 def test_persistent_matches_oracle(batch, i):
-    host, probs, outs = batch
+    host, probs, outs, _ = batch
     kind, m, n, k, l, its, center, renorm, special = CASES[i]
     A = host[i]
     om = philox.omega(900 + i, n, l)
@@ -144,7 +162,7 @@ def test_persistent_matches_oracle(batch, i):
 
 
 def test_persistent_agrees_with_streams(ctx, batch):
-    host, probs, outs = batch
+    host, probs, outs, _ = batch
     ctx.set_batch_mode(1)
     try:
         ref = ctx.svd_batched(probs, sync=True)
@@ -161,14 +179,69 @@ def test_persistent_repeat_bit_identical(ctx, batch):
     # the same batch again, another batch in between (the table is rewritten by
     # every call):
     # bit-identical results every time
-    host, probs, outs = batch
+    host, probs, outs, split = batch
     small = [probs[0], probs[5], probs[13]]
-    for rep in range(2):
-        again = ctx.svd_batched(probs, sync=True)
-        for o, a in zip(outs, again):
-            for x, y in zip(o, a):
-                assert np.array_equal(x, y.cpu().numpy()), "repeat %d" % rep
-        ctx.svd_batched(small, sync=True)
+    ctx.set_batch_split(*SPLITS[split])
+    try:
+        for rep in range(2):
+            again = ctx.svd_batched(probs, sync=True)
+            for o, a in zip(outs, again):
+                for x, y in zip(o, a):
+                    assert np.array_equal(x, y.cpu().numpy()), "repeat %d" % rep
+            ctx.svd_batched(small, sync=True)
+    finally:
+        ctx.set_batch_split()
+
+
+def test_split_changes_rounding_only(ctx):
+    # the same problems whole and split: the split ones sum their partial
+    # products in another order, so they differ in the last bits (which shows
+    # the split happened) and agree to rounding
+    host, probs = _problems()
+    ctx.set_batch_split(1)
+    whole = ctx.svd_batched(probs, sync=True)
+    ctx.set_batch_split(8, 4)
+    split = ctx.svd_batched(probs, sync=True)
+    ctx.set_batch_split()
+    differ = 0
+    for i, (a, b) in enumerate(zip(whole, split)):
+        if CASES[i][8] == "zero":
+            continue
+        S0, S1 = a[1].cpu().numpy(), b[1].cpu().numpy()
+        np.testing.assert_allclose(S1, S0, rtol=1e-5, atol=1e-7 * S0[0])
+        differ += int(not np.array_equal(S0, S1) or not torch.equal(a[0], b[0]))
+    assert differ >= 8
+
+
+def test_split_wait_limit_reports_timeout(ctx, gpu_lib):
+    # a wait limit of one poll, forced from the host: a share that arrives
+    # first stops waiting at once and its problem reports RPCA_ERR_TIMEOUT
+    # (every kernel still ends normally); the problems solved whole are not
+    # affected, and with the default limit the batch is clean again
+    TIMEOUT = 7
+    host, probs = _problems()
+    big = [i for i, c in enumerate(CASES) if min(c[1], c[2]) >= 1000 and c[7] != "lu"]
+    assert len(big) >= 3
+    ctx.set_batch_split(8, 4, 1)
+    try:
+        ctx.svd_batched(probs)
+        st = ctx.batch_status(len(probs))
+        with pytest.raises(gpu_lib.RpcaError) as e:
+            ctx.sync()
+        assert e.value.status == TIMEOUT
+    finally:
+        ctx.set_batch_split()
+    assert set(st) <= {0, TIMEOUT} and sum(s == TIMEOUT for s in st) >= 1
+    small = [i for i, c in enumerate(CASES) if min(c[1], c[2]) < 128 or c[7] == "lu"]
+    assert all(st[i] == 0 for i in small)
+    ctx.svd_batched(probs, sync=True)
+    assert ctx.batch_status(len(probs)) == [0] * len(probs)
+
+
+def test_batch_split_rejects_bad_values(ctx, gpu_lib):
+    for args in ((0, 1, 0), (17, 1, 0), (4, 5, 0), (4, 0, 0), (4, 2, -1)):
+        with pytest.raises(gpu_lib.RpcaError):
+            ctx.set_batch_split(*args)
 
 
 def test_persistent_and_streams_in_one_call(ctx):
