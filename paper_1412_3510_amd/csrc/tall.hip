@@ -261,22 +261,116 @@ __global__ void __launch_bounds__(256 * NG) gram_kernel(const float* __restrict_
     for (int v = 0; v < T; ++v) out[(ti * T + u) * LP + tj * T + v] = acc[u][v];
 }
 
+// The same Gram matrix on the float64 matrix cores (lp = 32, 64):
+// v_mfma_f64_16x16x4f64 takes a 16 x 4 block of X^T and a 4 x 16 block of
+// X2 -- in both, lane L holds the entry (row r + L / 16, column 16 t + L % 16)
+// of X or X2, loaded straight from memory -- and lane L's register q of the
+// 16 x 16 result is entry (L / 16 + 4 q, L % 16).  A wave accumulates the
+// (lp / 16)^2 tiles (only those with ti <= tj when X2 = X: the rest follow
+// by symmetry) over 4-row groups of its rows; the waves of the workgroup
+// then add their tiles in LDS in wave order.  Products of float32 values are
+// exact in float64 and every sum is in float64, as in gram_kernel; only the
+// order of the additions differs.
+static constexpr int kGramWaves = 4;
+
+template <int LP, bool SAME>
+__global__ void __launch_bounds__(64 * kGramWaves) gram_mfma_kernel(
+    const float* __restrict__ X, int64_t ldx, const float* __restrict__ X2, int64_t ldx2,
+    int64_t rows, double* __restrict__ partial, const int* __restrict__ skip_flag) {
+  if (skip_flag && *skip_flag == 0) return;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int T = LP / 16;
+  constexpr int NT2 = SAME ? T * (T + 1) / 2 : T * T;  // tiles a wave accumulates
+  constexpr int U = 4;                                 // 4-row groups per step (loads in flight)
+  __shared__ double sh[LP * LP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int64_t r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+  d4 acc[NT2];
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  const float* X2p = SAME ? X : X2;
+  const int64_t ld2 = SAME ? ldx : ldx2;
+  // wave w takes the 4-row groups w, w + W, w + 2 W, ... of the range
+  for (int64_t g0 = r0 + 4 * wave; g0 < r1; g0 += 4 * kGramWaves * U) {
+    double a[U][T], b[U][T];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = g0 + 4 * kGramWaves * u + lr;
+      const bool ok = r < r1;
+      const int64_t rc = ok ? r : r0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float va = X[rc * ldx + 16 * t + lc];
+        a[u][t] = ok ? (double)va : 0.0;
+        if (!SAME) {
+          const float vb = X2p[rc * ld2 + 16 * t + lc];
+          b[u][t] = ok ? (double)vb : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+        for (int tj = SAME ? ti : 0; tj < T; ++tj) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ti], SAME ? a[u][tj] : b[u][tj],
+                                                        acc[t], 0, 0, 0);
+          ++t;
+        }
+    }
+  }
+  // the waves' tiles added in LDS in wave order (entry (i, j) of G at i * LP + j)
+  for (int w = 0; w < kGramWaves; ++w) {
+    if (wave == w) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+        for (int tj = SAME ? ti : 0; tj < T; ++tj) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = 16 * ti + lr + 4 * q, j = 16 * tj + lc;
+            const double v = (w == 0) ? acc[t][q] : sh[i * LP + j] + acc[t][q];
+            sh[i * LP + j] = v;
+            if (SAME && ti != tj) sh[j * LP + i] = v;
+          }
+          ++t;
+        }
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.x * LP * LP;
+  for (int e = threadIdx.x; e < LP * LP; e += 64 * kGramWaves) out[e] = sh[e];
+}
+
 void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int lp,
                  const float* X2, int64_t ldx2, double* partial, double* G,
                  const int* skip_flag) {
-  // four row groups for tall inputs (lp <= 64; lp = 128 has no LDS for them)
-  const int ng = (rows >= kGramTall && lp <= 64) ? 4 : 1;
-  const int nblk = gram_grid(rows, ng);
-#define GRAM_GO(LP_, NG_)                                                                      \
-  hipLaunchKernelGGL((gram_kernel<LP_, NG_>), dim3(nblk), dim3(256 * NG_), 0, st, X, ldx, X2,   \
-                     ldx2, rows, partial, skip_flag)
-  switch (lp) {
-    case 32: if (ng == 4) GRAM_GO(32, 4); else GRAM_GO(32, 1); break;
-    case 64: if (ng == 4) GRAM_GO(64, 4); else GRAM_GO(64, 1); break;
-    case 128: GRAM_GO(128, 1); break;
-    default: return;
+  int nblk;
+  if (lp == 32 || lp == 64) {
+    // the matrix-core form: one workgroup of four waves per 256 rows, at most
+    // kGramMaxBlocks workgroups
+    const int64_t b = ceil_div(rows > 0 ? rows : 1, (int64_t)256);
+    nblk = (int)(b < kGramMaxBlocks ? b : kGramMaxBlocks);
+#define GRAM_MF(LP_, SAME_)                                                                     \
+  hipLaunchKernelGGL((gram_mfma_kernel<LP_, SAME_>), dim3(nblk), dim3(64 * kGramWaves), 0, st, X, \
+                     ldx, X2, ldx2, rows, partial, skip_flag)
+    if (lp == 32) {
+      if (X2) GRAM_MF(32, false); else GRAM_MF(32, true);
+    } else {
+      if (X2) GRAM_MF(64, false); else GRAM_MF(64, true);
+    }
+#undef GRAM_MF
+  } else {
+    // lp = 128: the float64 FMA form (its accumulators would not fit the
+    // matrix-core layout's registers)
+    nblk = gram_grid(rows, 1);
+    hipLaunchKernelGGL((gram_kernel<128, 1>), dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2,
+                       rows, partial, skip_flag);
   }
-#undef GRAM_GO
   const int lp2 = lp * lp;
   launch_reduce(st, partial, nblk, lp2, lp2, 1.0, G, nullptr, skip_flag);
 }
