@@ -681,78 +681,86 @@ __device__ __attribute__((noinline)) void p_lu(float* Y_, int rows, int l) {
 }
 
 // ---- G (LP x LP, float64) = X^T X2 (X2 = X when null) ---------------------
+// On the float64 matrix cores: v_mfma_f64_16x16x4f64 takes a 16 x 4 block of
+// X^T and a 4 x 16 block of X2, lane L holding the entry (row r + L / 16,
+// column 16 t + L % 16) of X or X2 in both, and lane L's register q of the
+// 16 x 16 result is entry (L / 16 + 4 q, L % 16).  Wave w accumulates the
+// tiles (ti <= tj only when X2 = X; the rest by symmetry) over the 4-row
+// groups w, w + 8, w + 16, ... of the rows; the waves add their tiles in LDS
+// in wave order.  Products of float32 values are exact in float64.
+template <int LP, bool SAME>
+__device__ __forceinline__ void gram_body(const GAS float* X, const GAS float* X2, int rows,
+                                          GAS double* G) {
+  PLds& S = g_S;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int T = LP / 16, NT2 = SAME ? T * (T + 1) / 2 : T * T;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+  double* sh = S.u.gr;  // LP x LP
+  d4 acc[NT2];
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 2;  // 4-row groups per step and wave (loads in flight)
+  for (int g0 = 4 * wave; g0 < rows; g0 += 4 * NWAVE * U) {
+    double a[U][T], b[U][T];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = g0 + 4 * NWAVE * u + lr;
+      const bool ok = r < rows;
+      const int rc = ok ? r : 0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float va = X[(int64_t)rc * LP + 16 * t + lc];
+        a[u][t] = ok ? (double)va : 0.0;
+        if constexpr (!SAME) {
+          const float vb = X2[(int64_t)rc * LP + 16 * t + lc];
+          b[u][t] = ok ? (double)vb : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+        for (int tj = SAME ? ti : 0; tj < T; ++tj) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ti], SAME ? a[u][tj] : b[u][tj],
+                                                        acc[t], 0, 0, 0);
+          ++t;
+        }
+    }
+  }
+  for (int w = 0; w < NWAVE; ++w) {
+    if (wave == w) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+        for (int tj = SAME ? ti : 0; tj < T; ++tj) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = 16 * ti + lr + 4 * q, j = 16 * tj + lc;
+            const double v = (w == 0) ? acc[t][q] : sh[i * LP + j] + acc[t][q];
+            sh[i * LP + j] = v;
+            if (SAME && ti != tj) sh[j * LP + i] = v;
+          }
+          ++t;
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < LP * LP; e += NT) G[e] = sh[e];
+  __syncthreads();
+}
+
 template <int LP>
 __device__ __attribute__((noinline)) void p_gram(const float* X_, const float* X2_, int rows, double* G_) {
   rows = uni(rows);
   auto X = as_global(uni(X_));
   auto X2 = as_global(uni(X2_));
   auto G = as_global(uni(G_));
-  PLds& S = g_S;
-  constexpr int T = LP / 16, SL = 16;
-  const int tid = threadIdx.x, grp = tid >> 8, t = tid & 255, ti = t >> 4, tj = t & 15;
-  const bool same = (X2 == nullptr);
-  double* sa = S.u.gr + grp * 2 * SL * 64;
-  double* sb = same ? sa : sa + SL * 64;
-  double acc[T][T];
-#pragma unroll
-  for (int u = 0; u < T; ++u)
-#pragma unroll
-    for (int v = 0; v < T; ++v) acc[u][v] = 0.0;
-  // slices of SL rows, two per step (one per group of 256 threads); the next
-  // step's values are loaded into registers while the current one is used
-  constexpr int PER = SL * LP / 256;
-  float pa[PER], pb[PER];
-  auto load = [&](int rs) {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = t + 256 * q, rr = e / LP, c = e % LP, r = rs + rr;
-      const int rc = min(r, rows - 1);
-      const float va = X[(int64_t)rc * LP + c];
-      pa[q] = (r < rows) ? va : 0.f;
-      if (!same) {
-        const float vb = X2[(int64_t)rc * LP + c];
-        pb[q] = (r < rows) ? vb : 0.f;
-      }
-    }
-  };
-  load(grp * SL);
-  for (int r0 = 0; r0 < rows; r0 += 2 * SL) {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      sa[t + 256 * q] = (double)pa[q];
-      if (!same) sb[t + 256 * q] = (double)pb[q];
-    }
-    __syncthreads();
-    if (r0 + 2 * SL < rows) load(r0 + 2 * SL + grp * SL);
-    for (int rr = 0; rr < SL; ++rr) {
-      double a[T], b[T];
-#pragma unroll
-      for (int u = 0; u < T; ++u) {
-        a[u] = sa[rr * LP + ti * T + u];
-        b[u] = sb[rr * LP + tj * T + u];
-      }
-#pragma unroll
-      for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int v = 0; v < T; ++v) acc[u][v] += a[u] * b[v];
-    }
-    __syncthreads();
-  }
-  if (grp == 1)
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-      for (int v = 0; v < T; ++v) S.u.gr[(ti * T + u) * LP + tj * T + v] = acc[u][v];
-  __syncthreads();
-  if (grp == 0)
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-      for (int v = 0; v < T; ++v) {
-        const int e = (ti * T + u) * LP + tj * T + v;
-        G[e] = acc[u][v] + S.u.gr[e];
-      }
-  __syncthreads();
+  if (X2_ == nullptr) gram_body<LP, true>(X, X, rows, G);
+  else gram_body<LP, false>(X, X2, rows, G);
 }
 
 // transpose and reciprocal diagonal of the float32 factor in S.u.tri.R (rows < l)
