@@ -34,7 +34,7 @@
 //     four passes with a shifted factorization and completion of dependent
 //     columns, exactly as in the multi-kernel path);
 //   * the Rayleigh-Ritz step: B^T = A_c^T Q = Q2 R, the one-sided Jacobi SVD
-//     of R (shared with the single-problem kernel), U = Q W, V = Q2 X;
+//     of R^T (shared with the single-problem kernel), U = Q X, V = Q2 W;
 //   * Nystrom: B1 = A Q, nu = sqrt(n) 2^-24 ||B1||_F, Cholesky of
 //     Q^T B1 + nu I (nu times 10 while it fails), F = (B1 + nu Q) C^-1, its
 //     SVD through Cholesky QR and Jacobi, lambda = max(s^2 - nu, 0);
@@ -1141,12 +1141,13 @@ __device__ __attribute__((noinline)) void solve_svd(const PersProblem& p, Buf& b
     if (it < p.its) mid(b.Y, m);
     else p_orth<LP>(b.Y, m, l, false, b.T, b.G, p.seed);
   }
-  // Rayleigh-Ritz: A_c^T Q = Q2 R, R = W S X^T (Jacobi), U = Q W, V = Q2 X
+  // Rayleigh-Ritz: A_c^T Q = Q2 R; the Jacobi SVD of R^T (graded rows of R:
+  // fewer sweeps) gives R^T = X S W^T, so U = Q X, V = Q2 W
   apply_at();
   p_orth<LP>(b.Z, n, l, true, b.T, b.G, p.seed + 1);
-  jacobi_wg<LP>(b.G, l, 0, b);
-  p_small_gemm<LP>(b.Y, m, l, b.Wacc, p.k, p.U, p.ldu);
-  p_small_gemm<LP>(b.Z, n, l, b.Xn, p.k, p.V, p.ldv);
+  jacobi_wg<LP>(b.G, l, 1, b);
+  p_small_gemm<LP>(b.Y, m, l, b.Xn, p.k, p.U, p.ldu);
+  p_small_gemm<LP>(b.Z, n, l, b.Wacc, p.k, p.V, p.ldv);
   if (threadIdx.x < p.k) p.S[threadIdx.x] = b.sv[threadIdx.x];
   p_status(p, b.sv, 0.0);
   p_sign(p.U, p.ldu, m, p.k, p.V, p.ldv, n);
@@ -1569,10 +1570,10 @@ __device__ __attribute__((noinline)) void team_svd(const PersProblem& p, Buf& b,
   }
   apply_at();
   T.orth(Z, nr0, nr1, true, p.seed + 1, false);
-  jacobi_wg<LP>(b.G, l, 0, b);
-  p_small_gemm<LP>(Y + (int64_t)mr0 * LP, mr1 - mr0, l, b.Wacc, p.k, p.U + (int64_t)mr0 * p.ldu,
+  jacobi_wg<LP>(b.G, l, 1, b);
+  p_small_gemm<LP>(Y + (int64_t)mr0 * LP, mr1 - mr0, l, b.Xn, p.k, p.U + (int64_t)mr0 * p.ldu,
                    p.ldu);
-  p_small_gemm<LP>(Z + (int64_t)nr0 * LP, nr1 - nr0, l, b.Xn, p.k, p.V + (int64_t)nr0 * p.ldv,
+  p_small_gemm<LP>(Z + (int64_t)nr0 * LP, nr1 - nr0, l, b.Wacc, p.k, p.V + (int64_t)nr0 * p.ldv,
                    p.ldv);
   if (g == 0 && threadIdx.x < p.k) p.S[threadIdx.x] = b.sv[threadIdx.x];
   T.sign(mr0, mr1, p.V, nr0, nr1);

@@ -625,13 +625,17 @@ rpca_status svd_impl(rpca_ctx ctx, const rpca_matrix* A, int k, int l, int its, 
       else orth_renorm(ctx, w, w.Y, m, false, seed);
     }
   }
-  // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; SVD of R
+  // Rayleigh-Ritz: B^T = A^T Q (n x l) = Q2 R; the one-sided Jacobi SVD
+  // rotates the columns of R^T (the rows of R, which the Cholesky QR leaves
+  // graded, so fewer sweeps are needed than for the columns of R):
+  // R^T W = X diag(s), i.e. R = W diag(s) X^T... with the roles of the two
+  // factors exchanged: R^T = X diag(s) W^T, B = R^T Q2^T = X diag(s) (Q2 W)^T
   apply_At(ctx, A, Ar, w, w.Y, w.Z, center);
   orth_renorm(ctx, w, w.Z, n, true, seed + 1);
-  launch_jacobi_svd(st, w.G, l, w.lp, 0, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
-  // U = Q W, V = Q2 X, S = top k
-  launch_small_gemm(st, w.Y, w.lp, m, l, w.Wacc, w.lp, k, U, ldu, ctx->num_cus);
-  launch_small_gemm(st, w.Z, w.lp, n, l, w.Xn, w.lp, k, V, ldv, ctx->num_cus);
+  launch_jacobi_svd(st, w.G, l, w.lp, 1, w.sv, w.Wacc, w.Xn, w.jwork, w.state + 6, k);
+  // U = Q X, V = Q2 W, S = top k
+  launch_small_gemm(st, w.Y, w.lp, m, l, w.Xn, w.lp, k, U, ldu, ctx->num_cus);
+  launch_small_gemm(st, w.Z, w.lp, n, l, w.Wacc, w.lp, k, V, ldv, ctx->num_cus);
   launch_finish_values(st, w.sv, k, nullptr, S, w.state, ctx->dstat, slot);
   launch_sign_fix(st, U, ldu, m, k, V, ldv, n, w.signwork);
   HIP_OK(hipGetLastError());
