@@ -346,6 +346,87 @@ __global__ void __launch_bounds__(64 * kGramWaves) gram_mfma_kernel(
   for (int e = threadIdx.x; e < LP * LP; e += 64 * kGramWaves) out[e] = sh[e];
 }
 
+// lp = 128 on the matrix cores: the 36 upper tiles (64 without symmetry)
+// are dealt to the four waves in order, 9 (16) each; every wave walks all
+// the workgroup's 4-row groups for its own tiles (the four waves read the
+// same rows, mostly from L1) and writes its tiles, and their mirror images,
+// straight to the workgroup's partial.  A wave's tiles are compile-time
+// constants (one instantiation per wave), so its operands are plain registers.
+// upper tiles (ti <= tj) of the 8 x 8 tile grid in row order
+__device__ constexpr int kG128Ti[36] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 4, 4, 4, 4, 5, 5, 5, 6, 6, 7};
+__device__ constexpr int kG128Tj[36] = {0, 1, 2, 3, 4, 5, 6, 7, 1, 2, 3, 4, 5, 6, 7, 2, 3, 4, 5, 6, 7, 3, 4, 5, 6, 7, 4, 5, 6, 7, 5, 6, 7, 6, 7, 7};
+template <bool SAME>
+__device__ __forceinline__ constexpr int g128_ti(int t) { return SAME ? kG128Ti[t] : t / 8; }
+template <bool SAME>
+__device__ __forceinline__ constexpr int g128_tj(int t) { return SAME ? kG128Tj[t] : t % 8; }
+
+template <bool SAME, int W>
+__device__ __forceinline__ void gram128_wave(const float* __restrict__ X, int64_t ldx,
+                                             const float* __restrict__ X2, int64_t ld2,
+                                             int64_t r0, int64_t r1, double* __restrict__ out) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int LP = 128, T = 8;
+  constexpr int NTOT = SAME ? T * (T + 1) / 2 : T * T, PER = NTOT / 4;
+  static_assert(PER * 4 == NTOT, "tiles per wave");
+  const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+  d4 acc[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t g0 = r0; g0 < r1; g0 += 8) {
+    double a[2][T], b[2][T];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t r = g0 + 4 * u + lr;
+      const bool ok = r < r1;
+      const int64_t rc = ok ? r : r0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float va = X[rc * ldx + 16 * t + lc];
+        a[u][t] = ok ? (double)va : 0.0;
+        if constexpr (!SAME) {
+          const float vb = X2[rc * ld2 + 16 * t + lc];
+          b[u][t] = ok ? (double)vb : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int ti = g128_ti<SAME>(W * PER + k), tj = g128_tj<SAME>(W * PER + k);
+        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ti], SAME ? a[u][tj] : b[u][tj],
+                                                      acc[k], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int ti = g128_ti<SAME>(W * PER + k), tj = g128_tj<SAME>(W * PER + k);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * ti + lr + 4 * q, j = 16 * tj + lc;
+      out[i * LP + j] = acc[k][q];
+      if (SAME && ti != tj) out[j * LP + i] = acc[k][q];
+    }
+  }
+}
+
+template <bool SAME>
+__global__ void __launch_bounds__(256) gram_mfma128_kernel(
+    const float* __restrict__ X, int64_t ldx, const float* __restrict__ X2, int64_t ldx2,
+    int64_t rows, double* __restrict__ partial, const int* __restrict__ skip_flag) {
+  if (skip_flag && *skip_flag == 0) return;
+  const int64_t r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+  const float* X2p = SAME ? X : X2;
+  const int64_t ld2 = SAME ? ldx : ldx2;
+  double* out = partial + (int64_t)blockIdx.x * 128 * 128;
+  switch (threadIdx.x >> 6) {  // (uniform per wave)
+    case 0: gram128_wave<SAME, 0>(X, ldx, X2p, ld2, r0, r1, out); break;
+    case 1: gram128_wave<SAME, 1>(X, ldx, X2p, ld2, r0, r1, out); break;
+    case 2: gram128_wave<SAME, 2>(X, ldx, X2p, ld2, r0, r1, out); break;
+    default: gram128_wave<SAME, 3>(X, ldx, X2p, ld2, r0, r1, out); break;
+  }
+}
+
 void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int lp,
                  const float* X2, int64_t ldx2, double* partial, double* G,
                  const int* skip_flag) {
@@ -365,11 +446,15 @@ void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int 
     }
 #undef GRAM_MF
   } else {
-    // lp = 128: the float64 FMA form (its accumulators would not fit the
-    // matrix-core layout's registers)
-    nblk = gram_grid(rows, 1);
-    hipLaunchKernelGGL((gram_kernel<128, 1>), dim3(nblk), dim3(256), 0, st, X, ldx, X2, ldx2,
-                       rows, partial, skip_flag);
+    // lp = 128: the tiles dealt to the waves, one workgroup per 256 rows
+    const int64_t b = ceil_div(rows > 0 ? rows : 1, (int64_t)256);
+    nblk = (int)(b < kGramMaxBlocks ? b : kGramMaxBlocks);
+    if (X2)
+      hipLaunchKernelGGL(gram_mfma128_kernel<false>, dim3(nblk), dim3(256), 0, st, X, ldx, X2,
+                         ldx2, rows, partial, skip_flag);
+    else
+      hipLaunchKernelGGL(gram_mfma128_kernel<true>, dim3(nblk), dim3(256), 0, st, X, ldx, X2,
+                         ldx2, rows, partial, skip_flag);
   }
   const int lp2 = lp * lp;
   launch_reduce(st, partial, nblk, lp2, lp2, 1.0, G, nullptr, skip_flag);
