@@ -28,14 +28,6 @@
 
 namespace rpca {
 
-__device__ __forceinline__ f32x16 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
-                                        const bf16x8& bl, f32x16 acc) {
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-  return acc;
-}
-
 // ------------------------------------------------------------------------
 // pack: tall float32 X (rows x cols, ld ldx) -> fragment-ordered bf16 (hi, lo)
 // ------------------------------------------------------------------------
@@ -233,7 +225,9 @@ __global__ void __launch_bounds__(64 * NW) ax_dma_kernel(const float* __restrict
   constexpr int PER = 4 + XW;  // DMA instructions per wave per stage
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // scalar wave index: the per-wave choices (live rows) are scalar branches
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t rbeg = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t rend = min(m, rbeg + rows_per_wg);
   const int64_t nstage = ceil_div(n, KC);
@@ -297,15 +291,7 @@ __global__ void __launch_bounds__(64 * NW) ax_dma_kernel(const float* __restrict
           const float4 a0 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * (c0 ^ sw));
           const float4 a1 = *reinterpret_cast<const float4*>(As + R * 128 + 16 * ((c0 + 1) ^ sw));
           bf16x8 ah, al;
-          __bf16 th, tl;
-          split_bf16(a0.x, th, tl); ah[0] = th; al[0] = tl;
-          split_bf16(a0.y, th, tl); ah[1] = th; al[1] = tl;
-          split_bf16(a0.z, th, tl); ah[2] = th; al[2] = tl;
-          split_bf16(a0.w, th, tl); ah[3] = th; al[3] = tl;
-          split_bf16(a1.x, th, tl); ah[4] = th; al[4] = tl;
-          split_bf16(a1.y, th, tl); ah[5] = th; al[5] = tl;
-          split_bf16(a1.z, th, tl); ah[6] = th; al[6] = tl;
-          split_bf16(a1.w, th, tl); ah[7] = th; al[7] = tl;
+          split_bf16x8(a0, a1, ah, al);
 #pragma unroll
           for (int cb = 0; cb < NB; ++cb) {
             const bf16x8 xh = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
@@ -411,15 +397,11 @@ __global__ void __launch_bounds__(64 * NW) atx_dma_kernel(const float* __restric
     const float* Af = reinterpret_cast<const float*>(As);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
+      const float* col = Af + (16 * s + 8 * g) * TC + word;
+      const float4 a0 = make_float4(col[0], col[TC], col[2 * TC], col[3 * TC]);
+      const float4 a1 = make_float4(col[4 * TC], col[5 * TC], col[6 * TC], col[7 * TC]);
       bf16x8 bh, bl;
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const float x = Af[(16 * s + 8 * g + jj) * TC + word];
-        __bf16 th, tl;
-        split_bf16(x, th, tl);
-        bh[jj] = th;
-        bl[jj] = tl;
-      }
+      split_bf16x8(a0, a1, bh, bl);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
         const bf16x8 xh = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
@@ -467,20 +449,29 @@ struct PassChoice {
 // 3 (48 KB each) for nb = 4
 static int ring8(int nb) { return nb == 4 ? 3 : 4; }
 
+// nw: 16 = the tall form (built in where every CU gets 256 rows or more), 8
+// or 4 waves of 32 rows
 static PassChoice ax_choice(int nb, int64_t m, int num_cus, const TuneCfg* cfg) {
   const bool can8 = (nb == 2 || nb == 4);
-  PassChoice c{(can8 && m >= (int64_t)num_cus * 256) ? 8 : 4, 0};
+  PassChoice c{ax_tall_ok(m, num_cus) ? 16 : 4, 0};
+  if (cfg && cfg->ax_waves == 16) c.nw = 16;
   if (cfg && cfg->ax_waves == 8 && can8) c.nw = 8;
   if (cfg && cfg->ax_waves == 4) c.nw = 4;
-  c.S = c.nw == 8 ? ring8(nb) : ((cfg && cfg->ax_ring >= 2 && cfg->ax_ring <= 4) ? cfg->ax_ring : ring_depth(nb));
+  c.S = c.nw == 16 ? 0 : c.nw == 8 ? ring8(nb) : ((cfg && cfg->ax_ring >= 2 && cfg->ax_ring <= 4) ? cfg->ax_ring : ring_depth(nb));
   return c;
 }
 
-int ax_candidates(int nb, int (*out)[2]) {
+int atx_candidates(int nb, int (*out)[2]) {
   int k = 0;
   if (nb == 2 || nb == 4) { out[k][0] = 8; out[k][1] = ring8(nb); ++k; }
   for (int S = 2; S <= 4; ++S) { out[k][0] = 4; out[k][1] = S; ++k; }
   return k;
+}
+
+int ax_candidates(int nb, int (*out)[2]) {
+  out[0][0] = 16;
+  out[0][1] = 0;
+  return 1 + atx_candidates(nb, out + 1);
 }
 
 template <int NB>
@@ -488,6 +479,10 @@ static void launch_ax_dma(hipStream_t st, const float* A, int64_t lda, int64_t m
                           const __bf16* Xp, float* Y, int64_t ldy, int num_cus,
                           const TuneCfg* cfg) {
   const PassChoice c = ax_choice(NB, m, num_cus, cfg);
+  if (c.nw == 16) {
+    launch_ax_tall(st, A, 0, lda, m, n, Xp, Y, ldy, NB, num_cus);
+    return;
+  }
   const int stage = 32 * c.nw * 128 + NB * 4096;
   const int per_cu = std::max(1, (160 * 1024) / (c.S * stage));
   int64_t G = (int64_t)num_cus * per_cu;
@@ -683,7 +678,7 @@ size_t atx_partial_bytes_max(int64_t m, int64_t n, int nb, int num_cus, int dtyp
   size_t b = plan_atx(m, n, nb, num_cus, dtype, nullptr).partial_bytes;
   if (dtype != 0) return b;
   int cand[8][2];
-  const int k = ax_candidates(nb, cand);
+  const int k = atx_candidates(nb, cand);
   for (int i = 0; i < k; ++i) {
     TuneCfg c;
     c.atx_waves = cand[i][0];

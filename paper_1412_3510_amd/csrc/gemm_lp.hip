@@ -16,7 +16,7 @@
 // LDS ring filled by global_load_lds_dwordx4 (128-byte row segments, 16-byte
 // chunks XOR-swizzled), packed X fragments streamed beside it, products on
 // v_mfma_f32_32x32x16_bf16 with float32 accumulation.  E4M3 bytes are widened
-// to bfloat16 exactly (v_cvt_pk_f32_fp8, then the high half of the float32).
+// to bfloat16 exactly, two at a time (v_cvt_scalef32_pk_bf16_fp8, scale 1).
 #include <algorithm>
 #include <cstdlib>
 
@@ -25,22 +25,6 @@
 #include "kernels.h"
 
 namespace rpca {
-
-// 8 E4M3 values (two dwords) -> 8 bfloat16, exact.
-__device__ __forceinline__ bf16x8 fp8x8_to_bf16(unsigned w0, unsigned w1) {
-  typedef float f32x2 __attribute__((ext_vector_type(2)));
-  const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, false);
-  const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, true);
-  const f32x2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, false);
-  const f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, true);
-  // the high 16 bits of each float32 hold the value exactly (<= 4 significant bits)
-  unsigned p[4];
-  p[0] = __builtin_amdgcn_perm(__float_as_uint(a.y), __float_as_uint(a.x), 0x07060302u);
-  p[1] = __builtin_amdgcn_perm(__float_as_uint(b.y), __float_as_uint(b.x), 0x07060302u);
-  p[2] = __builtin_amdgcn_perm(__float_as_uint(c.y), __float_as_uint(c.x), 0x07060302u);
-  p[3] = __builtin_amdgcn_perm(__float_as_uint(d.y), __float_as_uint(d.x), 0x07060302u);
-  return __builtin_bit_cast(bf16x8, p);
-}
 
 template <int E>
 struct LpCfg {
@@ -84,7 +68,9 @@ __global__ void __launch_bounds__(64 * NW) ax_lp_kernel(const unsigned char* __r
   static_assert(S * STAGE <= 160 * 1024, "LDS ring");
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // scalar wave index: the per-wave choices (live rows) are scalar branches
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t rbeg = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t rend = min(m, rbeg + rows_per_wg);
   const int64_t nstage = ceil_div(n, KC);
@@ -312,14 +298,6 @@ constexpr bool lp_can8() {
   return (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 3;
 }
 
-// the 8-wave form of the A X kernel also with a two-stage ring (E4M3 at
-// nb = 4: 64 KB stages); unlike the row splits of A^T X, the tile height does
-// not change the order of any sum, so the results are the same either way
-template <int NB, int E>
-constexpr bool lp_ax_can8() {
-  return (LpCfg<E>::KS * NB) % 8 == 0 && lp_ring<NB, E, 8>() >= 2;
-}
-
 bool lp_atx_can8(int nb, int dtype) {
   if (dtype == 2) return nb == 1 ? lp_can8<1, 1>() : nb == 2 ? lp_can8<2, 1>() : lp_can8<4, 1>();
   return nb == 1 ? lp_can8<1, 2>() : nb == 2 ? lp_can8<2, 2>() : lp_can8<4, 2>();
@@ -358,35 +336,37 @@ static void ax_lp_launch(hipStream_t st, const unsigned char* A, int64_t lda, in
                      lda, m, n, Xp, Y, ldy, rows_per);
 }
 
-// 8 waves (256-row tiles) when the kernel has the form (lp_ax_can8) and every
-// CU gets a full tile; else 4 waves
+// the tall form (ax_tall.hip) where every CU gets 256 rows or more, else
+// 4 waves on 128-row tiles (either one when the configuration names it)
 template <int NB, int E>
 static void ax_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64_t m, int64_t n,
-                     const __bf16* Xp, float* Y, int64_t ldy, int num_cus) {
-  if constexpr (lp_ax_can8<NB, E>()) {
-    if (m >= (int64_t)num_cus * 256) {
-      ax_lp_launch<NB, E, 8>(st, A, lda, m, n, Xp, Y, ldy, num_cus);
-      return;
-    }
+                     const __bf16* Xp, float* Y, int64_t ldy, int num_cus, const TuneCfg* cfg) {
+  bool tall = ax_tall_ok(m, num_cus);
+  if (cfg && cfg->ax_waves == 16) tall = true;
+  if (cfg && cfg->ax_waves == 4) tall = false;
+  if (tall) {
+    launch_ax_tall(st, A, E == 2 ? 1 : 2, lda, m, n, Xp, Y, ldy, NB, num_cus);
+    return;
   }
   ax_lp_launch<NB, E, 4>(st, A, lda, m, n, Xp, Y, ldy, num_cus);
 }
 
 void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
-                  const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus) {
+                  const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus,
+                  const TuneCfg* cfg) {
   const unsigned char* a = static_cast<const unsigned char*>(A);
   if (dtype == 2) {
     switch (nb) {
-      case 1: ax_lp_go<1, 1>(st, a, lda, m, n, Xp, Y, ldy, num_cus); break;
-      case 2: ax_lp_go<2, 1>(st, a, lda, m, n, Xp, Y, ldy, num_cus); break;
-      case 4: ax_lp_go<4, 1>(st, a, lda, m, n, Xp, Y, ldy, num_cus); break;
+      case 1: ax_lp_go<1, 1>(st, a, lda, m, n, Xp, Y, ldy, num_cus, cfg); break;
+      case 2: ax_lp_go<2, 1>(st, a, lda, m, n, Xp, Y, ldy, num_cus, cfg); break;
+      case 4: ax_lp_go<4, 1>(st, a, lda, m, n, Xp, Y, ldy, num_cus, cfg); break;
       default: break;
     }
   } else {
     switch (nb) {
-      case 1: ax_lp_go<1, 2>(st, a, lda, m, n, Xp, Y, ldy, num_cus); break;
-      case 2: ax_lp_go<2, 2>(st, a, lda, m, n, Xp, Y, ldy, num_cus); break;
-      case 4: ax_lp_go<4, 2>(st, a, lda, m, n, Xp, Y, ldy, num_cus); break;
+      case 1: ax_lp_go<1, 2>(st, a, lda, m, n, Xp, Y, ldy, num_cus, cfg); break;
+      case 2: ax_lp_go<2, 2>(st, a, lda, m, n, Xp, Y, ldy, num_cus, cfg); break;
+      case 4: ax_lp_go<4, 2>(st, a, lda, m, n, Xp, Y, ldy, num_cus, cfg); break;
       default: break;
     }
   }

@@ -25,7 +25,8 @@ void launch_pack(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int 
 // class; the launchers fall back to the built-in choice for values they do
 // not support.
 struct TuneCfg {
-  int ax_waves = 0;   // waves per workgroup of Y = A X: 4 or 8 (8: lp = 64 or 128)
+  int ax_waves = 0;   // Y = A X: 4 or 8 waves of 32 rows (8: lp = 64 or 128), or
+                      // 16 for the tall form (8 waves of 64 rows, ax_tall.hip)
   int ax_ring = 0;    // LDS ring stages of the 4-wave form: 2, 3 or 4
   int atx_waves = 0;  // the same for A^T X
   int atx_ring = 0;
@@ -36,8 +37,15 @@ struct TuneCfg {
 void launch_ax(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus,
                const TuneCfg* cfg = nullptr);
-// the (waves, ring) pairs launch_ax can run for nb (the autotuner's candidates)
+// the (waves, ring) pairs launch_ax and launch_atx can run for nb (the
+// autotuner's candidates)
 int ax_candidates(int nb, int (*out)[2]);
+int atx_candidates(int nb, int (*out)[2]);
+// Y = A X in the tall form (any dtype, nb 1, 2 or 4; the layout rules of the
+// LDS-DMA kernels), and whether it is the built-in choice for m rows
+void launch_ax_tall(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+                    const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus);
+bool ax_tall_ok(int64_t m, int num_cus);
 // whether float32 A in this layout takes the LDS-DMA kernels (which have the
 // configurations above)
 bool dma_ok_shape(const void* A, int64_t lda, int64_t n);
@@ -73,8 +81,10 @@ int lp_per_cu(int nb, int dtype);
 // whether the low-precision kernels have their 8-wave (256-row / 256-column
 // tile) form for this nb and dtype
 bool lp_atx_can8(int nb, int dtype);
+// cfg (nullable): ax_waves 16 or 4 forces the tall or the 4-wave form
 void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
-                  const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus);
+                  const __bf16* Xp, float* Y, int64_t ldy, int nb, int num_cus,
+                  const TuneCfg* cfg = nullptr);
 void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                    const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
 // float32 A -> bfloat16 (dtype 1) or E4M3 with column scales (dtype 2)
