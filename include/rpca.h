@@ -427,7 +427,10 @@ rpca_status rpca_set_batch_streams(rpca_ctx ctx, int32_t streams);
  * ``out`` (nullable) receives the choice and the average launch time of each
  * chosen configuration.  Sparse A: RPCA_ERR_UNSUPPORTED. */
 typedef struct {
-  int32_t ax_waves, ax_ring;    /* Y = A X: waves per workgroup, ring stages */
+  int32_t ax_waves, ax_ring;    /* Y = A X: 4 or 8 waves of 32 rows and the ring
+                                   stages, or 16 (ring 0) for the tall form: 8
+                                   waves of 64 rows, the built-in choice when
+                                   every CU gets 256 rows or more */
   int32_t atx_waves, atx_ring;  /* A^T X                                     */
   int32_t lu_rows;              /* rows per tournament block                 */
   int32_t candidates;           /* configurations timed                      */
@@ -440,7 +443,10 @@ rpca_status rpca_tune(rpca_ctx ctx, const rpca_matrix* A, int32_t l, int32_t rep
  *   log2m log2n lp dtype ax_waves ax_ring atx_waves atx_ring lu_rows
  * (lines starting with '#' are comments).  Loading adds to the table and
  * replaces entries of the same class; a malformed line fails with
- * RPCA_ERR_INVALID_ARG and leaves the table as it was. */
+ * RPCA_ERR_INVALID_ARG and leaves the table as it was.  A loaded line also
+ * picks the A X form of a bfloat16 or E4M3 copy (dtype 1, 2): ax_waves 16
+ * the tall form, 4 the 4-wave form; other fields of such a line besides
+ * lu_rows are ignored. */
 rpca_status rpca_tune_save(rpca_ctx ctx, const char* path);
 rpca_status rpca_tune_load(rpca_ctx ctx, const char* path);
 rpca_status rpca_tune_clear(rpca_ctx ctx);

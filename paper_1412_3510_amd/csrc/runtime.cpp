@@ -414,7 +414,8 @@ void run_ax(rpca_ctx ctx, const AView& A, const Work& w, const __bf16* Xp, float
     launch_ax(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus,
               &w.cfg);
   else
-    launch_ax_lp(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus);
+    launch_ax_lp(ctx->stream, A.data, A.dtype, A.ld, A.m, A.n, Xp, Y, w.lp, w.nb, ctx->num_cus,
+                 &w.cfg);
   end_timed(ctx, t);
   ctx->stats.a_passes++;
 }
@@ -1630,8 +1631,9 @@ rpca_status rpca_tune(rpca_ctx ctx, const rpca_matrix* A, int32_t l, int32_t rep
   launch_fill_zero(st, w.Z, n * w.lp);
   launch_gaussian(st, 0x7475ull, 0u, n, l, w.Z, w.lp, nullptr);
   pack_n_side(ctx, w, w.Z, n, Av);
-  int cand[8][2];
+  int cand[8][2], acand[8][2];
   const int nc = ax_candidates(w.nb, cand);
+  const int nac = atx_candidates(w.nb, acand);
   if (f32 && dma_ok_shape(Av.data, Av.ld, n)) {
     double bms = 1e30;
     for (int i = 0; i < nc; ++i) {
@@ -1655,10 +1657,10 @@ rpca_status rpca_tune(rpca_ctx ctx, const rpca_matrix* A, int32_t l, int32_t rep
   }
   if (s == RPCA_OK && f32 && dma_ok_shape(Av.data, Av.ld, n)) {
     double bms = 1e30;
-    for (int i = 0; i < nc && s == RPCA_OK; ++i) {
+    for (int i = 0; i < nac && s == RPCA_OK; ++i) {
       TuneCfg c{};
-      c.atx_waves = cand[i][0];
-      c.atx_ring = cand[i][1];
+      c.atx_waves = acand[i][0];
+      c.atx_ring = acand[i][1];
       const AtxPlan plan = plan_atx(m, n, w.nb, ctx->num_cus, RPCA_F32, &c);
       double ms = 0;
       s = timed([&] {

@@ -164,7 +164,6 @@ void launch_fro2_d(hipStream_t st, const float* X, int64_t ldx, int64_t rows, in
 // ------------------------------------------------------------------------
 static constexpr int kGramMaxBlocks = 256;
 static constexpr int kGramSlice = 32;
-static constexpr int64_t kGramTall = (int64_t)kGramMaxBlocks * kGramSlice * 4;  // NG = 4 from here
 
 template <int LP, int NG>
 struct GramCfg {
