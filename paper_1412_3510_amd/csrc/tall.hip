@@ -262,22 +262,46 @@ __global__ void __launch_bounds__(256 * NG) gram_kernel(const float* __restrict_
 
 // The same Gram matrix on the float64 matrix cores (lp = 32, 64):
 // v_mfma_f64_16x16x4f64 takes a 16 x 4 block of X^T and a 4 x 16 block of
-// X2 -- in both, lane L holds the entry (row r + L / 16, column 16 t + L % 16)
-// of X or X2, loaded straight from memory -- and lane L's register q of the
-// 16 x 16 result is entry (L / 16 + 4 q, L % 16).  A wave accumulates the
-// (lp / 16)^2 tiles (only those with ti <= tj when X2 = X: the rest follow
-// by symmetry) over 4-row groups of its rows; the waves of the workgroup
-// then add their tiles in LDS in wave order.  Products of float32 values are
-// exact in float64 and every sum is in float64, as in gram_kernel; only the
-// order of the additions differs.
-static constexpr int kGramWaves = 4;
+// X2, lane L holding row r + L / 16 of both, and lane L's register q of the
+// 16 x 16 result is entry (L / 16 + 4 q, L % 16).  Tile t of each dimension
+// holds the columns T i + t (i = 0..15, T = lp / 16), so lane L's T entries
+// of a row -- columns T (L % 16) .. T (L % 16) + T - 1 -- are contiguous and
+// come in one 8- or 16-byte load, and result entry (i, j) of tile pair
+// (ti, tj) is G[T i + ti][T j + tj].  A wave accumulates the T^2 tile pairs
+// (those with ti <= tj when X2 = X: the rest follow by symmetry) over 4-row
+// groups of its rows, U groups in flight; the waves of the workgroup then
+// add their tiles in LDS in wave order (8 waves at lp = 32, 4 at lp = 64,
+// where the wider tiles already keep the loads in flight).  Products of
+// float32 values are exact in float64 and every sum is in float64, as in
+// gram_kernel; only the order of the additions differs.
+template <int LP>
+__host__ __device__ constexpr int gram_waves() { return LP == 32 ? 8 : 4; }
+
+template <int T>
+__device__ __forceinline__ void gram_load_row(const float* __restrict__ p, bool ok, double* out) {
+  if constexpr (T == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    out[0] = ok ? (double)v.x : 0.0;
+    out[1] = ok ? (double)v.y : 0.0;
+  } else {
+#pragma unroll
+    for (int h = 0; h < T / 4; ++h) {
+      const float4 v = *reinterpret_cast<const float4*>(p + 4 * h);
+      out[4 * h + 0] = ok ? (double)v.x : 0.0;
+      out[4 * h + 1] = ok ? (double)v.y : 0.0;
+      out[4 * h + 2] = ok ? (double)v.z : 0.0;
+      out[4 * h + 3] = ok ? (double)v.w : 0.0;
+    }
+  }
+}
 
 template <int LP, bool SAME>
-__global__ void __launch_bounds__(64 * kGramWaves) gram_mfma_kernel(
+__global__ void __launch_bounds__(64 * gram_waves<LP>()) gram_mfma_kernel(
     const float* __restrict__ X, int64_t ldx, const float* __restrict__ X2, int64_t ldx2,
     int64_t rows, double* __restrict__ partial, const int* __restrict__ skip_flag) {
   if (skip_flag && *skip_flag == 0) return;
   typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int kGramWaves = gram_waves<LP>();
   constexpr int T = LP / 16;
   constexpr int NT2 = SAME ? T * (T + 1) / 2 : T * T;  // tiles a wave accumulates
   constexpr int U = 4;                                 // 4-row groups per step (loads in flight)
@@ -298,15 +322,8 @@ __global__ void __launch_bounds__(64 * kGramWaves) gram_mfma_kernel(
       const int64_t r = g0 + 4 * kGramWaves * u + lr;
       const bool ok = r < r1;
       const int64_t rc = ok ? r : r0;
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const float va = X[rc * ldx + 16 * t + lc];
-        a[u][t] = ok ? (double)va : 0.0;
-        if (!SAME) {
-          const float vb = X2p[rc * ld2 + 16 * t + lc];
-          b[u][t] = ok ? (double)vb : 0.0;
-        }
-      }
+      gram_load_row<T>(X + rc * ldx + T * lc, ok, a[u]);
+      if (!SAME) gram_load_row<T>(X2p + rc * ld2 + T * lc, ok, b[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -331,7 +348,7 @@ __global__ void __launch_bounds__(64 * kGramWaves) gram_mfma_kernel(
         for (int tj = SAME ? ti : 0; tj < T; ++tj) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int i = 16 * ti + lr + 4 * q, j = 16 * tj + lc;
+            const int i = T * (lr + 4 * q) + ti, j = T * lc + tj;
             const double v = (w == 0) ? acc[t][q] : sh[i * LP + j] + acc[t][q];
             sh[i * LP + j] = v;
             if (SAME && ti != tj) sh[j * LP + i] = v;
@@ -349,8 +366,10 @@ __global__ void __launch_bounds__(64 * kGramWaves) gram_mfma_kernel(
 // are dealt to the four waves in order, 9 (16) each; every wave walks all
 // the workgroup's 4-row groups for its own tiles (the four waves read the
 // same rows, mostly from L1) and writes its tiles, and their mirror images,
-// straight to the workgroup's partial.  A wave's tiles are compile-time
-// constants (one instantiation per wave), so its operands are plain registers.
+// straight to the workgroup's partial.  As at lp = 32 and 64, tile t holds
+// the columns 8 i + t, so a lane reads its 8 entries of a row as two 16-byte
+// loads.  A wave's tiles are compile-time constants (one instantiation per
+// wave), so its operands are plain registers.
 // upper tiles (ti <= tj) of the 8 x 8 tile grid in row order
 __device__ constexpr int kG128Ti[36] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 4, 4, 4, 4, 5, 5, 5, 6, 6, 7};
 __device__ constexpr int kG128Tj[36] = {0, 1, 2, 3, 4, 5, 6, 7, 1, 2, 3, 4, 5, 6, 7, 2, 3, 4, 5, 6, 7, 3, 4, 5, 6, 7, 4, 5, 6, 7, 5, 6, 7, 6, 7, 7};
@@ -366,30 +385,24 @@ __device__ __forceinline__ void gram128_wave(const float* __restrict__ X, int64_
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int LP = 128, T = 8;
   constexpr int NTOT = SAME ? T * (T + 1) / 2 : T * T, PER = NTOT / 4;
+  constexpr int U = SAME ? 4 : 2;  // 4-row groups per step (loads in flight)
   static_assert(PER * 4 == NTOT, "tiles per wave");
   const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
   d4 acc[PER];
 #pragma unroll
   for (int t = 0; t < PER; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t g0 = r0; g0 < r1; g0 += 8) {
-    double a[2][T], b[2][T];
+  for (int64_t g0 = r0; g0 < r1; g0 += 4 * U) {
+    double a[U][T], b[U][T];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t r = g0 + 4 * u + lr;
       const bool ok = r < r1;
       const int64_t rc = ok ? r : r0;
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const float va = X[rc * ldx + 16 * t + lc];
-        a[u][t] = ok ? (double)va : 0.0;
-        if constexpr (!SAME) {
-          const float vb = X2[rc * ld2 + 16 * t + lc];
-          b[u][t] = ok ? (double)vb : 0.0;
-        }
-      }
+      gram_load_row<T>(X + rc * ldx + T * lc, ok, a[u]);
+      if constexpr (!SAME) gram_load_row<T>(X2 + rc * ld2 + T * lc, ok, b[u]);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int ti = g128_ti<SAME>(W * PER + k), tj = g128_tj<SAME>(W * PER + k);
@@ -402,7 +415,7 @@ __device__ __forceinline__ void gram128_wave(const float* __restrict__ X, int64_
     const int ti = g128_ti<SAME>(W * PER + k), tj = g128_tj<SAME>(W * PER + k);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = 16 * ti + lr + 4 * q, j = 16 * tj + lc;
+      const int i = T * (lr + 4 * q) + ti, j = T * lc + tj;
       out[i * LP + j] = acc[k][q];
       if (SAME && ti != tj) out[j * LP + i] = acc[k][q];
     }
@@ -431,12 +444,12 @@ void launch_gram(hipStream_t st, const float* X, int64_t ldx, int64_t rows, int 
                  const int* skip_flag) {
   int nblk;
   if (lp == 32 || lp == 64) {
-    // the matrix-core form: one workgroup of four waves per 256 rows, at most
+    // the matrix-core form: one workgroup per 256 rows, at most
     // kGramMaxBlocks workgroups
     const int64_t b = ceil_div(rows > 0 ? rows : 1, (int64_t)256);
     nblk = (int)(b < kGramMaxBlocks ? b : kGramMaxBlocks);
 #define GRAM_MF(LP_, SAME_)                                                                     \
-  hipLaunchKernelGGL((gram_mfma_kernel<LP_, SAME_>), dim3(nblk), dim3(64 * kGramWaves), 0, st, X, \
+  hipLaunchKernelGGL((gram_mfma_kernel<LP_, SAME_>), dim3(nblk), dim3(64 * gram_waves<LP_>()), 0, st, X, \
                      ldx, X2, ldx2, rows, partial, skip_flag)
     if (lp == 32) {
       if (X2) GRAM_MF(32, false); else GRAM_MF(32, true);
