@@ -635,10 +635,17 @@ __global__ void __launch_bounds__(256) atx_f32_kernel(const float* __restrict__ 
 // on wide, tall A, else 4; the low-precision kernels have one configuration.
 static PassChoice atx_choice(int64_t m, int64_t n, int nb, int num_cus, int dtype,
                              const TuneCfg* cfg) {
-  // low precision: 256-column tiles where the kernel has the form, on wide,
-  // tall A (its ring depth is fixed by the stage size)
-  if (dtype != 0)
-    return PassChoice{(lp_atx_can8(nb, dtype) && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4, 0};
+  // low precision: the wide form (512-column tiles) on wide, tall A, else
+  // 256-column tiles where the kernel has the form (its ring depth is fixed
+  // by the stage size), else 128; a loaded configuration may name 16 or 4
+  if (dtype != 0) {
+    const bool big = n >= 1024 && m >= (int64_t)num_cus * 128;
+    int nw = big ? 16 : 4;
+    if (cfg && cfg->atx_waves == 16) nw = 16;
+    if (cfg && cfg->atx_waves == 4) nw = 4;
+    if (cfg && cfg->atx_waves == 8) nw = lp_atx_can8(nb, dtype) ? 8 : 4;
+    return PassChoice{nw, 0};
+  }
   // built in: 8 waves for nb = 2 only (at nb = 4 the 4-wave form measured
   // faster: 1.42 against 1.55 ms at 200000 x 8000); the autotuner may pick 8
   const bool can8 = (nb == 2 || nb == 4);
@@ -655,11 +662,12 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype, const Tun
   p.ntiles = (int)ceil_div(n, 128);
   p.waves = c.nw;
   p.ring = c.S;
-  p.gtiles = (int)ceil_div(n, 32 * p.waves);
-  const int rs = dtype == 0 ? 32 : lp_rows_per_stage(dtype);  // rows per stage
+  p.gtiles = (int)ceil_div(n, p.waves == 16 ? 512 : 32 * p.waves);
+  const int rs = dtype == 0 ? 32 : p.waves == 16 ? atx_wide_rows_per_stage(dtype)
+                                                 : lp_rows_per_stage(dtype);  // rows per stage
   const int64_t stages = ceil_div(m, rs);
   // workgroups resident per CU for the LDS ring of the DMA kernel
-  const int per_cu = p.waves == 8 ? 1
+  const int per_cu = p.waves >= 8 ? 1
                      : dtype == 0 ? std::max(1, (160 * 1024) / (p.ring * dma_stage_bytes(nb)))
                                   : lp_per_cu(nb, dtype);
   int64_t want = (int64_t)per_cu * num_cus / p.gtiles;
@@ -676,7 +684,14 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype, const Tun
 
 size_t atx_partial_bytes_max(int64_t m, int64_t n, int nb, int num_cus, int dtype) {
   size_t b = plan_atx(m, n, nb, num_cus, dtype, nullptr).partial_bytes;
-  if (dtype != 0) return b;
+  if (dtype != 0) {
+    for (int w : {4, 8, 16}) {  // every form a loaded configuration may name
+      TuneCfg c;
+      c.atx_waves = w;
+      b = std::max(b, plan_atx(m, n, nb, num_cus, dtype, &c).partial_bytes);
+    }
+    return b;
+  }
   int cand[8][2];
   const int k = atx_candidates(nb, cand);
   for (int i = 0; i < k; ++i) {

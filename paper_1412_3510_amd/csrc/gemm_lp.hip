@@ -392,6 +392,10 @@ static void atx_lp_go(hipStream_t st, const unsigned char* A, int64_t lda, int64
 
 void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                    const __bf16* Xp, float* P, const AtxPlan& plan, int nb) {
+  if (plan.waves == 16) {
+    launch_atx_wide(st, A, dtype, lda, m, n, Xp, P, plan, nb);
+    return;
+  }
   const unsigned char* a = static_cast<const unsigned char*>(A);
   if (dtype == 2) {
     switch (nb) {

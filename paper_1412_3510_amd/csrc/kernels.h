@@ -53,7 +53,8 @@ bool dma_ok_shape(const void* A, int64_t lda, int64_t n);
 // Split-K partial products of A^T X (X packed on the m side).
 struct AtxPlan {
   int ntiles;        // ceil(n / 128): the partials hold 4 * ntiles 32-column blocks per split
-  int waves;         // waves per workgroup of the DMA kernel (4 or 8)
+  int waves;         // waves per workgroup of the DMA kernel (4 or 8), or 16 for the
+                     // wide form of a low-precision copy (8 waves, 512-column tiles)
   int ring;          // its LDS ring stages
   int gtiles;        // column tiles of that kernel, ceil(n / (32 * waves))
   int nsplit;        // number of row splits
@@ -87,6 +88,10 @@ void launch_ax_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t
                   const TuneCfg* cfg = nullptr);
 void launch_atx_lp(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                    const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
+// the wide form (atx_wide.hip): rows per stage, and the launch
+int atx_wide_rows_per_stage(int dtype);
+void launch_atx_wide(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
+                     const __bf16* Xp, float* P, const AtxPlan& plan, int nb);
 // float32 A -> bfloat16 (dtype 1) or E4M3 with column scales (dtype 2)
 size_t quantize_work_bytes(int64_t m, int64_t n);
 void launch_quantize(hipStream_t st, const float* A, int64_t lda, int64_t m, int64_t n, int dtype,

@@ -1,5 +1,7 @@
 """Y = A X in the tall form (8 waves of 64 rows, 64-byte row segments per
-stage, equal tiles per workgroup), on the GPU through the C ABI.
+stage, equal tiles per workgroup), and the partials of A^T Q in the wide form
+(8 waves of 64 columns, 512-column tiles) for the low-precision copies, on
+the GPU through the C ABI.
 
   * For the float32, bfloat16 and E4M3 copies of A, the tall form gives the
     same Y bit for bit as the 4-wave form. Both accumulate the K16 steps in
@@ -13,11 +15,18 @@ stage, equal tiles per workgroup), on the GPU through the C ABI.
     - n of one or two stages, so that the copies of the next tile are issued
       before the current tile is consumed;
     - lp = 32, 64 and 128.
+  * The wide form of A^T Q (bfloat16 and E4M3 copies), forced through a
+    loaded tune table like the 128-column form, is within (m + 3) 2^-24
+    (|A8^T| |Q'|) s_j of the float64 product of the same rounded operands (Q'
+    the operand rounded to bfloat16, s_j the E4M3 column scale), on ragged
+    row splits and a last tile of 16 columns.
 """
 
 import numpy as np
 import pytest
 import torch
+
+from oracle import precision
 
 pytestmark = pytest.mark.gpu
 
@@ -90,3 +99,39 @@ def test_tall_equals_four_wave_form(ctx, gpu_lib, tmp_path, kind, m, n, l):
         bound = (2.0 ** -15 + n * 2.0 ** -24) * (np.abs(A64) @ np.abs(X)) + 1e-30
         assert np.all(np.abs(Yt.cpu().numpy() - ref) <= bound)
 
+
+
+def _forced_atx(ctx, tmp_path, m, n, l, dtype, waves, run):
+    path = tmp_path / ("atx%d.txt" % waves)
+    path.write_text("# forced\n%s 0 0 %d 0 0\n" % (_class(m, n, l, dtype), waves))
+    ctx.tune_clear()
+    ctx.tune_load(str(path))
+    try:
+        return run()
+    finally:
+        ctx.tune_clear()
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("m,n,l", [(5000, 528, 30), (70001, 1040, 120), (40, 512, 60),
+                                   (12345, 2048, 64)])
+def test_wide_atx_within_bound(ctx, gpu_lib, tmp_path, kind, m, n, l):
+    rng = np.random.default_rng(m + n + l)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    Q = rng.standard_normal((m, l)).astype(np.float32)
+    dA, dQ = _dev(A), _dev(Q)
+    q, s = ctx.quantize(dA, kind)
+    mat = gpu_lib.dense(q, col_scale=s, A_f32=dA)
+    if kind == "bf16":
+        A8 = precision.from_bf16_bits(q.view(torch.int16).cpu().numpy().view(np.uint16))
+        sh = np.ones(n)
+    else:
+        A8 = precision.e4m3_decode(q.view(torch.uint8).cpu().numpy())
+        sh = s.cpu().numpy().astype(np.float64)
+    Qb = precision.to_bf16(Q)
+    want = (A8.T @ Qb) * sh[:, None]
+    bound = (m + 3) * 2.0 ** -24 * (np.abs(A8.T) @ np.abs(Qb)) * sh[:, None] + 1e-30
+    run = lambda: ctx.matmul(q, dQ, trans=True, mat=mat).cpu().numpy()  # noqa: E731
+    for waves in (16, 4):
+        Z = _forced_atx(ctx, tmp_path, m, n, l, DT[kind], waves, run)
+        assert np.all(np.abs(Z - want) <= bound), waves
