@@ -1,13 +1,15 @@
-// Partials of A^T X, wide form, for the bfloat16 and E4M3 copies of A (the
-// passes of the range finder; the E4M3 column scales apply to the rows of
-// the reduced result).  Section 2 prices the method by its passes over A;
+// Partials of A^T X, wide form, for the float32 A (products as three
+// bfloat16 terms of the split operands) and its bfloat16 and E4M3 copies
+// (one term on the operand's high part; the E4M3 column scales apply to the
+// rows of the reduced result).  Section 2 prices the method by its passes over A;
 // what this kernel changes against the 128- and 256-column tiles of
 // gemm_lp.hip is the share of each stage that the packed m-side operand
 // takes, and how often that operand is read:
 //
 //  * 8 waves own two 32-column blocks each: tiles of 512 columns.  A stage
-//    is 32 KB of A -- 32 rows of bfloat16 or 64 rows of E4M3 -- and the
-//    operand fragments of those rows (8 KB, 16 KB for E4M3 at lp = 128)
+//    is 32 KB of A -- 16 rows of float32, 32 of bfloat16 or 64 of E4M3 --
+//    and the operand fragments of those rows (8 KB, 16 KB for E4M3 at
+//    lp = 128)
 //    serve all 512 columns; at 128 columns, E4M3 stages held 16 KB of A and
 //    32 KB of operand.  The operand is read once per column tile, so 16
 //    times at n = 8000 instead of 63.
@@ -16,9 +18,10 @@
 //    counts this wave's copies issued after it.
 //
 // LDS: row k of a stage occupies RB = 512 E bytes; its 16-byte chunk c sits
-// at position c ^ (4 ((k >> 3) & 1)), so that the two halves of a wave,
-// which read rows 8 apart, fall on different banks.  A 1 KB DMA block is
-// one bfloat16 row or two E4M3 rows; block q is issued by wave q % 8.  Each
+// at position c ^ (2 E ((k >> 3) & 1)), so that the two halves of a wave,
+// which read 32 E bytes each in rows 8 apart, fall on different banks.  A
+// 1 KB DMA block is half a float32 row, one bfloat16 row or two E4M3 rows;
+// block q is issued by wave q % 8.  Each
 // lane gathers the 8 entries of its column in 8 consecutive rows of a K16
 // step (the B operand of v_mfma_f32_32x32x16_bf16); the operand fragment is
 // the A operand.  Partials are laid out by 32-column block, ntiles * 4
@@ -37,13 +40,14 @@ struct WideCfg {
   static constexpr int RB = TC * E;                   // bytes per tile row
   static constexpr int KR = 32768 / RB;               // rows per stage
   static constexpr int KS = KR / 16;                  // K16 steps per stage
-  static constexpr int XF = KS * NB;                  // 1 KB operand fragments per stage
+  static constexpr int XF = KS * NB * (E == 4 ? 2 : 1);  // 1 KB operand fragments per stage
   static constexpr int ABYTES = 32768;
   static constexpr int STAGE = ABYTES + XF * 1024;
   static constexpr int S = (160 * 1024) / STAGE > 4 ? 4 : (160 * 1024) / STAGE;
 };
 
-__device__ __forceinline__ int wide_swz(int k) { return 4 * ((k >> 3) & 1); }
+template <int E>
+__device__ __forceinline__ int wide_swz(int k) { return 2 * E * ((k >> 3) & 1); }
 
 template <int NB, int E>
 __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __restrict__ A,
@@ -55,6 +59,7 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
   constexpr int RB = C::RB, KR = C::KR, KS = C::KS, XF = C::XF, S = C::S, STAGE = C::STAGE;
   constexpr int ABYTES = C::ABYTES;
   constexpr int XFW = (XF + 7) / 8;
+  constexpr int XSTRIDE = E == 4 ? 1 : 2;  // KB between consecutive fragments in Xp
   static_assert(S >= 2 && S * STAGE <= 160 * 1024 && KR % 16 == 0, "stage shape");
   __shared__ __attribute__((aligned(1024))) char ring[S * STAGE];
 
@@ -79,7 +84,7 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
     const int byte = 1024 * (wave + 8 * i) + 16 * lane;
     const int k = byte / RB, pos = (byte % RB) / 16;
     rr[i] = k;
-    const int64_t cb = col0 * E + 16 * (pos ^ wide_swz(k));
+    const int64_t cb = col0 * E + 16 * (pos ^ wide_swz<E>(k));
     cbyte[i] = (cb + 16 <= nbytes) ? cb : 0;  // past n: any valid chunk (columns never stored)
   }
   int issued = 0, done = 0, islot = 0;
@@ -95,7 +100,8 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
 #pragma unroll
     for (int jx = 0; jx < XFW; ++jx) {
       const int f = wave + 8 * jx;
-      if (f < XF) dma16(xg + ((ist * XF + f) * 2) * 1024 + 16 * lane, slot + ABYTES + f * 1024);
+      if (f < XF)
+        dma16(xg + ((ist * XF + f) * XSTRIDE) * 1024 + 16 * lane, slot + ABYTES + f * 1024);
     }
     issued += per;
     islot = islot + 1 == S ? 0 : islot + 1;
@@ -125,21 +131,36 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
     const char* Xs = As + ABYTES;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      bf16x8 xh[NB];
+      bf16x8 xh[NB], xl[NB];
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
-        xh[cb] = *reinterpret_cast<const bf16x8*>(Xs + (s * NB + cb) * 1024 + 16 * lane);
+      for (int cb = 0; cb < NB; ++cb) {
+        if (E == 4) {
+          xh[cb] = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2) * 1024 + 16 * lane);
+          xl[cb] = *reinterpret_cast<const bf16x8*>(Xs + ((s * NB + cb) * 2 + 1) * 1024 + 16 * lane);
+        } else {
+          xh[cb] = *reinterpret_cast<const bf16x8*>(Xs + (s * NB + cb) * 1024 + 16 * lane);
+        }
+      }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int cbt = (64 * wave + 32 * b + jl) * E;  // byte of the column in a tile row
         const int chunk = cbt / 16, off = cbt % 16;
-        bf16x8 bop;
-        if (E == 2) {
+        bf16x8 bop, bopl;
+        if (E == 4) {
+          float v[8];
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) {
+            const int k = 16 * s + 8 * g + jj;
+            v[jj] = *reinterpret_cast<const float*>(As + k * RB + 16 * (chunk ^ wide_swz<E>(k)) + off);
+          }
+          split_bf16x8(make_float4(v[0], v[1], v[2], v[3]), make_float4(v[4], v[5], v[6], v[7]),
+                       bop, bopl);
+        } else if (E == 2) {
           unsigned short h[8];
 #pragma unroll
           for (int jj = 0; jj < 8; ++jj) {
             const int k = 16 * s + 8 * g + jj;
-            h[jj] = *reinterpret_cast<const unsigned short*>(As + k * RB + 16 * (chunk ^ wide_swz(k)) + off);
+            h[jj] = *reinterpret_cast<const unsigned short*>(As + k * RB + 16 * (chunk ^ wide_swz<E>(k)) + off);
           }
           bop = __builtin_bit_cast(bf16x8, h);
         } else {
@@ -151,7 +172,7 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
             for (int jj = 0; jj < 4; ++jj) {
               const int k = 16 * s + 8 * g + 4 * qq + jj;
               const unsigned byte = *reinterpret_cast<const unsigned char*>(
-                  As + k * RB + 16 * (chunk ^ wide_swz(k)) + off);
+                  As + k * RB + 16 * (chunk ^ wide_swz<E>(k)) + off);
               v |= byte << (8 * jj);
             }
             w[qq] = v;
@@ -159,8 +180,10 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
           bop = fp8x8_to_bf16(w[0], w[1]);
         }
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-          acc[b][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[cb], bop, acc[b][cb], 0, 0, 0);
+        for (int cb = 0; cb < NB; ++cb) {
+          if (E == 4) acc[b][cb] = mfma3(xh[cb], xl[cb], bop, bopl, acc[b][cb]);
+          else acc[b][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[cb], bop, acc[b][cb], 0, 0, 0);
+        }
       }
     }
     cslot = cslot + 1 == S ? 0 : cslot + 1;
@@ -177,7 +200,9 @@ __global__ void __launch_bounds__(512) atx_wide_kernel(const unsigned char* __re
   }
 }
 
-int atx_wide_rows_per_stage(int dtype) { return dtype == 2 ? WideCfg<1, 4>::KR : WideCfg<2, 4>::KR; }
+int atx_wide_rows_per_stage(int dtype) {
+  return dtype == 2 ? WideCfg<1, 4>::KR : dtype == 1 ? WideCfg<2, 4>::KR : WideCfg<4, 4>::KR;
+}
 
 void launch_atx_wide(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m, int64_t n,
                      const __bf16* Xp, float* P, const AtxPlan& plan, int nb) {
@@ -191,7 +216,8 @@ void launch_atx_wide(hipStream_t st, const void* A, int dtype, int64_t lda, int6
     default: break;                                                                                \
   }
   if (dtype == 2) { RPCA_WIDE(1) }
-  else { RPCA_WIDE(2) }
+  else if (dtype == 1) { RPCA_WIDE(2) }
+  else { RPCA_WIDE(4) }
 #undef RPCA_WIDE
 }
 

@@ -463,15 +463,18 @@ static PassChoice ax_choice(int nb, int64_t m, int num_cus, const TuneCfg* cfg) 
 
 int atx_candidates(int nb, int (*out)[2]) {
   int k = 0;
+  out[k][0] = 16; out[k][1] = 0; ++k;  // the wide form (atx_wide.hip)
   if (nb == 2 || nb == 4) { out[k][0] = 8; out[k][1] = ring8(nb); ++k; }
   for (int S = 2; S <= 4; ++S) { out[k][0] = 4; out[k][1] = S; ++k; }
   return k;
 }
 
 int ax_candidates(int nb, int (*out)[2]) {
-  out[0][0] = 16;
-  out[0][1] = 0;
-  return 1 + atx_candidates(nb, out + 1);
+  int k = 0;
+  out[k][0] = 16; out[k][1] = 0; ++k;  // the tall form (ax_tall.hip)
+  if (nb == 2 || nb == 4) { out[k][0] = 8; out[k][1] = ring8(nb); ++k; }
+  for (int S = 2; S <= 4; ++S) { out[k][0] = 4; out[k][1] = S; ++k; }
+  return k;
 }
 
 template <int NB>
@@ -646,13 +649,16 @@ static PassChoice atx_choice(int64_t m, int64_t n, int nb, int num_cus, int dtyp
     if (cfg && cfg->atx_waves == 8) nw = lp_atx_can8(nb, dtype) ? 8 : 4;
     return PassChoice{nw, 0};
   }
-  // built in: 8 waves for nb = 2 only (at nb = 4 the 4-wave form measured
-  // faster: 1.42 against 1.55 ms at 200000 x 8000); the autotuner may pick 8
+  // built in: the wide form (512-column tiles, atx_wide.hip) on wide, tall
+  // A -- 0.315 against 0.325 ms (8 waves) at 100000 x 4000, l = 60, and 1.49
+  // against 1.62 ms (4 waves) at 200000 x 8000, l = 120 -- else 4 waves; the
+  // autotuner may pick any form
   const bool can8 = (nb == 2 || nb == 4);
-  PassChoice c{(nb == 2 && n >= 1024 && m >= (int64_t)num_cus * 128) ? 8 : 4, 0};
+  PassChoice c{(n >= 1024 && m >= (int64_t)num_cus * 128) ? 16 : 4, 0};
+  if (cfg && cfg->atx_waves == 16) c.nw = 16;
   if (cfg && cfg->atx_waves == 8 && can8) c.nw = 8;
   if (cfg && cfg->atx_waves == 4) c.nw = 4;
-  c.S = c.nw == 8 ? ring8(nb) : ((cfg && cfg->atx_ring >= 2 && cfg->atx_ring <= 4) ? cfg->atx_ring : ring_depth(nb));
+  c.S = c.nw == 16 ? 0 : c.nw == 8 ? ring8(nb) : ((cfg && cfg->atx_ring >= 2 && cfg->atx_ring <= 4) ? cfg->atx_ring : ring_depth(nb));
   return c;
 }
 
@@ -663,8 +669,8 @@ AtxPlan plan_atx(int64_t m, int64_t n, int nb, int num_cus, int dtype, const Tun
   p.waves = c.nw;
   p.ring = c.S;
   p.gtiles = (int)ceil_div(n, p.waves == 16 ? 512 : 32 * p.waves);
-  const int rs = dtype == 0 ? 32 : p.waves == 16 ? atx_wide_rows_per_stage(dtype)
-                                                 : lp_rows_per_stage(dtype);  // rows per stage
+  const int rs = p.waves == 16 ? atx_wide_rows_per_stage(dtype)
+                 : dtype == 0 ? 32 : lp_rows_per_stage(dtype);  // rows per stage
   const int64_t stages = ceil_div(m, rs);
   // workgroups resident per CU for the LDS ring of the DMA kernel
   const int per_cu = p.waves >= 8 ? 1
@@ -708,6 +714,10 @@ void launch_atx(hipStream_t st, const void* A, int dtype, int64_t lda, int64_t m
   (void)dtype;
   const float* Af = static_cast<const float*>(A);
   const dim3 grid((unsigned)(plan.ntiles * plan.nsplit));
+  if (dma_ok(Af, lda, n) && plan.waves == 16) {
+    launch_atx_wide(st, A, 0, lda, m, n, Xp, P, plan, nb);
+    return;
+  }
   if (dma_ok(Af, lda, n)) {
     const int S = plan.ring;
     if (plan.waves == 8 && nb == 2) {

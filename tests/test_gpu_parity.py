@@ -49,8 +49,8 @@ def _product_bound(A, X, K):
 
 
 # n % 4 == 0 takes the LDS-DMA kernels, other n the register-staged ones;
-# m >= 65536 takes the tall form of A X and, with n >= 1024 at l = 60, the
-# 8-wave form of A^T X
+# m >= 65536 takes the tall form of A X and, with n >= 1024, the wide form
+# of A^T X (512-column tiles; at n = 1028 the last one 4 columns wide)
 @pytest.mark.parametrize("m,n,l", [(1000, 500, 12), (777, 333, 60), (300, 1000, 120),
                                    (65, 97, 33), (4099, 257, 64), (4099, 260, 64),
                                    (131, 1028, 120), (70001, 400, 60), (33, 36, 30),

@@ -15,10 +15,11 @@ the GPU through the C ABI.
     - n of one or two stages, so that the copies of the next tile are issued
       before the current tile is consumed;
     - lp = 32, 64 and 128.
-  * The wide form of A^T Q (bfloat16 and E4M3 copies), forced through a
-    loaded tune table like the 128-column form, is within (m + 3) 2^-24
+  * The wide form of A^T Q, forced through a loaded tune table like the
+    128-column form: for the bfloat16 and E4M3 copies within (m + 3) 2^-24
     (|A8^T| |Q'|) s_j of the float64 product of the same rounded operands (Q'
-    the operand rounded to bfloat16, s_j the E4M3 column scale), on ragged
+    the operand rounded to bfloat16, s_j the E4M3 column scale), for float32
+    A within the split-product bound (2^-15 + m 2^-24)(|A^T| |Q|), on ragged
     row splits and a last tile of 16 columns.
 """
 
@@ -112,7 +113,7 @@ def _forced_atx(ctx, tmp_path, m, n, l, dtype, waves, run):
         ctx.tune_clear()
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("m,n,l", [(5000, 528, 30), (70001, 1040, 120), (40, 512, 60),
                                    (12345, 2048, 64)])
 def test_wide_atx_within_bound(ctx, gpu_lib, tmp_path, kind, m, n, l):
@@ -120,6 +121,16 @@ def test_wide_atx_within_bound(ctx, gpu_lib, tmp_path, kind, m, n, l):
     A = rng.standard_normal((m, n)).astype(np.float32)
     Q = rng.standard_normal((m, l)).astype(np.float32)
     dA, dQ = _dev(A), _dev(Q)
+    if kind == "f32":
+        # the split-bfloat16 product bound against the float64 product
+        A64 = A.astype(np.float64)
+        want = A64.T @ Q.astype(np.float64)
+        bound = (2.0 ** -15 + m * 2.0 ** -24) * (np.abs(A64.T) @ np.abs(Q)) + 1e-30
+        run = lambda: ctx.matmul(dA, dQ, trans=True).cpu().numpy()  # noqa: E731
+        for waves in (16, 4):
+            Z = _forced_atx(ctx, tmp_path, m, n, l, 0, waves, run)
+            assert np.all(np.abs(Z - want) <= bound), waves
+        return
     q, s = ctx.quantize(dA, kind)
     mat = gpu_lib.dense(q, col_scale=s, A_f32=dA)
     if kind == "bf16":

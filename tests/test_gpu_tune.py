@@ -1,9 +1,9 @@
 """The autotuner (rpca_tune) and its table, on the GPU, through the C ABI.
 
   * rpca_tune times every candidate configuration (for lp = 64: five forms
-    of the A X kernel, the tall one among them, four of the A^T X kernel,
-    three tournament block heights) and reports a choice the launchers
-    support;
+    of the A X kernel, the tall one among them, five of the A^T X kernel,
+    the wide one among them, three tournament block heights) and reports a
+    choice the launchers support;
   * every configuration the autotuner can choose, forced through a loaded
     table, gives solves that match the FP64 oracle: singular values within
     1e-4 relative, orthonormal factors, spectral error no worse than the
@@ -60,9 +60,9 @@ def test_tune_reports_a_choice(ctx, case):
     _, dA, _, _ = case
     ctx.tune_clear()
     r = ctx.tune(dA, L, reps=2)
-    assert r["candidates"] == 5 + 4 + 3
+    assert r["candidates"] == 5 + 5 + 3
     assert (r["ax_waves"], r["ax_ring"]) in ((16, 0), (8, 4), (4, 2), (4, 3), (4, 4))
-    assert (r["atx_waves"], r["atx_ring"]) in ((8, 4), (4, 2), (4, 3), (4, 4))
+    assert (r["atx_waves"], r["atx_ring"]) in ((16, 0), (8, 4), (4, 2), (4, 3), (4, 4))
     assert r["lu_rows"] in (256, 512, 1024)
     assert r["ms_ax"] > 0 and r["ms_atx"] > 0 and r["ms_lu"] > 0
     assert ctx.tune_count() == 1
@@ -71,7 +71,7 @@ def test_tune_reports_a_choice(ctx, case):
 
 @pytest.mark.parametrize("cfg", [(8, 4, 8, 4, 512), (4, 2, 4, 3, 256), (4, 4, 4, 2, 1024),
                                  (4, 3, 8, 4, 256), (8, 4, 4, 4, 1024), (16, 0, 8, 4, 512),
-                                 (16, 0, 4, 2, 256)])
+                                 (16, 0, 4, 2, 256), (16, 0, 16, 0, 512), (4, 3, 16, 0, 256)])
 def test_forced_configuration_matches_oracle(ctx, case, tmp_path, cfg):
     path = tmp_path / "tune.txt"
     path.write_text("# forced\n%s %d %d %d %d %d\n" % ((_class(M, N, 64),) + cfg))
@@ -84,18 +84,18 @@ def test_forced_configuration_matches_oracle(ctx, case, tmp_path, cfg):
         ctx.tune_clear()
 
 
-@pytest.mark.parametrize("ax", ["8 3", "16 0"])
-def test_forced_8wave_lp128_matches_oracle(ctx, tmp_path, ax):
-    # l = 120 (lp = 128): the 8-wave forms of both passes (3-stage rings), or
-    # the tall A X with the 8-wave A^T X, forced for this shape class, against
-    # the oracle
+@pytest.mark.parametrize("cfg", ["8 3 8 3", "16 0 8 3", "16 0 16 0"])
+def test_forced_8wave_lp128_matches_oracle(ctx, tmp_path, cfg):
+    # l = 120 (lp = 128): the 8-wave forms of both passes (3-stage rings), the
+    # tall A X with the 8-wave A^T X, or the tall and the wide forms, forced
+    # for this shape class, against the oracle
     m, n, k, l = 20000, 1024, 100, 120
     sig = dense.spectrum_tall(n)
     A = dense.dense(m, n, sig, seed=778)
     U0, S0, V0 = rsvd.rsvd(A, k, l, ITS, philox.omega(SEED, n, l))
     err0 = spectral.spectral_err_exact(A, U0, S0, V0)
     path = tmp_path / "tune128.txt"
-    path.write_text("# forced\n%s %s 8 3 512\n" % (_class(m, n, 128), ax))
+    path.write_text("# forced\n%s %s 512\n" % (_class(m, n, 128), cfg))
     ctx.tune_clear()
     ctx.tune_load(str(path))
     try:
