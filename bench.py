@@ -83,9 +83,10 @@ def parse():
 
 
 # Kernel sources whose change invalidates stored counter readings.
-TRAFFIC_SOURCES = ("paper_1412_3510_amd/csrc/ax_tall.hip", "paper_1412_3510_amd/csrc/gemm.hip",
-                   "paper_1412_3510_amd/csrc/dma.h", "paper_1412_3510_amd/csrc/common.h")
-PASS_KERNELS = {"ax": "rpca::ax_tall_kernel", "atx": "rpca::atx_dma_kernel"}
+TRAFFIC_SOURCES = ("paper_1412_3510_amd/csrc/ax_tall.hip", "paper_1412_3510_amd/csrc/atx_wide.hip",
+                   "paper_1412_3510_amd/csrc/gemm.hip", "paper_1412_3510_amd/csrc/dma.h",
+                   "paper_1412_3510_amd/csrc/common.h")
+PASS_KERNELS = {"ax": "rpca::ax_tall_kernel", "atx": "rpca::atx_wide_kernel"}
 
 
 def _sources_digest():
@@ -707,7 +708,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": {"ax": "ax_tall_kernel (Y = A X)",
-                           "atx": "atx_dma_kernel (A^T X, split over rows)"}[dom],
+                           "atx": "atx_wide_kernel (A^T X, split over rows)"}[dom],
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes": bytes_per}
     passes = {q: {"avg_ms": round(v[0], 4), "GB/s": round(v[1] / (v[0] * 1e-3) / 1e9, 1)}
               for q, v in kernels.items()}

@@ -75,8 +75,8 @@ def _op(Al, sh, kind):
 
 @pytest.mark.parametrize("kind", ["bf16", "fp8"])
 # 70001 and 66000 rows: the tall form of A X (one tile of 274 or 258 rows per
-# workgroup).  40000 x 1040: 256-column tiles for A^T Q (bfloat16 at l = 60
-# and 120), the last one 16 columns wide
+# workgroup).  40000 x 1040: the wide form of A^T Q (two 512-column tiles and
+# a last one 16 columns wide)
 @pytest.mark.parametrize("m,n,l", [(1000, 512, 12), (777, 320, 60), (300, 1024, 120),
                                    (4099, 256, 64), (70001, 400, 60), (130, 48, 33),
                                    (66000, 208, 120), (40000, 1040, 60), (40000, 1040, 120)])
