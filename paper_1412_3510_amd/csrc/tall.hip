@@ -544,36 +544,44 @@ __global__ void __launch_bounds__(256) trsm_kernel(float* __restrict__ X, int64_
     *reinterpret_cast<float4*>(dst + c) = make_float4(x[c], x[c + 1], x[c + 2], x[c + 3]);
 }
 
-// The same solve, right-looking: the results are bitwise those of
-// trsm_kernel. once x_i is final, row i of U updates the entries to
-// its right, so each x_j still accumulates x_i U[i][j] in increasing i.  Row
-// i of U is the same for every lane: the compiler reads it with scalar loads
-// (U is never written here) and the products take it as a scalar operand,
-// with no LDS traffic per product.  The loads' latency is hidden only with
-// several waves per SIMD, so launch_trsm takes this form for large row
-// counts; with U in LDS instead (trsm_kernel), every product reads LDS,
-// whose bandwidth bounds the large cases.
+// The same solve, right-looking and blocked: once x_i is final, row i of U
+// updates the entries to its right, so each x_j still accumulates
+// x_i U[i][j] in increasing i and the results are bitwise those of
+// trsm_kernel.  Two choices make it the faster form for many rows:
+//  * independent updates: the products of a step go to different x_j, so
+//    they issue back to back (the left-looking form chains each x_j's sum);
+//  * U in LDS, read at one address by the whole wave (a broadcast: four
+//    entries per read, no bank conflicts), where scalar loads of U (64 KB
+//    at lp = 128, more than the scalar cache) wait on L2 for most rows.
+// The columns go in blocks of 16: the diagonal block is solved, stored, and
+// used to update the blocks to its right; then the register window shifts
+// one block down, so the loop over blocks stays rolled (about 27 KB of code
+// at lp = 128, against 94 KB fully unrolled).
 // ------------------------------------------------------------------------
-template <int LP>
-__global__ void __launch_bounds__(256) trsm_rows_kernel(float* __restrict__ X, int64_t ldx,
-                                                        int64_t rows, int l,
-                                                        const float* __restrict__ Ut,
-                                                        const int* __restrict__ piv,
-                                                        const int* __restrict__ skip_flag,
-                                                        const float* __restrict__ nu,
-                                                        const float* __restrict__ addX,
-                                                        int64_t ldadd) {
+template <int LP, int NT>
+__global__ void __launch_bounds__(NT) trsm_blocked_kernel(float* __restrict__ X, int64_t ldx,
+                                                          int64_t rows, int l,
+                                                          const float* __restrict__ Ut,
+                                                          const int* __restrict__ piv,
+                                                          const int* __restrict__ skip_flag,
+                                                          const float* __restrict__ nu,
+                                                          const float* __restrict__ addX,
+                                                          int64_t ldadd) {
   if (skip_flag && *skip_flag == 0) return;
+  constexpr int B = 16, NBK = LP / B;
+  static_assert(LP % B == 0, "whole blocks");
+  __shared__ __attribute__((aligned(16))) float sU[LP * LP];
   __shared__ float sd[LP];
   __shared__ int sp[LP];
-  if (threadIdx.x < LP) {
-    const int j = threadIdx.x;
+  for (int e = threadIdx.x * 4; e < LP * LP; e += NT * 4)
+    *reinterpret_cast<float4*>(sU + e) = *reinterpret_cast<const float4*>(Ut + e);
+  for (int j = threadIdx.x; j < LP; j += NT) {
     const float d = (j < l) ? Ut[j * LP + j] : 0.f;
     sd[j] = (d != 0.f) ? 1.0f / d : 0.f;
     sp[j] = (piv && j < l) ? piv[j] : -1;
   }
   __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (row >= rows) return;
   float x[LP];
   const float* src = X + row * ldx;
@@ -591,23 +599,45 @@ __global__ void __launch_bounds__(256) trsm_rows_kernel(float* __restrict__ X, i
       x[c] += s * v.x; x[c + 1] += s * v.y; x[c + 2] += s * v.z; x[c + 3] += s * v.w;
     }
   }
-#pragma unroll
-  for (int i = 0; i < LP; ++i) {
-    if (i < l) {
-      const float d = sd[i];
-      x[i] = (d != 0.f) ? x[i] * d : ((row == sp[i]) ? 1.f : 0.f);
-      // (columns at or beyond l are updated too, and zeroed when reached)
-      const float* ui = Ut + i * LP;
-#pragma unroll
-      for (int j = i + 1; j < LP; ++j) x[j] -= x[i] * ui[j];
-    } else {
-      x[i] = 0.f;
-    }
-  }
   float* dst = X + row * ldx;
+  // x[0 .. LP - 16 b) holds columns 16 b .. LP - 1 at the start of block b
+#pragma unroll 1
+  for (int b = 0; b < NBK; ++b) {
+    const int i0 = b * B;
 #pragma unroll
-  for (int c = 0; c < LP; c += 4)
-    *reinterpret_cast<float4*>(dst + c) = make_float4(x[c], x[c + 1], x[c + 2], x[c + 3]);
+    for (int i = 0; i < B; ++i) {
+      const int gi = i0 + i;
+      if (gi < l) {
+        const float d = sd[gi];
+        x[i] = (d != 0.f) ? x[i] * d : ((row == sp[gi]) ? 1.f : 0.f);
+        const float* ui = sU + gi * LP + i0;
+#pragma unroll
+        for (int j = i + 1; j < B; ++j) x[j] -= x[i] * ui[j];
+      } else {
+        x[i] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < B; c += 4)
+      *reinterpret_cast<float4*>(dst + i0 + c) = make_float4(x[c], x[c + 1], x[c + 2], x[c + 3]);
+    // blocks to the right (columns at or beyond l are updated too, and
+    // zeroed when reached; none is left once the block reaches l)
+    if (i0 + B < l) {
+#pragma unroll
+      for (int c = 1; c < NBK; ++c) {
+        if (c < NBK - b) {
+#pragma unroll
+          for (int i = 0; i < B; ++i) {
+            const float* ui = sU + (i0 + i) * LP + i0 + c * B;
+#pragma unroll
+            for (int j = 0; j < B; ++j) x[c * B + j] -= x[i] * ui[j];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < LP - B; ++t) x[t] = x[t + B];
+  }
 }
 
 void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int lp,
@@ -615,19 +645,22 @@ void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int
                  const float* addX, int64_t ldadd, int num_cus) {
   if (rows == 0) return;
   const dim3 grid((unsigned)ceil_div(rows, 256));
-  // lp = 128 with at least three waves per SIMD: U rows from scalar loads
-  const bool rows_form = lp == 128 && rows >= (int64_t)num_cus * 4 * 64 * 3;
+  // lp = 64 and 128 with a workgroup of rows per CU or more: the blocked form
+  const bool blocked = lp >= 64 && rows >= (int64_t)num_cus * 256;
+#define TRSM_GO(K_) hipLaunchKernelGGL(K_, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd)
   switch (lp) {
-    case 32: hipLaunchKernelGGL(trsm_kernel<32>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
-    case 64: hipLaunchKernelGGL(trsm_kernel<64>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd); break;
+    case 32: TRSM_GO(trsm_kernel<32>); break;
+    case 64:
+      if (blocked) TRSM_GO((trsm_blocked_kernel<64, 256>));
+      else TRSM_GO(trsm_kernel<64>);
+      break;
     case 128:
-      if (rows_form)
-        hipLaunchKernelGGL(trsm_rows_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd);
-      else
-        hipLaunchKernelGGL(trsm_kernel<128>, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd);
+      if (blocked) TRSM_GO((trsm_blocked_kernel<128, 256>));
+      else TRSM_GO(trsm_kernel<128>);
       break;
     default: break;
   }
+#undef TRSM_GO
 }
 
 // ------------------------------------------------------------------------
