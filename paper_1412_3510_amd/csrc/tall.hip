@@ -573,8 +573,22 @@ __global__ void __launch_bounds__(NT) trsm_blocked_kernel(float* __restrict__ X,
   __shared__ __attribute__((aligned(16))) float sU[LP * LP];
   __shared__ float sd[LP];
   __shared__ int sp[LP];
-  for (int e = threadIdx.x * 4; e < LP * LP; e += NT * 4)
-    *reinterpret_cast<float4*>(sU + e) = *reinterpret_cast<const float4*>(Ut + e);
+  {
+    // up to 16 loads in flight per thread before their stores (a plain
+    // copy loop waits out the memory latency once per 16 bytes)
+    constexpr int PER = LP * LP / (4 * NT), GR = PER < 16 ? PER : 16;
+    static_assert(PER * 4 * NT == LP * LP && PER % GR == 0, "U fill shape");
+    const float4* u4 = reinterpret_cast<const float4*>(Ut);
+    float4* s4 = reinterpret_cast<float4*>(sU);
+#pragma unroll
+    for (int g0 = 0; g0 < PER; g0 += GR) {
+      float4 t[GR];
+#pragma unroll
+      for (int u = 0; u < GR; ++u) t[u] = u4[(g0 + u) * NT + threadIdx.x];
+#pragma unroll
+      for (int u = 0; u < GR; ++u) s4[(g0 + u) * NT + threadIdx.x] = t[u];
+    }
+  }
   for (int j = threadIdx.x; j < LP; j += NT) {
     const float d = (j < l) ? Ut[j * LP + j] : 0.f;
     sd[j] = (d != 0.f) ? 1.0f / d : 0.f;
@@ -645,7 +659,9 @@ void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int
                  const float* addX, int64_t ldadd, int num_cus) {
   if (rows == 0) return;
   const dim3 grid((unsigned)ceil_div(rows, 256));
-  // lp = 64 and 128 with a workgroup of rows per CU or more: the blocked form
+  // lp = 64 with a workgroup of rows per CU or more, and lp = 128: the
+  // blocked form (lp = 128 on fewer rows in workgroups of 64 threads, which
+  // spreads them over more CUs)
   const bool blocked = lp >= 64 && rows >= (int64_t)num_cus * 256;
 #define TRSM_GO(K_) hipLaunchKernelGGL(K_, grid, dim3(256), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd)
   switch (lp) {
@@ -655,8 +671,11 @@ void launch_trsm(hipStream_t st, float* X, int64_t ldx, int64_t rows, int l, int
       else TRSM_GO(trsm_kernel<64>);
       break;
     case 128:
-      if (blocked) TRSM_GO((trsm_blocked_kernel<128, 256>));
-      else TRSM_GO(trsm_kernel<128>);
+      if (blocked)
+        TRSM_GO((trsm_blocked_kernel<128, 256>));
+      else
+        hipLaunchKernelGGL((trsm_blocked_kernel<128, 64>), dim3((unsigned)ceil_div(rows, 64)),
+                           dim3(64), 0, st, X, ldx, rows, l, Ut, piv, skip_flag, nu, addX, ldadd);
       break;
     default: break;
   }

@@ -29,8 +29,13 @@ def _dev(a):
 
 
 # ---------------------------------------------------------------- Philox
+# the device kernel writes tiles of 8 to 256 rows and up to 128 columns:
+# 1001, 20001 and 300001 rows end on a ragged tile (blocks of four variates
+# straddle columns where n % 4 != 0), 131 and 200 columns take two column
+# tiles, 300001 rows take 256-row tiles
 @pytest.mark.parametrize("n,l,seed,stream", [(500, 12, 2001, 0), (1001, 7, 2**40 + 3, 1),
-                                             (33, 5, 0, 0)])
+                                             (33, 5, 0, 0), (301, 131, 77, 2), (9, 200, 3, 1),
+                                             (20001, 33, 5, 0), (300001, 4, 11, 0)])
 def test_gaussian_matches_oracle(ctx, n, l, seed, stream):
     om, w = ctx.gaussian(seed, n, l, stream=stream, words=True)
     torch.cuda.synchronize()

@@ -31,7 +31,8 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("n,l,seed", [(1, 1, 0), (7, 3, 5), (1000, 12, 2 ** 40 + 3), (333, 64, 9)])
+@pytest.mark.parametrize("n,l,seed", [(1, 1, 0), (7, 3, 5), (1000, 12, 2 ** 40 + 3), (333, 64, 9),
+                                      (301, 131, 4)])
 def test_uniform_omega_bit_exact(ctx, n, l, seed):
     got = ctx.uniform(seed, n, l).cpu().numpy()
     np.testing.assert_array_equal(got, philox.omega_uniform(seed, n, l))
